@@ -1,0 +1,168 @@
+/*
+ * poredvm: iterative discrete-velocity solve of the steady linearised BGK
+ * equation on a voxelised porous geometry, on one AMD Instinct MI355X (gfx950).
+ *
+ * Reference: Ho, Zhu, Wu, Wang, Guo, Li, Zhang, "A multi-level parallel solver
+ * for rarefied gas flows in porous media", arXiv:1712.01132.
+ *   model and boundary conditions ......... Sec. 2.1, Eqs. linearised_Boltzmann_equation,
+ *                                           diffusive-specular_BC (alpha = 1), wall_density,
+ *                                           periodic_BC, symmetric_BC
+ *   velocity grid ......................... Sec. 2.2 (half-range Gauss-Hermite, Cartesian)
+ *   upwind stencil ........................ Sec. 2.3, Eq. numerical stencil
+ *   iteration (sweep, BC, moments) ........ Sec. 3.1 steps (i)-(iii), Algorithm 1
+ *   permeability and convergence .......... Eq. k_Gp, Sec. 3.1 steps (iv)-(v),
+ *                                           Eq. convergence_criterion
+ *
+ * Conventions shared by every entry point:
+ *  - Geometry: a voxel image of n[0] x n[1] (x n[2]) cubic voxels, index
+ *    i + n0 * (j + n1 * l), x1 = the flow axis = the fastest index. Nodes sit at
+ *    voxel centres; lengths are scaled by L = n[0] voxels (so dx = 1/n0) and
+ *    Kn is referenced to that L.
+ *  - The flow is driven by the periodic pressure jump along x1: molecules
+ *    entering at the inlet carry h(outlet) + jump (Eq. periodic_BC); the
+ *    paper's value is jump = 1. Lateral faces are specular (Eq. symmetric_BC,
+ *    mirror plane = the outer voxel face) or, optionally, periodic.
+ *  - The velocity grid is the tensor product of per-axis 1D lists that are
+ *    symmetric about 0, even-sized and free of 0, with normalised weights
+ *    (sum 1 per axis; they absorb exp(-v^2)/sqrt(pi)). In 2D the distribution
+ *    is the reduced one with v3 integrated out.
+ *  - Status codes are returned, never thrown; a message is kept per handle and
+ *    per thread (pdvm_last_error).
+ *  - All device work is enqueued on the stream given at creation; calls that
+ *    return host data synchronise that stream first.
+ *  - A handle may be used by one host thread at a time.
+ */
+#ifndef POREDVM_H
+#define POREDVM_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum {
+  PDVM_OK = 0,
+  PDVM_NOT_CONVERGED = 1,   /* iteration budget used up; state valid and resumable */
+  PDVM_E_INVAL = -1,        /* invalid argument or configuration */
+  PDVM_E_NOMEM = -2,        /* allocation failed or workspace too small */
+  PDVM_E_HIP = -3,          /* a HIP runtime call failed */
+  PDVM_E_NONFINITE = -4,    /* r or k became NaN/Inf; the last good state is kept */
+  PDVM_E_STATE = -5,        /* checkpoint buffer of the wrong size or problem */
+  PDVM_E_UNSUPPORTED = -6   /* valid but not implemented (e.g. tau feedback in 2D) */
+};
+
+enum { PDVM_FP64 = 0, PDVM_FP32 = 1 };                       /* sweep + h storage precision */
+enum { PDVM_LATERAL_SPECULAR = 0, PDVM_LATERAL_PERIODIC = 1 };
+enum { PDVM_STOP_FIELD = 0, PDVM_STOP_PAPER_ERR = 1 };
+
+typedef struct pdvm_solver pdvm_solver;
+
+typedef struct {
+  int32_t dim;               /* 2 or 3 */
+  int32_t n[3];              /* voxels per axis; n[2] ignored (1) in 2D; each >= 2 */
+  const uint8_t *solid;      /* host, n0*n1(*n2) bytes, nonzero = solid; copied at create */
+  int32_t nv[3];             /* 1D velocity counts per axis (even, >= 2) */
+  const double *vnode[3];    /* host, ascending 1D nodes per axis; copied */
+  const double *vweight[3];  /* host, 1D weights per axis, > 0, sum 1; copied */
+  double kn;                 /* Knudsen number (> 0; +INFINITY = free molecular) */
+  double jump;               /* pressure jump added at the x1 wrap (paper: 1.0) */
+  int32_t precision;         /* PDVM_FP64 or PDVM_FP32 (moments and reductions stay FP64) */
+  int32_t lateral_bc;        /* PDVM_LATERAL_SPECULAR (paper) or PDVM_LATERAL_PERIODIC */
+  int32_t tau_feedback;      /* 0 = isothermal source as in the paper's runs; 1 = feed the
+                                temperature term back (3D only, else PDVM_E_UNSUPPORTED) */
+  int32_t check_every;       /* host polls convergence every this many iterations (0 = 16) */
+  int32_t tile[3];           /* sweep tile edge per axis in voxels (0 = library default;
+                                the x1 edge is capped at 32) */
+  int32_t stencil_rule;      /* when the upwind stencil along an axis drops to first order
+                                (Sec. 2.3 says: when the upstream point is a boundary point):
+                                1 = when either of the two upstream images is solid;
+                                0 = only when the first one is (a solid second image then
+                                    enters the second-order stencil with its wall value;
+                                    this iteration can diverge on some geometries) */
+} pdvm_config;
+
+typedef struct {
+  int64_t iters;             /* iterations completed in this call */
+  int64_t total_iters;       /* iterations since the last initial state */
+  double r;                  /* field residual max|u^l - u^(l-1)| / max|u^l| (FP64) */
+  double err;                /* paper criterion Err(l) at the last multiple of 100, -1 if none */
+  double k;                  /* apparent permeability (2/sqrt(pi)) Kn G_p */
+  double gp;                 /* G_p = mean of u1 over all cells (solid = 0) */
+  double seconds;            /* wall time of the call */
+  int32_t converged;         /* 1 if stopped on the tolerance */
+} pdvm_stats;
+
+/* Half-range Gauss-Hermite velocity grid (Sec. 2.2): n_total/2 nodes of the
+ * Gauss rule for exp(-x^2) on [0, inf), mirrored to both signs; weights
+ * normalised to sum 1. nodes/weights: host arrays of n_total doubles (caller
+ * owned). n_total even, 2..256. Returns PDVM_OK or PDVM_E_INVAL. */
+int pdvm_halfrange_gh(int32_t n_total, double *nodes, double *weights);
+
+/* Device bytes the solver needs for cfg (0 if cfg is invalid). */
+size_t pdvm_workspace_bytes(const pdvm_config *cfg);
+
+/* Validate cfg, preprocess the geometry (per-voxel stencil-order flags,
+ * percolation check along x1) and upload it (Sec. 2.3, pre-processing of the
+ * (C0, C1, C2) choice). dev_workspace: NULL (the library allocates and frees)
+ * or a device buffer of at least pdvm_workspace_bytes(cfg) bytes, owned by the
+ * caller, that must outlive the solver. hip_stream: a hipStream_t or NULL (the
+ * null stream). The initial state is rest (all perturbations zero).
+ * PDVM_E_INVAL if no pore component winds around x1. */
+int pdvm_create(const pdvm_config *cfg, void *dev_workspace, size_t ws_bytes,
+                void *hip_stream, pdvm_solver **out);
+
+/* Initial state: the local linearised equilibrium h = rho + 2 u.v of the
+ * given host fields (rho: N doubles, u: dim*N doubles component-major; NULL =
+ * zero). Resets the iteration counter. */
+int pdvm_set_initial(pdvm_solver *s, const double *rho, const double *u);
+
+/* Run up to max_iters iterations (Algorithm 1). stop_mode PDVM_STOP_FIELD:
+ * stop when r <= tol; PDVM_STOP_PAPER_ERR: stop when Err(l) < tol at a
+ * multiple of 100 iterations (Eq. convergence_criterion). tol <= 0 runs all
+ * max_iters. Returns PDVM_OK (converged), PDVM_NOT_CONVERGED, or an error. */
+int pdvm_iterate(pdvm_solver *s, int64_t max_iters, double tol, int32_t stop_mode,
+                 pdvm_stats *out);
+
+/* Macroscopic fields of the current state (Eq. perturbed_quantities), host
+ * arrays of N (rho, tau) or dim*N (u, q) doubles, solid voxels read 0; NULL
+ * skips. tau and q are diagnostics (2D: reduced forms with v3 integrated
+ * out); they are computed from the stored distribution on demand. */
+int pdvm_get_moments(pdvm_solver *s, double *rho, double *u, double *tau, double *q);
+
+/* G_p, k = (2/sqrt(pi)) Kn G_p (Eq. k_Gp), and optionally the per-section
+ * G_p(i) (n[0] doubles, mean of u1 over the cross-section at x1 index i). */
+int pdvm_get_flux(pdvm_solver *s, double *gp, double *k, double *gp_section);
+
+/* Checkpoint: everything the next iteration reads (moments, wall data, the
+ * boundary layers of the distribution, counters). With buf == NULL, *bytes
+ * receives the size. Restoring into a solver created with the same config
+ * continues bitwise identically. PDVM_E_STATE on a size or problem mismatch. */
+int pdvm_get_state(pdvm_solver *s, void *buf, size_t *bytes);
+int pdvm_set_state(pdvm_solver *s, const void *buf, size_t bytes);
+
+/* Per-kernel timing over `iters` iterations on the solver's stream with HIP
+ * events: average milliseconds per launch of the sweep kernel, of the moment
+ * kernel and of the reduction kernel, and the number of sweep launches per
+ * iteration; also the algorithmic bytes per iteration of the sweep (h written
+ * once per fluid voxel and velocity) and of the moment kernel (h read once).
+ * Runs real iterations (the state advances). */
+typedef struct {
+  double sweep_ms_per_launch, moments_ms_per_launch, reduce_ms_per_launch;
+  double sweep_ms_per_iter, moments_ms_per_iter, iter_ms;
+  int32_t sweep_launches_per_iter;
+  double sweep_bytes_per_iter, moments_bytes_per_iter;
+  double fluid_cells, velocities;
+} pdvm_timing;
+int pdvm_time_kernels(pdvm_solver *s, int32_t iters, pdvm_timing *out);
+
+void pdvm_destroy(pdvm_solver *s);
+
+/* Last error message of the handle, or of the calling thread if s is NULL. */
+const char *pdvm_last_error(const pdvm_solver *s);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* POREDVM_H */

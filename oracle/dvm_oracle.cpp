@@ -29,7 +29,8 @@
 // Readings taken where the paper is silent (each listed in the design notes):
 //   voxel-centred nodes x_a = (i_a + 1/2)/N1, period N1 along x1, jump J = 1;
 //   the specular plane is the outer voxel face (mirror node -c-1 / 2N-1-c);
-//   first order only when the immediate upstream image is solid;
+//   first order when the immediate upstream image is solid (stencil_rule 0) or
+//   when either upstream image is solid (stencil_rule 1);
 //   wall density of the solid met by a stencil along axis j with upwind sign s
 //   is taken from the fluid node next to it in the +s direction, with the
 //   quadrature sum D_j = sum_{v_j>0} W v_j as denominator;
@@ -65,6 +66,10 @@ struct Oracle {
   double D[3] = {0, 0, 0};   // D_j = sum_{v_j > 0} W v_j
   double kn = 1.0, nu = 0.0, J = 1.0;
   int lateral_periodic = 0, tau_fb = 0, nthreads = 1;
+  // 0: first order iff the first upstream image is solid (a solid second
+  //    upstream image enters the second-order stencil with its wall value);
+  // 1: first order iff either upstream image is solid.
+  int stencil_rule = 1;
 
   // lagged state (per cell; solid entries stay 0)
   std::vector<double> rho, tau;
@@ -179,11 +184,12 @@ void sweep_velocity(const Oracle &o, int k, double *hk) {
           const double a = std::fabs(o.v[j][k]) * inv_dx;
           int s1 = 0, s2 = 0;
           const double y1 = upstream_value(o, x, j, 1, k, hk, &s1);
-          if (s1) {            // first order: C = (1, -1, 0)/dx
+          double y2 = 0.0;
+          if (!s1) y2 = upstream_value(o, x, j, 2, k, hk, &s2);
+          if (s1 || (o.stencil_rule == 1 && s2)) {  // first order: C = (1, -1, 0)/dx
             den += a;
             num += a * y1;
-          } else {             // second order: C = (1.5, -2, 0.5)/dx
-            const double y2 = upstream_value(o, x, j, 2, k, hk, &s2);
+          } else {                                   // second order: C = (1.5, -2, 0.5)/dx
             den += 1.5 * a;
             num += a * (2.0 * y1 - 0.5 * y2);
           }
@@ -213,8 +219,9 @@ extern "C" {
 void *orc_create(int dim, const int *n, const uint8_t *solid, const int *nv,
                  const double *nodes, const double *weights, double kn,
                  double jump, int lateral_periodic, int tau_feedback,
-                 int nthreads) {
+                 int nthreads, int stencil_rule) {
   Oracle *o = new Oracle();
+  o->stencil_rule = stencil_rule;
   o->dim = dim;
   for (int a = 0; a < 3; ++a) { o->n[a] = a < dim ? n[a] : 1; o->nv[a] = a < dim ? nv[a] : 1; }
   o->N = (long)o->n[0] * o->n[1] * o->n[2];
@@ -479,11 +486,10 @@ void orc_apply_advection(void *hh, int k, const double *f, double *out) {
       const double a = std::fabs(o.v[j][k]) * inv_dx;
       int s1 = 0, s2 = 0;
       const double y1 = upstream_value(o, x, j, 1, k, f, &s1);
-      if (s1) acc += a * (f[c] - y1);
-      else {
-        const double y2 = upstream_value(o, x, j, 2, k, f, &s2);
-        acc += a * (1.5 * f[c] - 2.0 * y1 + 0.5 * y2);
-      }
+      double y2 = 0.0;
+      if (!s1) y2 = upstream_value(o, x, j, 2, k, f, &s2);
+      if (s1 || (o.stencil_rule == 1 && s2)) acc += a * (f[c] - y1);
+      else acc += a * (1.5 * f[c] - 2.0 * y1 + 0.5 * y2);
     }
     out[c] = acc;
   }

@@ -13,7 +13,7 @@ Boltzmann_equations; boundary values from Sec. 2.1):
 
 with a_j = |v_jk|/dx, (c1, c2) = (2, -1/2) and den = nu + sum 1.5 a_j for the
 second-order stencil, (c1) = (1) and a_j in place of 1.5 a_j for the first-order
-one (used when the first upstream image is solid). Y are upstream values:
+one (used when an upstream image is solid, see `stencil_rule`). Y are upstream values:
 the unknown h at a fluid node inside the domain; h at the periodic / mirror
 image plus the pressure jump at a ghost node; the wall density
 Phi_j^-s(x_f)/D_j (+ jump) at a solid node, with Phi_j^+-(x) =
@@ -61,10 +61,13 @@ def _velocity_table(grid, dim):
     return v[:dim], W, mirror[:dim]
 
 
-def solve_fixed_point(solid, nv, kn, jump=1.0, lateral_periodic=False, grid=None):
+def solve_fixed_point(solid, nv, kn, jump=1.0, lateral_periodic=False, grid=None, stencil_rule=1):
     """Return dict with rho (gauge mean 0 over fluid), u (dim, ...), delta, h.
 
-    solid: (N2, N1) or (N3, N2, N1) uint8 mask, 1 = solid."""
+    solid: (N2, N1) or (N3, N2, N1) uint8 mask, 1 = solid. stencil_rule 1: the
+    first-order stencil is used when either upstream image is solid; 0: only
+    when the first one is (a solid second image then enters the second-order
+    stencil with its wall value)."""
     solid = np.asarray(solid, np.uint8)
     dim = solid.ndim
     shape = solid.shape
@@ -154,13 +157,21 @@ def solve_fixed_point(solid, nv, kn, jump=1.0, lateral_periodic=False, grid=None
                     b[r] += weight * jm * jump
                     return False, not ghost
 
-                # first upstream image decides the order
+                # the upstream images decide the order
                 y = list(x)
                 y[j] -= s
                 yr, _, _, _ = resolve(y, j)
-                if flat[cell(yr)]:
+                y1_solid = bool(flat[cell(yr)])
+                y2_solid = False
+                if not y1_solid:
+                    y = list(x)
+                    y[j] -= 2 * s
+                    yr, _, _, _ = resolve(y, j)
+                    y2_solid = bool(flat[cell(yr)])
+                if y1_solid or (stencil_rule == 1 and y2_solid):
                     den += a
-                    upstream(1, a)
+                    _, c1cur = upstream(1, a)
+                    cur += a if c1cur else 0.0
                 else:
                     den += 1.5 * a
                     _, c1cur = upstream(1, 2.0 * a)

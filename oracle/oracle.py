@@ -38,7 +38,7 @@ def _load():
         lib.orc_create.restype = vp
         lib.orc_create.argtypes = [ctypes.c_int, ip, ctypes.POINTER(ctypes.c_uint8), ip, dp, dp,
                                    ctypes.c_double, ctypes.c_double, ctypes.c_int, ctypes.c_int,
-                                   ctypes.c_int]
+                                   ctypes.c_int, ctypes.c_int]
         lib.orc_destroy.argtypes = [vp]
         lib.orc_num_velocities.argtypes = [vp]
         lib.orc_set_initial.argtypes = [vp, dp, dp, dp]
@@ -67,10 +67,12 @@ class OracleSolver:
 
     If `grid` is None the half-range Gauss-Hermite grid of the oracle's own
     quadrature module is used; otherwise grid = [(nodes, weights), ...] per axis.
+    stencil_rule 1 (default): first-order upwind stencil along an axis when
+    either upstream image is solid; 0: only when the first one is.
     """
 
     def __init__(self, solid, nv, kn, jump=1.0, lateral_periodic=False,
-                 tau_feedback=False, threads=None, grid=None):
+                 tau_feedback=False, threads=None, grid=None, stencil_rule=1):
         lib = _load()
         solid = np.ascontiguousarray(solid, dtype=np.uint8)
         self.dim = solid.ndim
@@ -96,7 +98,7 @@ class OracleSolver:
                                  solid.ctypes.data_as(ctypes.POINTER(ctypes.c_uint8)),
                                  nv_arr, _dp(nodes), _dp(weights), self.kn, float(jump),
                                  int(bool(lateral_periodic)), int(bool(tau_feedback)),
-                                 self.threads)
+                                 self.threads, int(stencil_rule))
         self._keep = (nodes, weights)
         self.K = lib.orc_num_velocities(self._h)
 

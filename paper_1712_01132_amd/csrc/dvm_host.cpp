@@ -1,0 +1,1004 @@
+// Host side of libporedvm: the C ABI of include/poredvm.h.
+//
+//  * validation and one-time preprocessing of the voxel image (per-voxel
+//    stencil-order flags, percolation along x1) -- the paper's pre-processing
+//    of the stencil coefficients (Sec. 2.3);
+//  * the half-range Gauss-Hermite velocity grid (Sec. 2.2);
+//  * device layout, upload and the iteration driver (Sec. 3.1, Algorithm 1):
+//    one iteration = the sweep over all tile diagonals, the moment kernel and
+//    the FP64 reduction, captured once as a HIP graph and replayed; the host
+//    polls a 16-byte status every few iterations.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <limits>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "../../include/poredvm.h"
+#include "dvm_internal.h"
+
+using namespace pdvm;
+
+namespace {
+
+thread_local std::string g_thread_error;
+
+void set_thread_error(const char *fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof(buf), fmt, ap);
+  va_end(ap);
+  g_thread_error = buf;
+}
+
+// ---------------------------------------------------------------------------
+// Half-range Gauss-Hermite rule in extended precision: the recurrence of the
+// orthogonal polynomials for exp(-x^2) on [0, inf) by the discretised
+// Stieltjes procedure (composite Gauss-Legendre on [0, 14]), then nodes and
+// weights from the Jacobi matrix by implicit QL iterations.
+
+void gauss_legendre(int m, std::vector<long double> &x, std::vector<long double> &w) {
+  x.assign(m, 0);
+  w.assign(m, 0);
+  const long double pi = 3.141592653589793238462643383279502884L;
+  for (int i = 0; i < m; ++i) {
+    long double z = cosl(pi * (i + 0.75L) / (m + 0.5L));
+    long double dp = 0;
+    for (int it = 0; it < 100; ++it) {
+      long double p0 = 1, p1 = z;
+      for (int k = 2; k <= m; ++k) {
+        const long double p2 = ((2 * k - 1) * z * p1 - (k - 1) * p0) / k;
+        p0 = p1;
+        p1 = p2;
+      }
+      dp = m * (z * p1 - p0) / (z * z - 1);
+      const long double dz = p1 / dp;
+      z -= dz;
+      if (fabsl(dz) < 1e-19L) break;
+    }
+    x[i] = z;
+    w[i] = 2 / ((1 - z * z) * dp * dp);
+  }
+}
+
+bool jacobi_eigen(std::vector<long double> &d, std::vector<long double> &e, std::vector<long double> &z) {
+  const int n = (int)d.size();
+  for (int l = 0; l < n; ++l) {
+    int iter = 0;
+    int m;
+    do {
+      for (m = l; m < n - 1; ++m) {
+        const long double dd = fabsl(d[m]) + fabsl(d[m + 1]);
+        if (fabsl(e[m]) <= 1e-21L * dd) break;
+      }
+      if (m != l) {
+        if (++iter > 200) return false;
+        long double g = (d[l + 1] - d[l]) / (2 * e[l]);
+        long double r = hypotl(g, 1.0L);
+        g = d[m] - d[l] + e[l] / (g + (g >= 0 ? r : -r));
+        long double s = 1, c = 1, p = 0;
+        int i;
+        bool early = false;
+        for (i = m - 1; i >= l; --i) {
+          long double f = s * e[i];
+          const long double b = c * e[i];
+          r = hypotl(f, g);
+          e[i + 1] = r;
+          if (r == 0) {
+            d[i + 1] -= p;
+            e[m] = 0;
+            early = true;
+            break;
+          }
+          s = f / r;
+          c = g / r;
+          g = d[i + 1] - p;
+          r = (d[i] - g) * s + 2 * c * b;
+          p = s * r;
+          d[i + 1] = g + p;
+          g = c * r - b;
+          f = z[i + 1];
+          z[i + 1] = s * z[i] + c * f;
+          z[i] = c * z[i] - s * f;
+        }
+        if (early) continue;
+        d[l] -= p;
+        e[l] = g;
+        e[m] = 0;
+      }
+    } while (m != l);
+  }
+  return true;
+}
+
+// ---------------------------------------------------------------------------
+// Percolation along x1: union-find over fluid voxels with the period offset of
+// each voxel relative to its root; a component winds around x1 when an edge
+// closes a cycle whose offsets disagree.
+
+struct PeriodicUF {
+  std::vector<int64_t> parent;
+  std::vector<int32_t> off;
+  std::vector<uint8_t> winds;
+  explicit PeriodicUF(int64_t n) : parent(n), off(n, 0), winds(n, 0) {
+    for (int64_t i = 0; i < n; ++i) parent[i] = i;
+  }
+  int64_t find(int64_t a, int32_t &oa) {
+    int32_t acc = 0;
+    int64_t r = a;
+    while (parent[r] != r) {
+      acc += off[r];
+      r = parent[r];
+    }
+    // path compression with offsets
+    int32_t rem = acc;
+    int64_t c = a;
+    while (parent[c] != c) {
+      const int64_t nxt = parent[c];
+      const int32_t o = off[c];
+      parent[c] = r;
+      off[c] = rem;
+      rem -= o;
+      c = nxt;
+    }
+    oa = acc;
+    return r;
+  }
+  // b's lifted position = a's + d periods
+  void unite(int64_t a, int64_t b, int32_t d) {
+    int32_t oa, ob;
+    const int64_t ra = find(a, oa), rb = find(b, ob);
+    if (ra != rb) {
+      parent[rb] = ra;
+      off[rb] = oa + d - ob;
+      winds[ra] |= winds[rb];
+    } else if (ob != oa + d) {
+      winds[ra] = 1;
+    }
+  }
+};
+
+// ---------------------------------------------------------------------------
+
+size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
+
+template <typename T>
+struct Layout {
+  size_t ctl, flags, absv, av, vsqm, rden, wq, h[2], src[2], srct[2], wall[2], rho[2], u[2], part, tiles, offs, scratch, total;
+};
+
+struct Problem {
+  int dim = 2;
+  int n[3] = {1, 1, 1};
+  int64_t N = 0, fluid = 0;
+  int hv[3] = {1, 1, 1};      // positive half-node counts
+  int Ko = 0, Ko_pad = 0, Kpad = 0, ngroups = 0;
+  int tile[3] = {1, 1, 1}, ntile[3] = {1, 1, 1};
+  int ndiag = 0;
+  int mom_blocks = 0;
+  double nu = 0, kn = 0, jump = 1, D[3] = {0, 0, 0};
+  int lateral_periodic = 0, tau_fb = 0, precision = 0, check_every = 16, stencil_rule = 1;
+  std::vector<uint32_t> flags;
+  std::vector<double> absv, wq, vsqm, rden;   // host FP64 tables, [rows][Ko_pad]
+  std::vector<int32_t> diag_tiles, diag_off;
+  uint64_t fingerprint = 0;  // hash of everything that defines the problem
+};
+
+uint64_t fnv1a(uint64_t h, const void *data, size_t n) {
+  const unsigned char *p = (const unsigned char *)data;
+  for (size_t i = 0; i < n; ++i) {
+    h ^= p[i];
+    h *= 1099511628211ull;
+  }
+  return h;
+}
+
+int validate_and_build(const pdvm_config *cfg, Problem &P, std::string &err) {
+  if (!cfg) { err = "config is NULL"; return PDVM_E_INVAL; }
+  if (cfg->dim != 2 && cfg->dim != 3) { err = "dim must be 2 or 3"; return PDVM_E_INVAL; }
+  P.dim = cfg->dim;
+  for (int a = 0; a < 3; ++a) {
+    P.n[a] = a < P.dim ? cfg->n[a] : 1;
+    if (a < P.dim && (P.n[a] < 2 || P.n[a] > (1 << 20))) { err = "each n[a] must be in [2, 2^20]"; return PDVM_E_INVAL; }
+  }
+  P.N = (int64_t)P.n[0] * P.n[1] * P.n[2];
+  if (P.N * 6 >= ((int64_t)1 << 31)) { err = "at most 2^31/6 voxels per problem"; return PDVM_E_INVAL; }
+  if (!cfg->solid) { err = "solid mask is NULL"; return PDVM_E_INVAL; }
+  if (!(cfg->kn > 0)) { err = "kn must be > 0 (or +inf)"; return PDVM_E_INVAL; }
+  if (!std::isfinite(cfg->jump)) { err = "jump must be finite"; return PDVM_E_INVAL; }
+  if (cfg->precision != PDVM_FP64 && cfg->precision != PDVM_FP32) { err = "precision must be FP64 or FP32"; return PDVM_E_INVAL; }
+  if (cfg->lateral_bc != PDVM_LATERAL_SPECULAR && cfg->lateral_bc != PDVM_LATERAL_PERIODIC) { err = "bad lateral_bc"; return PDVM_E_INVAL; }
+  if (cfg->tau_feedback && P.dim != 3) { err = "tau feedback needs the second reduced distribution in 2D"; return PDVM_E_UNSUPPORTED; }
+  P.kn = cfg->kn;
+  P.nu = std::isinf(cfg->kn) ? 0.0 : std::sqrt(M_PI) / (2.0 * cfg->kn);
+  P.jump = cfg->jump;
+  P.precision = cfg->precision;
+  P.lateral_periodic = cfg->lateral_bc == PDVM_LATERAL_PERIODIC;
+  P.tau_fb = cfg->tau_feedback ? 1 : 0;
+  P.check_every = cfg->check_every > 0 ? cfg->check_every : 16;
+  if (cfg->stencil_rule != 0 && cfg->stencil_rule != 1) { err = "stencil_rule must be 0 or 1"; return PDVM_E_INVAL; }
+  P.stencil_rule = cfg->stencil_rule;
+
+  // velocity grid: per axis, symmetric, even, no zero node, weights > 0, sum 1
+  std::vector<double> xp[3], wp[3];
+  for (int a = 0; a < 3; ++a) {
+    if (a >= P.dim) { xp[a] = {0.0}; wp[a] = {1.0}; P.hv[a] = 1; continue; }
+    const int m = cfg->nv[a];
+    if (m < 2 || m % 2 || m > 512) { err = "nv[a] must be even in [2, 512]"; return PDVM_E_INVAL; }
+    if (!cfg->vnode[a] || !cfg->vweight[a]) { err = "velocity node/weight array is NULL"; return PDVM_E_INVAL; }
+    const double *x = cfg->vnode[a], *w = cfg->vweight[a];
+    double sw = 0;
+    for (int i = 0; i < m; ++i) {
+      if (!(w[i] > 0) || !std::isfinite(x[i])) { err = "weights must be > 0 and nodes finite"; return PDVM_E_INVAL; }
+      if (i > 0 && !(x[i] > x[i - 1])) { err = "nodes must be strictly ascending"; return PDVM_E_INVAL; }
+      sw += w[i];
+    }
+    if (std::fabs(sw - 1.0) > 1e-12) { err = "weights of each axis must sum to 1"; return PDVM_E_INVAL; }
+    for (int i = 0; i < m / 2; ++i) {
+      const double xl = x[i], xr = x[m - 1 - i];
+      if (std::fabs(xl + xr) > 1e-13 * std::max(1.0, std::fabs(xr)) ||
+          std::fabs(w[i] - w[m - 1 - i]) > 1e-13 * w[i]) {
+        err = "velocity grid must be symmetric about 0";
+        return PDVM_E_INVAL;
+      }
+    }
+    if (!(x[m / 2] > 0)) { err = "velocity grid must not contain 0"; return PDVM_E_INVAL; }
+    P.hv[a] = m / 2;
+    for (int i = 0; i < m / 2; ++i) { xp[a].push_back(x[m / 2 + i]); wp[a].push_back(w[m / 2 + i]); }
+  }
+  P.Ko = P.hv[0] * P.hv[1] * P.hv[2];
+  if (P.Ko > 16 * kWave) { err = "at most 1024 velocities per sign octant"; return PDVM_E_INVAL; }
+  const int elem = P.precision == PDVM_FP64 ? 8 : 4;
+  const int line = 128 / elem;
+  P.Ko_pad = (P.Ko + line - 1) / line * line;
+  P.Kpad = P.Ko_pad << P.dim;
+  P.ngroups = (P.Ko + kWave - 1) / kWave;
+
+  // per-slot tables of one octant (slot q <-> positive node indices p_j)
+  const double dx_inv = (double)P.n[0];
+  P.absv.assign(3 * (size_t)P.Ko_pad, 0.0);
+  P.wq.assign(5 * (size_t)P.Ko_pad, 0.0);
+  P.vsqm.assign(P.Ko_pad, 0.0);
+  P.rden.assign(8 * (size_t)P.Ko_pad, 0.0);
+  for (int q = 0; q < P.Ko; ++q) {
+    const int p[3] = {q % P.hv[0], (q / P.hv[0]) % P.hv[1], q / (P.hv[0] * P.hv[1])};
+    double W = 1, vsq = 0;
+    for (int j = 0; j < 3; ++j) {
+      W *= wp[j][p[j]];
+      if (j < P.dim) { P.absv[j * P.Ko_pad + q] = xp[j][p[j]]; vsq += xp[j][p[j]] * xp[j][p[j]]; }
+    }
+    P.wq[q] = W;
+    for (int j = 0; j < P.dim; ++j) P.wq[(1 + j) * P.Ko_pad + q] = W * xp[j][p[j]];
+    // |v|^2 weight row (2D: the reduced distribution adds <v3^2> = 1/2)
+    P.wq[(1 + P.dim) * P.Ko_pad + q] = W * (vsq + (P.dim == 2 ? 0.5 : 0.0));
+    P.vsqm[q] = vsq - 1.5;
+    for (int combo = 0; combo < (1 << P.dim); ++combo) {
+      double den = P.nu;
+      for (int j = 0; j < P.dim; ++j) den += xp[j][p[j]] * dx_inv * (((combo >> j) & 1) ? 1.0 : 1.5);
+      P.rden[combo * P.Ko_pad + q] = 1.0 / den;
+    }
+  }
+  // D_j = sum over all velocities with v_j > 0 of W v_j (2^(dim-1) octants)
+  for (int j = 0; j < P.dim; ++j) {
+    double d = 0;
+    for (int q = 0; q < P.Ko; ++q) d += P.wq[(1 + j) * P.Ko_pad + q];
+    P.D[j] = d * (double)(1 << (P.dim - 1));
+  }
+
+  // geometry: flags and percolation
+  const uint8_t *sm = cfg->solid;
+  P.flags.assign(P.N, 0);
+  auto is_solid = [&](int x, int y, int z) { return sm[x + (int64_t)P.n[0] * (y + (int64_t)P.n[1] * z)] != 0; };
+  auto image = [&](int j, int c) {
+    if (j == 0) return c < 0 ? c + P.n[0] : c - P.n[0];
+    if (P.lateral_periodic) return c < 0 ? c + P.n[j] : c - P.n[j];
+    return c < 0 ? -c - 1 : 2 * P.n[j] - 1 - c;
+  };
+  int64_t fluid = 0;
+  for (int z = 0; z < P.n[2]; ++z)
+    for (int y = 0; y < P.n[1]; ++y)
+      for (int x = 0; x < P.n[0]; ++x) {
+        const int64_t c = x + (int64_t)P.n[0] * (y + (int64_t)P.n[1] * z);
+        if (sm[c]) { P.flags[c] = F_SOLID; continue; }
+        ++fluid;
+        uint32_t f = 0;
+        for (int j = 0; j < P.dim; ++j)
+          for (int si = 0; si < 2; ++si) {
+            const int s = si ? -1 : 1;
+            bool sol[3] = {false, false, false};
+            for (int m = 1; m <= 2; ++m) {
+              int cc[3] = {x, y, z};
+              cc[j] -= m * s;
+              if (cc[j] < 0 || cc[j] >= P.n[j]) cc[j] = image(j, cc[j]);
+              sol[m] = is_solid(cc[0], cc[1], cc[2]);
+            }
+            const bool first = sol[1] || (P.stencil_rule == 1 && sol[2]);
+            if (first) f |= f_first(j, si);
+            if (sol[1]) f |= f_y1s(j, si);
+            if (!first && sol[2]) f |= f_y2s(j, si);
+          }
+        P.flags[c] = f;
+      }
+  P.fluid = fluid;
+  if (fluid == 0) { err = "the geometry has no fluid voxel"; return PDVM_E_INVAL; }
+  {
+    PeriodicUF uf(P.N);
+    for (int z = 0; z < P.n[2]; ++z)
+      for (int y = 0; y < P.n[1]; ++y)
+        for (int x = 0; x < P.n[0]; ++x) {
+          const int64_t c = x + (int64_t)P.n[0] * (y + (int64_t)P.n[1] * z);
+          if (sm[c]) continue;
+          const int xn = x + 1 < P.n[0] ? x + 1 : 0;
+          const int64_t cx = xn + (int64_t)P.n[0] * (y + (int64_t)P.n[1] * z);
+          if (!sm[cx]) uf.unite(c, cx, x + 1 < P.n[0] ? 0 : 1);
+          if (y + 1 < P.n[1]) {
+            const int64_t cy = c + P.n[0];
+            if (!sm[cy]) uf.unite(c, cy, 0);
+          }
+          if (z + 1 < P.n[2]) {
+            const int64_t cz = c + (int64_t)P.n[0] * P.n[1];
+            if (!sm[cz]) uf.unite(c, cz, 0);
+          }
+        }
+    bool any = false;
+    for (int64_t c = 0; c < P.N && !any; ++c) {
+      if (sm[c]) continue;
+      int32_t o;
+      const int64_t r = uf.find(c, o);
+      any = uf.winds[r] != 0;
+    }
+    if (!any) { err = "no pore component winds around x1 (no flow path)"; return PDVM_E_INVAL; }
+  }
+
+  // sweep tiles and their diagonals (oriented tile coordinates sum to d)
+  {
+    // (x1, x2): a square compiled edge (4 or 8); x3: any depth
+    int e = cfg->tile[0] > 0 ? cfg->tile[0] : 8;
+    e = e <= kTileEdge[0] ? kTileEdge[0] : kTileEdge[1];
+    for (int a = 0; a < 3; ++a) {
+      int t = 1;
+      if (a < 2) t = e;
+      else if (P.dim == 3) t = cfg->tile[2] > 0 ? cfg->tile[2] : 8;
+      P.tile[a] = std::max(1, std::min(t, P.n[a]));
+      P.ntile[a] = (P.n[a] + P.tile[a] - 1) / P.tile[a];
+    }
+  }
+  P.ndiag = P.ntile[0] + P.ntile[1] + P.ntile[2] - 2;
+  std::vector<std::vector<int32_t>> per(P.ndiag);
+  for (int c = 0; c < P.ntile[2]; ++c)
+    for (int b = 0; b < P.ntile[1]; ++b)
+      for (int a = 0; a < P.ntile[0]; ++a) {
+        auto &v = per[a + b + c];
+        v.push_back(a); v.push_back(b); v.push_back(c); v.push_back(0);
+      }
+  P.diag_off.assign(1, 0);
+  for (auto &v : per) {
+    P.diag_tiles.insert(P.diag_tiles.end(), v.begin(), v.end());
+    P.diag_off.push_back((int32_t)(P.diag_tiles.size() / 4));
+  }
+  P.mom_blocks = (int)std::min<int64_t>((P.N + 3) / 4, 4096);
+  uint64_t fp = 1469598103934665603ull;
+  const double scal[5] = {P.kn, P.jump, (double)P.lateral_periodic, (double)P.tau_fb, (double)P.stencil_rule};
+  fp = fnv1a(fp, scal, sizeof(scal));
+  fp = fnv1a(fp, P.n, sizeof(P.n));
+  fp = fnv1a(fp, P.hv, sizeof(P.hv));
+  fp = fnv1a(fp, P.flags.data(), P.flags.size() * 4);
+  fp = fnv1a(fp, P.absv.data(), P.absv.size() * 8);
+  fp = fnv1a(fp, P.wq.data(), P.wq.size() * 8);
+  P.fingerprint = fp;
+  return PDVM_OK;
+}
+
+template <typename T>
+Layout<T> make_layout(const Problem &P) {
+  Layout<T> L{};
+  size_t o = 0;
+  auto take = [&](size_t bytes) { const size_t at = o; o += align256(bytes); return at; };
+  const size_t N = (size_t)P.N;
+  L.ctl = take(sizeof(Ctl));
+  L.flags = take(N * 4);
+  L.absv = take(3 * (size_t)P.Ko_pad * sizeof(T));
+  L.av = take(3 * (size_t)P.Ko_pad * sizeof(T));
+  L.vsqm = take((size_t)P.Ko_pad * sizeof(T));
+  L.rden = take(8 * (size_t)P.Ko_pad * sizeof(T));
+  L.wq = take(5 * (size_t)P.Ko_pad * 8);
+  for (int b = 0; b < 2; ++b) {
+    L.h[b] = take(N * (size_t)P.Kpad * sizeof(T));
+    L.src[b] = take(N * kSrcStride * sizeof(T));
+    L.srct[b] = take(N * sizeof(T));
+    L.wall[b] = take(N * 6 * sizeof(T));
+    L.rho[b] = take(N * 8);
+    L.u[b] = take(3 * N * 8);
+  }
+  L.part = take((size_t)P.mom_blocks * 4 * 8);
+  L.tiles = take(P.diag_tiles.size() * 4);
+  L.offs = take(P.diag_off.size() * 4);
+  L.scratch = take(8 * N * 8);  // tau, q (3), rho, u (3) staging
+  L.total = o;
+  return L;
+}
+
+size_t layout_bytes(const Problem &P) {
+  return P.precision == PDVM_FP64 ? make_layout<double>(P).total : make_layout<float>(P).total;
+}
+
+}  // namespace
+
+struct pdvm_solver {
+  Problem P;
+  hipStream_t stream = nullptr;
+  char *ws = nullptr;
+  bool own_ws = false;
+  size_t ws_bytes = 0;
+  Geo<double> gd{};
+  Geo<float> gf{};
+  double *scratch = nullptr;
+  Ctl *host_ctl = nullptr;   // pinned mirror of the control block
+  bool own_stream = false;
+  hipGraphExec_t graph = nullptr;
+  int graph_iters = 0;
+  std::string err;
+  int fail(int code, const char *fmt, ...) {
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof(buf), fmt, ap);
+    va_end(ap);
+    err = buf;
+    g_thread_error = buf;
+    return code;
+  }
+};
+
+#define HIPCHK(s, call)                                                              \
+  do {                                                                               \
+    hipError_t e_ = (call);                                                          \
+    if (e_ != hipSuccess) return (s)->fail(PDVM_E_HIP, "%s: %s", #call, hipGetErrorString(e_)); \
+  } while (0)
+
+namespace {
+
+template <typename T>
+Geo<T> &geo(pdvm_solver *s);
+template <>
+Geo<double> &geo<double>(pdvm_solver *s) { return s->gd; }
+template <>
+Geo<float> &geo<float>(pdvm_solver *s) { return s->gf; }
+
+template <typename T>
+int setup_device(pdvm_solver *s) {
+  const Problem &P = s->P;
+  const Layout<T> L = make_layout<T>(P);
+  Geo<T> &g = geo<T>(s);
+  char *b = s->ws;
+  g.dim = P.dim;
+  for (int a = 0; a < 3; ++a) { g.n[a] = P.n[a]; g.tile[a] = P.tile[a]; g.ntile[a] = P.ntile[a]; }
+  g.N = P.N;
+  g.Ko = P.Ko; g.Ko_pad = P.Ko_pad; g.Kpad = P.Kpad; g.ngroups = P.ngroups;
+  g.lateral_periodic = P.lateral_periodic;
+  g.tau_fb = P.tau_fb;
+  g.y2wall = P.stencil_rule == 0;
+  g.jump = T(P.jump);
+  g.nu = P.nu;
+  for (int j = 0; j < 3; ++j) g.D[j] = P.D[j] > 0 ? P.D[j] : 1.0;
+  g.ctl = (Ctl *)(b + L.ctl);
+  g.flags = (const uint32_t *)(b + L.flags);
+  g.absv = (const T *)(b + L.absv);
+  g.av = (const T *)(b + L.av);
+  g.vsqm = (const T *)(b + L.vsqm);
+  g.rden = (const T *)(b + L.rden);
+  g.wq = (const double *)(b + L.wq);
+  for (int k = 0; k < 2; ++k) {
+    g.h[k] = (T *)(b + L.h[k]);
+    g.src[k] = (T *)(b + L.src[k]);
+    g.srct[k] = (T *)(b + L.srct[k]);
+    g.wall[k] = (T *)(b + L.wall[k]);
+    g.rho[k] = (double *)(b + L.rho[k]);
+    g.u[k] = (double *)(b + L.u[k]);
+  }
+  g.part = (double *)(b + L.part);
+  g.mom_blocks = P.mom_blocks;
+  g.diag_tiles = (const int32_t *)(b + L.tiles);
+  g.diag_off = (const int32_t *)(b + L.offs);
+  g.ndiag = P.ndiag;
+  s->scratch = (double *)(b + L.scratch);
+
+  // tables in the sweep precision
+  std::vector<T> absv(P.absv.size()), av(P.absv.size()), vsqm(P.vsqm.size()), rden(P.rden.size());
+  for (size_t i = 0; i < absv.size(); ++i) { absv[i] = T(P.absv[i]); av[i] = T(P.absv[i] * P.n[0]); }
+  for (size_t i = 0; i < vsqm.size(); ++i) vsqm[i] = T(P.vsqm[i]);
+  for (size_t i = 0; i < rden.size(); ++i) rden[i] = T(P.rden[i]);
+  hipStream_t st = s->stream;
+  HIPCHK(s, hipMemsetAsync(b, 0, L.total, st));
+  HIPCHK(s, hipMemcpyAsync((void *)g.flags, P.flags.data(), P.flags.size() * 4, hipMemcpyHostToDevice, st));
+  HIPCHK(s, hipMemcpyAsync((void *)g.absv, absv.data(), absv.size() * sizeof(T), hipMemcpyHostToDevice, st));
+  HIPCHK(s, hipMemcpyAsync((void *)g.av, av.data(), av.size() * sizeof(T), hipMemcpyHostToDevice, st));
+  HIPCHK(s, hipMemcpyAsync((void *)g.vsqm, vsqm.data(), vsqm.size() * sizeof(T), hipMemcpyHostToDevice, st));
+  HIPCHK(s, hipMemcpyAsync((void *)g.rden, rden.data(), rden.size() * sizeof(T), hipMemcpyHostToDevice, st));
+  HIPCHK(s, hipMemcpyAsync((void *)g.wq, P.wq.data(), P.wq.size() * 8, hipMemcpyHostToDevice, st));
+  HIPCHK(s, hipMemcpyAsync((void *)g.diag_tiles, P.diag_tiles.data(), P.diag_tiles.size() * 4, hipMemcpyHostToDevice, st));
+  HIPCHK(s, hipMemcpyAsync((void *)g.diag_off, P.diag_off.data(), P.diag_off.size() * 4, hipMemcpyHostToDevice, st));
+  Ctl c{};
+  c.kn_coef = 2.0 / std::sqrt(M_PI) * (std::isinf(P.kn) ? 0.0 : P.kn);
+  c.err = -1.0;
+  c.stop = 1;
+  HIPCHK(s, hipMemcpyAsync(g.ctl, &c, sizeof(Ctl), hipMemcpyHostToDevice, st));
+  HIPCHK(s, hipStreamSynchronize(st));
+  return PDVM_OK;
+}
+
+template <typename T>
+int enqueue_iteration(pdvm_solver *s) {
+  const Geo<T> &g = geo<T>(s);
+  const int nsg = s->P.ngroups << s->P.dim;
+  for (int d = 0; d < s->P.ndiag; ++d) {
+    const int items = (s->P.diag_off[d + 1] - s->P.diag_off[d]) * nsg;
+    HIPCHK(s, launch_sweep<T>(g, d, items, s->stream));
+  }
+  HIPCHK(s, launch_moments<T>(g, s->stream));
+  HIPCHK(s, launch_reduce(g.ctl, g.part, g.mom_blocks, g.N, s->stream));
+  return PDVM_OK;
+}
+
+int enqueue_iteration_any(pdvm_solver *s) {
+  return s->P.precision == PDVM_FP64 ? enqueue_iteration<double>(s) : enqueue_iteration<float>(s);
+}
+
+Ctl *dev_ctl(pdvm_solver *s) { return s->P.precision == PDVM_FP64 ? s->gd.ctl : s->gf.ctl; }
+
+int build_graph(pdvm_solver *s) {
+  if (s->graph) return PDVM_OK;
+  // a few iterations per replay amortise the launch of the graph itself
+  const int per = std::max(1, std::min(8, s->P.check_every));
+  hipGraph_t gr;
+  HIPCHK(s, hipStreamBeginCapture(s->stream, hipStreamCaptureModeThreadLocal));
+  int rc = PDVM_OK;
+  for (int i = 0; i < per && rc == PDVM_OK; ++i) rc = enqueue_iteration_any(s);
+  hipError_t e = hipStreamEndCapture(s->stream, &gr);
+  if (rc != PDVM_OK) return rc;
+  if (e != hipSuccess) return s->fail(PDVM_E_HIP, "graph capture: %s", hipGetErrorString(e));
+  e = hipGraphInstantiate(&s->graph, gr, nullptr, nullptr, 0);
+  (void)hipGraphDestroy(gr);
+  if (e != hipSuccess) return s->fail(PDVM_E_HIP, "graph instantiate: %s", hipGetErrorString(e));
+  s->graph_iters = per;
+  return PDVM_OK;
+}
+
+int read_ctl(pdvm_solver *s) {
+  HIPCHK(s, hipMemcpyAsync(s->host_ctl, dev_ctl(s), sizeof(Ctl), hipMemcpyDeviceToHost, s->stream));
+  HIPCHK(s, hipStreamSynchronize(s->stream));
+  return PDVM_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int pdvm_halfrange_gh(int32_t n_total, double *nodes, double *weights) {
+  if (n_total < 2 || n_total % 2 || n_total > 64 || !nodes || !weights) {
+    set_thread_error("n_total must be even in [2, 64] and outputs non-NULL");
+    return PDVM_E_INVAL;
+  }
+  const int n = n_total / 2;
+  // discretise int_0^14 f(x) exp(-x^2) dx by composite Gauss-Legendre
+  std::vector<long double> gx, gw;
+  gauss_legendre(24, gx, gw);
+  const int panels = 96;
+  const long double X = 14.0L, hp = X / panels;
+  std::vector<long double> x, w;
+  for (int p = 0; p < panels; ++p)
+    for (size_t i = 0; i < gx.size(); ++i) {
+      const long double t = hp * (p + 0.5L * (gx[i] + 1));
+      x.push_back(t);
+      w.push_back(0.5L * hp * gw[i] * expl(-t * t));
+    }
+  // Stieltjes procedure for the recurrence coefficients
+  std::vector<long double> alpha(n), beta(n), p0(x.size(), 0), p1(x.size(), 1), p2(x.size());
+  long double norm_prev = 1;
+  for (int k = 0; k < n; ++k) {
+    long double nrm = 0, xn = 0;
+    for (size_t i = 0; i < x.size(); ++i) {
+      nrm += w[i] * p1[i] * p1[i];
+      xn += w[i] * x[i] * p1[i] * p1[i];
+    }
+    alpha[k] = xn / nrm;
+    beta[k] = k == 0 ? nrm : nrm / norm_prev;
+    norm_prev = nrm;
+    for (size_t i = 0; i < x.size(); ++i) {
+      p2[i] = (x[i] - alpha[k]) * p1[i] - (k == 0 ? 0 : beta[k]) * p0[i];
+      p0[i] = p1[i];
+      p1[i] = p2[i];
+    }
+  }
+  std::vector<long double> d(alpha), e(n, 0), z(n, 0);
+  for (int i = 0; i + 1 < n; ++i) e[i] = sqrtl(beta[i + 1]);
+  z[0] = 1;
+  if (!jacobi_eigen(d, e, z)) {
+    set_thread_error("eigenvalue iteration did not converge");
+    return PDVM_E_INVAL;
+  }
+  std::vector<std::pair<long double, long double>> nw(n);
+  long double tot = 0;
+  for (int i = 0; i < n; ++i) {
+    nw[i] = {d[i], beta[0] * z[i] * z[i]};
+    tot += nw[i].second;
+  }
+  std::sort(nw.begin(), nw.end());
+  for (int i = 0; i < n; ++i) {
+    nodes[n + i] = (double)nw[i].first;
+    nodes[n - 1 - i] = -(double)nw[i].first;
+    weights[n + i] = (double)(nw[i].second / (2 * tot));
+    weights[n - 1 - i] = weights[n + i];
+  }
+  return PDVM_OK;
+}
+
+size_t pdvm_workspace_bytes(const pdvm_config *cfg) {
+  Problem P;
+  std::string err;
+  if (validate_and_build(cfg, P, err) != PDVM_OK) {
+    g_thread_error = err;
+    return 0;
+  }
+  return layout_bytes(P);
+}
+
+int pdvm_create(const pdvm_config *cfg, void *dev_workspace, size_t ws_bytes, void *hip_stream,
+                pdvm_solver **out) {
+  if (!out) { set_thread_error("out is NULL"); return PDVM_E_INVAL; }
+  *out = nullptr;
+  pdvm_solver *s = new (std::nothrow) pdvm_solver();
+  if (!s) { set_thread_error("host allocation failed"); return PDVM_E_NOMEM; }
+  std::string err;
+  int rc = validate_and_build(cfg, s->P, err);
+  if (rc != PDVM_OK) {
+    g_thread_error = err;
+    delete s;
+    return rc;
+  }
+  s->stream = (hipStream_t)hip_stream;
+  if (!s->stream) {
+    // the null stream cannot be captured into a graph: use a private one
+    if (hipStreamCreateWithFlags(&s->stream, hipStreamNonBlocking) != hipSuccess) {
+      set_thread_error("hipStreamCreate failed");
+      delete s;
+      return PDVM_E_HIP;
+    }
+    s->own_stream = true;
+  }
+  const size_t need = layout_bytes(s->P);
+  if (dev_workspace) {
+    if (ws_bytes < need || ((uintptr_t)dev_workspace & 255)) {
+      set_thread_error("workspace needs %zu bytes, 256-byte aligned (got %zu)", need, ws_bytes);
+      pdvm_destroy(s);
+      return PDVM_E_NOMEM;
+    }
+    s->ws = (char *)dev_workspace;
+  } else {
+    void *p = nullptr;
+    if (hipMalloc(&p, need) != hipSuccess) {
+      set_thread_error("hipMalloc of %zu bytes failed", need);
+      pdvm_destroy(s);
+      return PDVM_E_NOMEM;
+    }
+    s->ws = (char *)p;
+    s->own_ws = true;
+  }
+  s->ws_bytes = need;
+  if (hipHostMalloc((void **)&s->host_ctl, sizeof(Ctl), hipHostMallocDefault) != hipSuccess) {
+    set_thread_error("pinned host allocation failed");
+    pdvm_destroy(s);
+    return PDVM_E_NOMEM;
+  }
+  rc = s->P.precision == PDVM_FP64 ? setup_device<double>(s) : setup_device<float>(s);
+  if (rc != PDVM_OK) {
+    g_thread_error = s->err;
+    pdvm_destroy(s);
+    return rc;
+  }
+  *out = s;
+  return PDVM_OK;
+}
+
+int pdvm_set_initial(pdvm_solver *s, const double *rho, const double *u) {
+  if (!s) { set_thread_error("solver is NULL"); return PDVM_E_INVAL; }
+  const int64_t N = s->P.N;
+  double *drho = nullptr, *du = nullptr;
+  if (rho) {
+    drho = s->scratch + 4 * N;
+    HIPCHK(s, hipMemcpyAsync(drho, rho, N * 8, hipMemcpyHostToDevice, s->stream));
+  }
+  if (u) {
+    du = s->scratch + 5 * N;
+    HIPCHK(s, hipMemcpyAsync(du, u, (size_t)s->P.dim * N * 8, hipMemcpyHostToDevice, s->stream));
+  }
+  // reset the counters, keep parity
+  HIPCHK(s, hipMemcpyAsync(s->host_ctl, dev_ctl(s), sizeof(Ctl), hipMemcpyDeviceToHost, s->stream));
+  HIPCHK(s, hipStreamSynchronize(s->stream));
+  Ctl c = *s->host_ctl;
+  c.iter = 0;
+  c.stop = 1;
+  c.status = 0;
+  c.err = -1.0;
+  c.r = c.k = c.gp = 0;
+  for (double &v : c.kring) v = 0;
+  *s->host_ctl = c;
+  HIPCHK(s, hipMemcpyAsync(dev_ctl(s), s->host_ctl, sizeof(Ctl), hipMemcpyHostToDevice, s->stream));
+  if (s->P.precision == PDVM_FP64) HIPCHK(s, launch_init_state<double>(s->gd, drho, du, s->stream));
+  else HIPCHK(s, launch_init_state<float>(s->gf, drho, du, s->stream));
+  HIPCHK(s, hipStreamSynchronize(s->stream));
+  return PDVM_OK;
+}
+
+int pdvm_iterate(pdvm_solver *s, int64_t max_iters, double tol, int32_t stop_mode, pdvm_stats *out) {
+  if (!s) { set_thread_error("solver is NULL"); return PDVM_E_INVAL; }
+  if (max_iters < 0 || (stop_mode != PDVM_STOP_FIELD && stop_mode != PDVM_STOP_PAPER_ERR) || std::isnan(tol))
+    return s->fail(PDVM_E_INVAL, "max_iters >= 0, a valid stop mode and a non-NaN tol are required");
+  const auto t0 = std::chrono::steady_clock::now();
+  int rc = build_graph(s);
+  if (rc != PDVM_OK) return rc;
+  rc = read_ctl(s);
+  if (rc != PDVM_OK) return rc;
+  const int64_t start = s->host_ctl->iter;
+  HIPCHK(s, launch_arm(dev_ctl(s), tol, stop_mode, max_iters, s->stream));
+  int64_t launched = 0;
+  const int per = s->graph_iters;
+  const int poll = std::max(per, s->P.check_every / per * per);
+  while (launched < max_iters) {
+    int64_t batch = 0;
+    while (batch < poll && launched < max_iters) {
+      HIPCHK(s, hipGraphLaunch(s->graph, s->stream));
+      batch += per;
+      launched += per;
+    }
+    rc = read_ctl(s);
+    if (rc != PDVM_OK) return rc;
+    if (s->host_ctl->stop) break;
+  }
+  if (launched >= max_iters) {
+    rc = read_ctl(s);
+    if (rc != PDVM_OK) return rc;
+  }
+  const Ctl &c = *s->host_ctl;
+  if (out) {
+    out->iters = c.iter - start;
+    out->total_iters = c.iter;
+    out->r = c.r;
+    out->err = c.err;
+    out->k = c.k;
+    out->gp = c.gp;
+    out->seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+    out->converged = c.status == 1;
+  }
+  if (c.status == -4) return s->fail(PDVM_E_NONFINITE, "residual or permeability became non-finite at iteration %lld; the previous state is kept", (long long)(c.iter + 1));
+  return c.status == 1 ? PDVM_OK : PDVM_NOT_CONVERGED;
+}
+
+int pdvm_get_moments(pdvm_solver *s, double *rho, double *u, double *tau, double *q) {
+  if (!s) { set_thread_error("solver is NULL"); return PDVM_E_INVAL; }
+  int rc = read_ctl(s);
+  if (rc != PDVM_OK) return rc;
+  const int par = s->host_ctl->par;
+  const int64_t N = s->P.N;
+  const double *drho = s->P.precision == PDVM_FP64 ? s->gd.rho[par] : s->gf.rho[par];
+  const double *du = s->P.precision == PDVM_FP64 ? s->gd.u[par] : s->gf.u[par];
+  if (rho) HIPCHK(s, hipMemcpyAsync(rho, drho, N * 8, hipMemcpyDeviceToHost, s->stream));
+  if (u) HIPCHK(s, hipMemcpyAsync(u, du, (size_t)s->P.dim * N * 8, hipMemcpyDeviceToHost, s->stream));
+  if (tau || q) {
+    double *dt = s->scratch, *dq = s->scratch + N;
+    if (s->P.precision == PDVM_FP64) HIPCHK(s, launch_diagnostics<double>(s->gd, dt, dq, s->stream));
+    else HIPCHK(s, launch_diagnostics<float>(s->gf, dt, dq, s->stream));
+    if (tau) HIPCHK(s, hipMemcpyAsync(tau, dt, N * 8, hipMemcpyDeviceToHost, s->stream));
+    if (q) HIPCHK(s, hipMemcpyAsync(q, dq, (size_t)s->P.dim * N * 8, hipMemcpyDeviceToHost, s->stream));
+  }
+  HIPCHK(s, hipStreamSynchronize(s->stream));
+  // solid voxels read 0 (the device buffers never write them after rest)
+  return PDVM_OK;
+}
+
+int pdvm_get_flux(pdvm_solver *s, double *gp, double *k, double *gp_section) {
+  if (!s) { set_thread_error("solver is NULL"); return PDVM_E_INVAL; }
+  const int64_t N = s->P.N;
+  std::vector<double> u1(N);
+  int rc = read_ctl(s);
+  if (rc != PDVM_OK) return rc;
+  const int par = s->host_ctl->par;
+  const double *du = s->P.precision == PDVM_FP64 ? s->gd.u[par] : s->gf.u[par];
+  HIPCHK(s, hipMemcpyAsync(u1.data(), du, N * 8, hipMemcpyDeviceToHost, s->stream));
+  HIPCHK(s, hipStreamSynchronize(s->stream));
+  double tot = 0;
+  for (int64_t c = 0; c < N; ++c) tot += (s->P.flags[c] & F_SOLID) ? 0.0 : u1[c];
+  const double G = tot / (double)N;
+  if (gp) *gp = G;
+  if (k) *k = 2.0 / std::sqrt(M_PI) * (std::isinf(s->P.kn) ? 0.0 : s->P.kn) * G;
+  if (gp_section) {
+    const int n0 = s->P.n[0];
+    const int64_t A = N / n0;
+    for (int i = 0; i < n0; ++i) gp_section[i] = 0;
+    for (int64_t c = 0; c < N; ++c)
+      if (!(s->P.flags[c] & F_SOLID)) gp_section[c % n0] += u1[c];
+    for (int i = 0; i < n0; ++i) gp_section[i] /= (double)A;
+  }
+  return PDVM_OK;
+}
+
+}  // extern "C"
+
+// checkpoint layout: header, Ctl, then per parity-current buffer: rho, u, src,
+// wall, then the boundary layers of h.
+namespace {
+struct StateHeader {
+  uint64_t magic;
+  int32_t dim, n0, n1, n2, Kpad, precision;
+  int64_t fluid;
+  uint64_t fingerprint;
+};
+constexpr uint64_t kMagic = 0x31504d56444d4150ull;  // "PAMDVMP1"
+
+std::vector<int> face_layers(const Problem &P, int a) {
+  std::vector<int> r;
+  for (int v : {0, 1, P.n[a] - 2, P.n[a] - 1})
+    if (v >= 0 && v < P.n[a] && std::find(r.begin(), r.end(), v) == r.end()) r.push_back(v);
+  return r;
+}
+
+size_t state_bytes(const Problem &P) {
+  const size_t es = P.precision == PDVM_FP64 ? 8 : 4;
+  const size_t N = (size_t)P.N;
+  size_t b = sizeof(StateHeader) + sizeof(Ctl) + N * 8 + 3 * N * 8 + N * kSrcStride * es + N * es + N * 6 * es;
+  for (int a = 0; a < P.dim; ++a) b += face_layers(P, a).size() * (N / P.n[a]) * (size_t)P.Kpad * es;
+  return b;
+}
+
+template <typename T>
+int state_io(pdvm_solver *s, char *buf, bool save) {
+  const Problem &P = s->P;
+  Geo<T> &g = geo<T>(s);
+  const size_t N = (size_t)P.N;
+  int rc = read_ctl(s);
+  if (rc != PDVM_OK) return rc;
+  const int par = s->host_ctl->par;
+  char *p = buf + sizeof(StateHeader) + sizeof(Ctl);
+  auto xfer = [&](void *dev, size_t bytes) -> int {
+    hipError_t e = save ? hipMemcpyAsync(p, dev, bytes, hipMemcpyDeviceToHost, s->stream)
+                        : hipMemcpyAsync(dev, p, bytes, hipMemcpyHostToDevice, s->stream);
+    p += bytes;
+    return e == hipSuccess ? PDVM_OK : s->fail(PDVM_E_HIP, "state copy: %s", hipGetErrorString(e));
+  };
+  if ((rc = xfer(g.rho[par], N * 8))) return rc;
+  if ((rc = xfer(g.u[par], 3 * N * 8))) return rc;
+  if ((rc = xfer(g.src[par], N * kSrcStride * sizeof(T)))) return rc;
+  if ((rc = xfer(g.srct[par], N * sizeof(T)))) return rc;
+  if ((rc = xfer(g.wall[par], N * 6 * sizeof(T)))) return rc;
+  T *stage = g.h[par ^ 1];  // free between iterations
+  for (int a = 0; a < P.dim; ++a)
+    for (int r : face_layers(P, a)) {
+      const size_t bytes = (N / P.n[a]) * (size_t)P.Kpad * sizeof(T);
+      if (save) {
+        HIPCHK(s, launch_face_copy<T>(g, a, r, stage, 1, s->stream));
+        if ((rc = xfer(stage, bytes))) return rc;
+      } else {
+        if ((rc = xfer(stage, bytes))) return rc;
+        HIPCHK(s, launch_face_copy<T>(g, a, r, stage, 0, s->stream));
+      }
+      HIPCHK(s, hipStreamSynchronize(s->stream));
+    }
+  HIPCHK(s, hipStreamSynchronize(s->stream));
+  return PDVM_OK;
+}
+}  // namespace
+
+extern "C" {
+
+int pdvm_get_state(pdvm_solver *s, void *buf, size_t *bytes) {
+  if (!s || !bytes) { set_thread_error("solver or bytes is NULL"); return PDVM_E_INVAL; }
+  const size_t need = state_bytes(s->P);
+  if (!buf) { *bytes = need; return PDVM_OK; }
+  if (*bytes < need) return s->fail(PDVM_E_STATE, "state buffer needs %zu bytes", need);
+  int rc = read_ctl(s);
+  if (rc != PDVM_OK) return rc;
+  StateHeader h{kMagic, s->P.dim, s->P.n[0], s->P.n[1], s->P.n[2], s->P.Kpad, s->P.precision, s->P.fluid,
+                s->P.fingerprint};
+  std::memcpy(buf, &h, sizeof(h));
+  std::memcpy((char *)buf + sizeof(h), s->host_ctl, sizeof(Ctl));
+  rc = s->P.precision == PDVM_FP64 ? state_io<double>(s, (char *)buf, true) : state_io<float>(s, (char *)buf, true);
+  *bytes = need;
+  return rc;
+}
+
+int pdvm_set_state(pdvm_solver *s, const void *buf, size_t bytes) {
+  if (!s || !buf) { set_thread_error("solver or buf is NULL"); return PDVM_E_INVAL; }
+  const size_t need = state_bytes(s->P);
+  if (bytes != need) return s->fail(PDVM_E_STATE, "state has %zu bytes, this problem needs %zu", bytes, need);
+  StateHeader h;
+  std::memcpy(&h, buf, sizeof(h));
+  if (h.magic != kMagic || h.dim != s->P.dim || h.n0 != s->P.n[0] || h.n1 != s->P.n[1] || h.n2 != s->P.n[2] ||
+      h.Kpad != s->P.Kpad || h.precision != s->P.precision || h.fluid != s->P.fluid ||
+      h.fingerprint != s->P.fingerprint)
+    return s->fail(PDVM_E_STATE, "state belongs to a different problem");
+  Ctl c;
+  std::memcpy(&c, (const char *)buf + sizeof(h), sizeof(Ctl));
+  int rc = read_ctl(s);
+  if (rc != PDVM_OK) return rc;
+  c.par = s->host_ctl->par;  // restore into this solver's current buffers
+  c.stop = 1;
+  *s->host_ctl = c;
+  HIPCHK(s, hipMemcpyAsync(dev_ctl(s), s->host_ctl, sizeof(Ctl), hipMemcpyHostToDevice, s->stream));
+  HIPCHK(s, hipStreamSynchronize(s->stream));
+  return s->P.precision == PDVM_FP64 ? state_io<double>(s, (char *)buf, false)
+                                     : state_io<float>(s, (char *)buf, false);
+}
+
+int pdvm_time_kernels(pdvm_solver *s, int32_t iters, pdvm_timing *out) {
+  if (!s || !out || iters <= 0) { set_thread_error("bad arguments"); return PDVM_E_INVAL; }
+  const Problem &P = s->P;
+  HIPCHK(s, launch_arm(dev_ctl(s), 0.0, 0, (int64_t)iters + 1, s->stream));
+  const int nd = P.ndiag;
+  std::vector<hipEvent_t> ev(nd + 3);
+  for (auto &e : ev) HIPCHK(s, hipEventCreate(&e));
+  double sweep = 0, mom = 0, red = 0, tot = 0;
+  const int nsg = P.ngroups << P.dim;
+  for (int it = 0; it < iters; ++it) {
+    HIPCHK(s, hipEventRecord(ev[0], s->stream));
+    for (int d = 0; d < nd; ++d) {
+      const int items = (P.diag_off[d + 1] - P.diag_off[d]) * nsg;
+      if (P.precision == PDVM_FP64) HIPCHK(s, launch_sweep<double>(s->gd, d, items, s->stream));
+      else HIPCHK(s, launch_sweep<float>(s->gf, d, items, s->stream));
+    }
+    HIPCHK(s, hipEventRecord(ev[1], s->stream));
+    if (P.precision == PDVM_FP64) HIPCHK(s, launch_moments<double>(s->gd, s->stream));
+    else HIPCHK(s, launch_moments<float>(s->gf, s->stream));
+    HIPCHK(s, hipEventRecord(ev[2], s->stream));
+    HIPCHK(s, launch_reduce(dev_ctl(s), P.precision == PDVM_FP64 ? s->gd.part : s->gf.part, P.mom_blocks, P.N, s->stream));
+    HIPCHK(s, hipEventRecord(ev[3], s->stream));
+    HIPCHK(s, hipEventSynchronize(ev[3]));
+    float a = 0, b = 0, c = 0;
+    HIPCHK(s, hipEventElapsedTime(&a, ev[0], ev[1]));
+    HIPCHK(s, hipEventElapsedTime(&b, ev[1], ev[2]));
+    HIPCHK(s, hipEventElapsedTime(&c, ev[2], ev[3]));
+    sweep += a;
+    mom += b;
+    red += c;
+    tot += a + b + c;
+  }
+  for (auto &e : ev) (void)hipEventDestroy(e);
+  const double es = P.precision == PDVM_FP64 ? 8.0 : 4.0;
+  out->sweep_ms_per_iter = sweep / iters;
+  out->moments_ms_per_iter = mom / iters;
+  out->iter_ms = tot / iters;
+  out->sweep_launches_per_iter = nd;
+  out->sweep_ms_per_launch = sweep / iters / nd;
+  out->moments_ms_per_launch = mom / iters;
+  out->reduce_ms_per_launch = red / iters;
+  out->fluid_cells = (double)P.fluid;
+  out->velocities = (double)(P.Ko << P.dim);
+  out->sweep_bytes_per_iter = es * (double)P.fluid * (double)(P.Ko << P.dim);
+  out->moments_bytes_per_iter = es * (double)P.fluid * (double)(P.Ko << P.dim);
+  return PDVM_OK;
+}
+
+void pdvm_destroy(pdvm_solver *s) {
+  if (!s) return;
+  if (s->graph) (void)hipGraphExecDestroy(s->graph);
+  if (s->stream) (void)hipStreamSynchronize(s->stream);
+  else (void)hipDeviceSynchronize();
+  if (s->own_ws && s->ws) (void)hipFree(s->ws);
+  if (s->host_ctl) (void)hipHostFree(s->host_ctl);
+  if (s->own_stream) (void)hipStreamDestroy(s->stream);
+  delete s;
+}
+
+const char *pdvm_last_error(const pdvm_solver *s) {
+  if (s) return s->err.c_str();
+  return g_thread_error.c_str();
+}
+
+}  // extern "C"

@@ -1,0 +1,91 @@
+// Internal declarations shared by the HIP kernels and the host library.
+// Not part of the public C ABI (include/poredvm.h).
+#pragma once
+#include <hip/hip_runtime.h>
+#include <cstdint>
+
+namespace pdvm {
+
+constexpr int kWave = 64;     // CDNA wavefront width: one discrete velocity per lane
+constexpr int kRing = 64;     // permeability history kept at multiples of 100 iterations
+constexpr int kMomBlock = 256;
+constexpr int kSrcStride = 4; // per-voxel source record: nu rho, 2 nu u_1, 2 nu u_2, 2 nu u_3 (0 in 2D)
+
+// Per-voxel flags, computed once on the host from the solid mask (the paper's
+// pre-processing of the stencil order, Sec. 2.3). For axis j and upwind sign
+// s (sidx = 0 for s = +1, 1 for s = -1): FIRST = use the first-order stencil;
+// Y1S = the image of x - s e_j is solid (its wall value is the first upstream
+// value); Y2S = second-order stencil whose image of x - 2 s e_j is solid
+// (wall value there).
+constexpr uint32_t F_SOLID = 1u;
+__host__ __device__ constexpr int fbit(int j, int sidx) { return 1 + 3 * (2 * j + sidx); }
+__host__ __device__ constexpr uint32_t f_first(int j, int sidx) { return 1u << fbit(j, sidx); }
+__host__ __device__ constexpr uint32_t f_y1s(int j, int sidx) { return 1u << (fbit(j, sidx) + 1); }
+__host__ __device__ constexpr uint32_t f_y2s(int j, int sidx) { return 1u << (fbit(j, sidx) + 2); }
+
+// Device-resident control block. `par` selects which of the two buffers of
+// every iterated array holds the last completed iteration; the reduction
+// kernel flips it only when the new iterate is finite, so a failing
+// iteration leaves the previous state intact. Every kernel returns at once
+// while `stop` is set, so graph replays past convergence cost no work.
+struct Ctl {
+  int32_t par;
+  int32_t stop;
+  int32_t status;       // 0 running, 1 converged, 2 budget reached, -4 non-finite
+  int32_t mode;         // 0 field residual, 1 paper Err(l)
+  int64_t iter;         // iterations since the initial state
+  int64_t iter_limit;   // stop (status 2) when iter reaches this
+  double tol;
+  double r, err, k, gp;
+  double kn_coef;       // (2/sqrt(pi)) Kn
+  double kring[kRing];  // k at iterations 100, 200, ... (cyclic)
+};
+
+template <typename T>
+struct Geo {
+  int32_t dim, n[3];
+  int64_t N;
+  int32_t Ko, Ko_pad, Kpad, ngroups;  // velocities per sign octant, padded, per voxel, 64-groups per octant
+  int32_t lateral_periodic, tau_fb;
+  int32_t y2wall;          // stencil rule 0: a solid second image enters the second-order stencil
+  T jump;
+  double nu, D[3];
+  const uint32_t *flags;   // [N]
+  const T *absv;           // [3][Ko_pad]   |v_j| of octant slot q
+  const T *av;             // [3][Ko_pad]   |v_j| / dx
+  const T *vsqm;           // [Ko_pad]      |v|^2 - 3/2
+  const T *rden;           // [8][Ko_pad]   1 / (nu + sum_j a_j (1 or 3/2)), bit j = first order on axis j
+  const double *wq;        // [5][Ko_pad]   W, W|v1|, W|v2|, W|v3|, W |v|^2 (2D: + W/2)
+  T *h[2];                 // [N][Kpad]     distribution, voxel-major, velocity fastest
+  T *src[2];               // [N][kSrcStride]
+  T *srct[2];              // [N] nu tau (only with the temperature term fed back)
+  T *wall[2];              // [N][6]        Phi_j^p / D_j  (p = 0: v_j > 0 half, 1: v_j < 0)
+  double *rho[2];          // [N]
+  double *u[2];            // [3][N]
+  Ctl *ctl;
+  double *part;            // [mom_blocks][4] per-block residual / flux partials
+  int32_t mom_blocks;
+  int32_t tile[3], ntile[3];
+  const int32_t *diag_tiles;  // [count][4] oriented tile coordinates (x1, x2, x3, pad)
+  const int32_t *diag_off;    // [ndiag + 1]
+  int32_t ndiag;
+};
+
+// Kernel launchers (dvm_kernels.hip). All enqueue on `st`.
+// Square sweep tile edges in (x1, x2) compiled into the kernel; the host
+// rounds a requested edge up to one of them.
+constexpr int kTileEdge[2] = {4, 8};
+template <typename T>
+hipError_t launch_sweep(const Geo<T> &g, int diag, int items, hipStream_t st);
+template <typename T>
+hipError_t launch_moments(const Geo<T> &g, hipStream_t st);
+hipError_t launch_reduce(Ctl *ctl, const double *part, int nblocks, int64_t N, hipStream_t st);
+hipError_t launch_arm(Ctl *ctl, double tol, int mode, int64_t max_iters, hipStream_t st);
+template <typename T>
+hipError_t launch_init_state(const Geo<T> &g, const double *rho, const double *u, hipStream_t st);
+template <typename T>
+hipError_t launch_diagnostics(const Geo<T> &g, double *tau, double *q, hipStream_t st);
+template <typename T>
+hipError_t launch_face_copy(const Geo<T> &g, int axis, int r, T *buf, int to_buf, hipStream_t st);
+
+}  // namespace pdvm

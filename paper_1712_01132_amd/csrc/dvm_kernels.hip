@@ -1,0 +1,671 @@
+// HIP kernels for gfx950 (CDNA4): the iteration of the discrete-velocity
+// solver of the steady linearised BGK equation (Sec. 3.1, Algorithm 1).
+//
+//   sweep_kernel      step (i): upwind forward substitution (Eq. numerical stencil,
+//                     Eq. Discretised_linearised_Boltzmann_equations) for one
+//                     diagonal of sweep tiles. One wavefront = one tile x 64
+//                     discrete velocities of one sign octant: lanes are velocities,
+//                     so every per-voxel decision (solid, stencil order, wall,
+//                     image) is wavefront-uniform and each voxel's 64 values are
+//                     one contiguous store.
+//   moments_kernel    steps (ii)-(iii): quadrature moments rho, u and the half-fluxes
+//                     Phi_j^+- of every fluid voxel (Eq. perturbed_quantities), the
+//                     wall densities Phi/D (Eq. wall_density), the rebuilt source
+//                     coefficients, and per-block FP64 residual / flux partials.
+//   reduce_kernel     steps (iv)-(v): FP64 residual, G_p, k (Eq. k_Gp), Err(l)
+//                     (Eq. convergence_criterion), stop decision, state flip.
+#include "dvm_internal.h"
+
+namespace pdvm {
+namespace {
+
+struct Img {
+  int r, mir, jmp;
+};
+
+// Image of a node coordinate c outside [0, n) along axis j: periodic with the
+// pressure jump along x1 (Eq. periodic_BC), specular across the outer voxel
+// face of a lateral axis (Eq. symmetric_BC) or plain periodic if requested.
+__device__ __forceinline__ Img image_of(int j, int c, int n, int lat_periodic) {
+  Img im{c, 0, 0};
+  if (j == 0) {
+    if (c < 0) { im.r = c + n; im.jmp = 1; }
+    else       { im.r = c - n; im.jmp = -1; }
+  } else if (lat_periodic) {
+    im.r = c < 0 ? c + n : c - n;
+  } else {
+    im.r = c < 0 ? -c - 1 : 2 * n - 1 - c;
+    im.mir = 1;
+  }
+  return im;
+}
+
+template <typename T>
+__device__ __forceinline__ int64_t cell_of(const Geo<T> &g, int x, int y, int z) {
+  return x + (int64_t)g.n[0] * (y + (int64_t)g.n[1] * z);
+}
+
+// h at an upstream fluid node along axis j: the current sweep inside the
+// domain, the previous iteration's value at the image outside it (with the
+// mirrored velocity across a specular face and the jump across the x1 wrap).
+template <typename T>
+__device__ __forceinline__ T upstream_fluid(const Geo<T> &g, const T *hc, const T *hp, int j,
+                                            int x, int y, int z, int kofs, int kmir) {
+  int c[3] = {x, y, z};
+  if (c[j] >= 0 && c[j] < g.n[j]) return hc[cell_of(g, c[0], c[1], c[2]) * g.Kpad + kofs];
+  const Img im = image_of(j, c[j], g.n[j], g.lateral_periodic);
+  c[j] = im.r;
+  const T v = hp[cell_of(g, c[0], c[1], c[2]) * g.Kpad + (im.mir ? kmir : kofs)];
+  return im.jmp ? v + T(im.jmp) * g.jump : v;
+}
+
+// Wall value of a solid met at the second upstream node along axis j: the wall
+// density seen from the first upstream (fluid) node y1 = x - s e_j, i.e. its
+// incoming half-flux over D_j, carried through y1's image if y1 is outside.
+template <typename T>
+__device__ __forceinline__ T wall_at_y1(const Geo<T> &g, const T *wall, int j, int s, int pin,
+                                                  int x, int y, int z) {
+  int c[3] = {x, y, z};
+  c[j] -= s;
+  if (c[j] >= 0 && c[j] < g.n[j]) return wall[cell_of(g, c[0], c[1], c[2]) * 6 + 2 * j + pin];
+  const Img im = image_of(j, c[j], g.n[j], g.lateral_periodic);
+  c[j] = im.r;
+  const int p = im.mir ? 1 - pin : pin;
+  const T v = wall[cell_of(g, c[0], c[1], c[2]) * 6 + 2 * j + p];
+  return im.jmp ? v + T(im.jmp) * g.jump : v;
+}
+
+// Step (i) for one diagonal of tiles. One wavefront = one tile x 64 discrete
+// velocities of one sign octant (lanes = velocities), so every per-voxel
+// decision is wavefront-uniform and each voxel's 64 values are one contiguous
+// store. The tile is TT x TT voxels in (x1, x2), any depth along x3, walked
+// plane by plane in the octant's order. Per plane, each lane first decodes one
+// voxel of the plane into an LDS record (source coefficients and, per axis,
+// the stencil weights on the two upstream values and the wall term); the
+// wavefront then walks the plane's 2 TT - 1 anti-diagonals, whose voxels are
+// independent of each other, so their loads and FMA chains overlap. The two
+// previous anti-diagonals stay in registers; values outside the tile come
+// from the current sweep of upstream tiles (earlier launches) or from the
+// lagged images outside the domain.
+constexpr uint32_t R_SKIP = 0x80000000u;  // solid voxel or outside the tile
+
+template <typename T, int DIM, int TT, bool Y2WALL>
+__global__ void __launch_bounds__(kWave)
+    sweep_kernel(Geo<T> g, int diag, const uint32_t *__restrict__ flags, const T *__restrict__ src0,
+                 const T *__restrict__ src1, const T *__restrict__ srct0, const T *__restrict__ srct1,
+                 const T *__restrict__ wall0, const T *__restrict__ wall1, T *__restrict__ h0,
+                 T *__restrict__ h1) {
+  constexpr int NC = TT * TT;
+  constexpr int RW = 5 + 3 * DIM;  // record: src (4), nu tau, then per axis (c1, c2, w)
+  __shared__ T rd_lds[8 * kWave];
+  __shared__ T rec[NC * RW];
+  __shared__ uint32_t rcode[NC];
+  const Ctl *ctl = g.ctl;
+  if (ctl->stop) return;
+  const int par = ctl->par;
+  const int d0 = g.diag_off[diag];
+  const int ntd = g.diag_off[diag + 1] - d0;
+  int item = blockIdx.x;
+  const int t = item % ntd;
+  item /= ntd;
+  const int grp = item % g.ngroups;
+  const int o = item / g.ngroups;
+  const int lane = threadIdx.x;
+  const int q = grp * kWave + lane;
+  const bool active = q < g.Ko;
+  const int qq = active ? q : 0;
+  int s[3], sidx[3], pin[3];
+#pragma unroll
+  for (int j = 0; j < 3; ++j) {
+    sidx[j] = (o >> j) & 1;
+    s[j] = sidx[j] ? -1 : 1;
+    pin[j] = 1 - sidx[j];  // incoming half at a wall emitting along s e_j has sign -s
+  }
+  T vv[3] = {T(0), T(0), T(0)}, aa[3] = {T(0), T(0), T(0)};
+#pragma unroll
+  for (int j = 0; j < DIM; ++j) {
+    const T av = g.absv[j * g.Ko_pad + qq];
+    vv[j] = s[j] > 0 ? av : -av;
+    aa[j] = g.av[j * g.Ko_pad + qq];
+  }
+#pragma unroll
+  for (int c = 0; c < (1 << DIM); ++c) rd_lds[c * kWave + lane] = g.rden[c * g.Ko_pad + qq];
+  const T vsqm = g.tau_fb ? g.vsqm[qq] : T(0);
+  const int kofs = o * g.Ko_pad + qq;
+  int kmir[3];
+#pragma unroll
+  for (int j = 0; j < 3; ++j) kmir[j] = (o ^ (1 << j)) * g.Ko_pad + qq;
+  T *hc = par ? h0 : h1;
+  const T *hp = par ? h1 : h0;
+  const T *src = par ? src1 : src0;
+  const T *srct = par ? srct1 : srct0;
+  const T *wall = par ? wall1 : wall0;
+  const int n0 = g.n[0], n1 = g.n[1];
+
+  int lo[3] = {0, 0, 0}, cnt[3] = {1, 1, 1};
+#pragma unroll
+  for (int j = 0; j < DIM; ++j) {
+    const int tp = g.diag_tiles[(d0 + t) * 4 + j];
+    const int tj = s[j] > 0 ? tp : g.ntile[j] - 1 - tp;
+    lo[j] = tj * g.tile[j];
+    cnt[j] = min(g.tile[j], g.n[j] - lo[j]);
+  }
+  const int xs = s[0] > 0 ? lo[0] : lo[0] + cnt[0] - 1;
+  const int ys = s[1] > 0 ? lo[1] : lo[1] + cnt[1] - 1;
+
+  for (int c3 = 0; c3 < cnt[2]; ++c3) {
+    const int z = s[2] > 0 ? lo[2] + c3 : lo[2] + cnt[2] - 1 - c3;
+    // --- stage: lane = voxel of the plane ---------------------------------
+    if (lane < NC) {
+      const int i = lane % TT, r = lane / TT;
+      uint32_t code = R_SKIP;
+      if (i < cnt[0] && r < cnt[1]) {
+        const int x = xs + i * s[0], y = ys + r * s[1];
+        const int c = (y + n1 * z) * n0 + x;
+        const uint32_t f = flags[c];
+        if (!(f & F_SOLID)) {
+          T *rp = rec + lane * RW;
+          const T *sp = src + c * kSrcStride;
+          rp[0] = sp[0];
+          rp[1] = sp[1];
+          rp[2] = sp[2];
+          rp[3] = DIM == 3 ? sp[3] : T(0);
+          rp[4] = g.tau_fb ? srct[c] : T(0);
+          code = 0;
+#pragma unroll
+          for (int j = 0; j < DIM; ++j) {
+            const uint32_t fj = f >> fbit(j, sidx[j]);
+            const bool first = fj & 1u, y1s = fj & 2u, y2s = fj & 4u;
+            T c1 = first ? (y1s ? T(0) : T(1)) : T(2);
+            T c2 = first ? T(0) : T(-0.5);
+            T w = (first && y1s) ? wall[c * 6 + 2 * j + pin[j]] : T(0);
+            if (Y2WALL && !first && y2s) {
+              c2 = T(0);
+              w = T(-0.5) * wall_at_y1(g, wall, j, s[j], pin[j], x, y, z);
+            }
+            rp[5 + 3 * j] = c1;
+            rp[6 + 3 * j] = c2;
+            rp[7 + 3 * j] = w;
+            code |= (first ? 1u : 0u) << j;
+          }
+        }
+      }
+      rcode[lane] = code;
+    }
+    // --- halos of the plane (before any store of this plane) --------------
+    // Away from the domain faces they are plain loads of the current sweep;
+    // only tiles touching a face resolve images.
+    T L1[TT], L2[TT], B1[TT], B2[TT];
+    const int64_t Kp = g.Kpad;
+    T *hz = hc + (int64_t)(n1 * z) * n0 * Kp + kofs;  // plane z of the current sweep
+    const bool xin = xs - 2 * s[0] >= 0 && xs - 2 * s[0] < n0;
+    const bool yin = ys - 2 * s[1] >= 0 && ys - 2 * s[1] < n1;
+#pragma unroll
+    for (int k = 0; k < TT; ++k) {
+      L1[k] = L2[k] = B1[k] = B2[k] = T(0);
+      if (k < cnt[1]) {
+        const int y = ys + k * s[1];
+        if (xin) {
+          L1[k] = hz[(int64_t)(y * n0 + xs - s[0]) * Kp];
+          L2[k] = hz[(int64_t)(y * n0 + xs - 2 * s[0]) * Kp];
+        } else {
+          L1[k] = upstream_fluid(g, hc, hp, 0, xs - s[0], y, z, kofs, kmir[0]);
+          L2[k] = upstream_fluid(g, hc, hp, 0, xs - 2 * s[0], y, z, kofs, kmir[0]);
+        }
+      }
+      if (k < cnt[0]) {
+        const int x = xs + k * s[0];
+        if (yin) {
+          B1[k] = hz[(int64_t)((ys - s[1]) * n0 + x) * Kp];
+          B2[k] = hz[(int64_t)((ys - 2 * s[1]) * n0 + x) * Kp];
+        } else {
+          B1[k] = upstream_fluid(g, hc, hp, 1, x, ys - s[1], z, kofs, kmir[1]);
+          B2[k] = upstream_fluid(g, hc, hp, 1, x, ys - 2 * s[1], z, kofs, kmir[1]);
+        }
+      }
+    }
+    const bool zin = DIM == 3 && z - 2 * s[2] >= 0 && z - 2 * s[2] < g.n[2];
+    const int64_t zstep = (int64_t)n1 * n0 * Kp * s[2];
+    __syncthreads();
+    // --- the plane's anti-diagonals ---------------------------------------
+    T D1[TT], D2[TT];
+#pragma unroll
+    for (int k = 0; k < TT; ++k) D1[k] = D2[k] = T(0);
+#pragma unroll
+    for (int d = 0; d < 2 * TT - 1; ++d) {
+      T Nw[TT];
+      T Z1[TT], Z2[TT];
+#pragma unroll
+      for (int r = 0; r < TT; ++r) {
+        Nw[r] = T(0);
+        Z1[r] = Z2[r] = T(0);
+        const int i = d - r;
+        if (DIM == 3 && i >= 0 && i < TT && i < cnt[0] && r < cnt[1]) {
+          const int x = xs + i * s[0], y = ys + r * s[1];
+          if (zin) {
+            const T *hv0 = hz + (int64_t)(y * n0 + x) * Kp;
+            Z1[r] = hv0[-zstep];
+            Z2[r] = hv0[-2 * zstep];
+          } else {
+            Z1[r] = upstream_fluid(g, hc, hp, 2, x, y, z - s[2], kofs, kmir[2]);
+            Z2[r] = upstream_fluid(g, hc, hp, 2, x, y, z - 2 * s[2], kofs, kmir[2]);
+          }
+        }
+      }
+#pragma unroll
+      for (int r = 0; r < TT; ++r) {
+        const int i = d - r;
+        if (i < 0 || i >= TT) continue;
+        const uint32_t code = __builtin_amdgcn_readfirstlane(rcode[i + TT * r]);
+        if (code & R_SKIP) continue;
+        const T *rp = rec + (i + TT * r) * RW;
+        T num = fma(rp[1], vv[0], rp[0]);
+        num = fma(rp[2], vv[1], num);
+        if (DIM == 3) num = fma(rp[3], vv[2], num);
+        if (g.tau_fb) num = fma(rp[4], vsqm, num);
+        const T x1a = i >= 1 ? D1[r] : L1[r];
+        const T x1b = i >= 2 ? D2[r] : (i == 1 ? L1[r] : L2[r]);
+        const T x2a = r >= 1 ? D1[r >= 1 ? r - 1 : 0] : B1[i];
+        const T x2b = r >= 2 ? D2[r >= 2 ? r - 2 : 0] : (r == 1 ? B1[i] : B2[i]);
+        num = fma(aa[0], fma(rp[5], x1a, fma(rp[6], x1b, rp[7])), num);
+        num = fma(aa[1], fma(rp[8], x2a, fma(rp[9], x2b, rp[10])), num);
+        if (DIM == 3) num = fma(aa[2], fma(rp[11], Z1[r], fma(rp[12], Z2[r], rp[13])), num);
+        const T hv = num * rd_lds[(code & 7u) * kWave + lane];
+        Nw[r] = hv;
+        const int x = xs + i * s[0], y = ys + r * s[1];
+        if (active) hz[(int64_t)(y * n0 + x) * Kp] = hv;
+      }
+#pragma unroll
+      for (int r = 0; r < TT; ++r) {
+        D2[r] = D1[r];
+        D1[r] = Nw[r];
+      }
+    }
+    __syncthreads();  // the next plane's staging overwrites the records
+  }
+}
+
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+  for (int m = 32; m >= 1; m >>= 1) v += __shfl_xor(v, m, kWave);
+  return v;
+}
+
+// Steps (ii)-(iii). One wavefront per fluid voxel at a time: lane l owns the
+// octant slots q = l + 64 m (m < NS) of every octant, keeps their quadrature
+// weights in registers, and accumulates rho and the half-fluxes; the loads of
+// a voxel's whole distribution are independent, so they are all in flight
+// together. Slots past the octant size load nothing and weigh 0.
+template <typename T, int DIM, int NS>
+__global__ void __launch_bounds__(kMomBlock) moments_kernel(Geo<T> g) {
+  const Ctl *ctl = g.ctl;
+  if (ctl->stop) return;
+  const int par = ctl->par, np = par ^ 1;
+  const T *h = g.h[np];
+  const double *uold = g.u[par];
+  double *rho_n = g.rho[np];
+  double *u_n = g.u[np];
+  T *src_n = g.src[np];
+  T *wall_n = g.wall[np];
+  const int lane = threadIdx.x & (kWave - 1), wid = threadIdx.x / kWave;
+  constexpr int WPB = kMomBlock / kWave;
+  const int64_t nw = (int64_t)gridDim.x * WPB;
+  double wr[NS][2 + DIM];
+  bool ok[NS];
+#pragma unroll
+  for (int m = 0; m < NS; ++m) {
+    const int q = lane + m * kWave;
+    ok[m] = q < g.Ko;
+#pragma unroll
+    for (int r = 0; r < 2 + DIM; ++r) wr[m][r] = ok[m] ? g.wq[r * g.Ko_pad + q] : 0.0;
+  }
+  double mdu = 0, mu = 0, su = 0;
+  for (int64_t c = (int64_t)blockIdx.x * WPB + wid; c < g.N; c += nw) {
+    if (g.flags[c] & F_SOLID) continue;
+    const T *hc = h + c * g.Kpad + lane;
+    T hv[1 << DIM][NS];
+#pragma unroll
+    for (int o = 0; o < (1 << DIM); ++o)
+#pragma unroll
+      for (int m = 0; m < NS; ++m) hv[o][m] = ok[m] ? hc[o * g.Ko_pad + m * kWave] : T(0);
+    double r = 0, e = 0;
+    double ph[3][2] = {{0, 0}, {0, 0}, {0, 0}};
+#pragma unroll
+    for (int o = 0; o < (1 << DIM); ++o) {
+      double pj[3] = {0, 0, 0};
+#pragma unroll
+      for (int m = 0; m < NS; ++m) {
+        const double x = (double)hv[o][m];
+        r = fma(wr[m][0], x, r);
+#pragma unroll
+        for (int j = 0; j < DIM; ++j) pj[j] = fma(wr[m][1 + j], x, pj[j]);
+        if (g.tau_fb) e = fma(wr[m][1 + DIM], x, e);
+      }
+#pragma unroll
+      for (int j = 0; j < DIM; ++j) ph[j][(o >> j) & 1] += pj[j];
+    }
+    r = wave_sum(r);
+#pragma unroll
+    for (int j = 0; j < DIM; ++j) {
+      ph[j][0] = wave_sum(ph[j][0]);
+      ph[j][1] = wave_sum(ph[j][1]);
+    }
+    if (g.tau_fb) e = wave_sum(e);
+    if (lane == 0) {
+      rho_n[c] = r;
+      T *sp = src_n + c * kSrcStride;
+      sp[0] = T(g.nu * r);
+#pragma unroll
+      for (int j = 0; j < DIM; ++j) {
+        const double uj = ph[j][0] - ph[j][1];
+        mdu = fmax(mdu, fabs(uj - uold[j * g.N + c]));
+        mu = fmax(mu, fabs(uj));
+        u_n[j * g.N + c] = uj;
+        sp[1 + j] = T(2.0 * g.nu * uj);
+        wall_n[c * 6 + 2 * j] = T(ph[j][0] / g.D[j]);
+        wall_n[c * 6 + 2 * j + 1] = T(ph[j][1] / g.D[j]);
+      }
+      if (g.tau_fb) g.srct[np][c] = T(g.nu * ((2.0 / 3.0) * e - r));
+      su += ph[0][0] - ph[0][1];
+    }
+  }
+  __shared__ double sh[WPB][3];
+  if (lane == 0) {
+    sh[wid][0] = mdu;
+    sh[wid][1] = mu;
+    sh[wid][2] = su;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double a = 0, b = 0, cc = 0;
+    for (int w = 0; w < WPB; ++w) {
+      a = fmax(a, sh[w][0]);
+      b = fmax(b, sh[w][1]);
+      cc += sh[w][2];
+    }
+    g.part[blockIdx.x * 4 + 0] = a;
+    g.part[blockIdx.x * 4 + 1] = b;
+    g.part[blockIdx.x * 4 + 2] = cc;
+  }
+}
+
+__global__ void __launch_bounds__(256) reduce_kernel(Ctl *ctl, const double *part, int nblocks, int64_t N) {
+  if (ctl->stop) return;
+  __shared__ double sa[256], sb[256], sc[256];
+  const int t = threadIdx.x;
+  double a = 0, b = 0, c = 0;
+  for (int i = t; i < nblocks; i += 256) {
+    a = fmax(a, part[i * 4 + 0]);
+    b = fmax(b, part[i * 4 + 1]);
+    c += part[i * 4 + 2];
+  }
+  sa[t] = a;
+  sb[t] = b;
+  sc[t] = c;
+  __syncthreads();
+  for (int w = 128; w >= 1; w >>= 1) {
+    if (t < w) {
+      sa[t] = fmax(sa[t], sa[t + w]);
+      sb[t] = fmax(sb[t], sb[t + w]);
+      sc[t] += sc[t + w];
+    }
+    __syncthreads();
+  }
+  if (t != 0) return;
+  const double maxdu = sa[0], maxu = sb[0];
+  const double r = maxu > 0 ? maxdu / maxu : maxdu;
+  const double gp = sc[0] / (double)N;
+  const double k = ctl->kn_coef * gp;
+  if (!isfinite(r) || !isfinite(k) || !isfinite(maxu)) {
+    ctl->status = -4;  // keep `par`: the previous iterate stays the state
+    ctl->stop = 1;
+    return;
+  }
+  const int64_t it = ctl->iter + 1;
+  ctl->iter = it;
+  ctl->par ^= 1;
+  ctl->r = r;
+  ctl->gp = gp;
+  ctl->k = k;
+  if (it % 100 == 0) {
+    const int64_t m = it / 100;
+    ctl->kring[m % kRing] = k;
+    if (m >= 2 && k != 0.0) ctl->err = fabs((k - ctl->kring[(m - 1) % kRing]) / k) / 100.0;
+  }
+  if (ctl->tol > 0) {
+    if (ctl->mode == 0 && r <= ctl->tol) { ctl->status = 1; ctl->stop = 1; }
+    if (ctl->mode == 1 && it % 100 == 0 && ctl->err >= 0 && ctl->err < ctl->tol) {
+      ctl->status = 1;
+      ctl->stop = 1;
+    }
+  }
+  if (!ctl->stop && it >= ctl->iter_limit) {
+    ctl->status = 2;
+    ctl->stop = 1;
+  }
+}
+
+__global__ void arm_kernel(Ctl *ctl, double tol, int mode, int64_t max_iters) {
+  ctl->tol = tol;
+  ctl->mode = mode;
+  ctl->iter_limit = ctl->iter + max_iters;
+  ctl->status = 0;
+  ctl->stop = max_iters > 0 ? 0 : 1;
+}
+
+// Local linearised equilibrium of given fields (moments of the current state
+// and the previous-iteration distribution that the boundaries read).
+template <typename T, int DIM>
+__global__ void init_moments_kernel(Geo<T> g, const double *rho, const double *u) {
+  const int par = g.ctl->par;
+  for (int64_t c = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; c < g.N; c += (int64_t)gridDim.x * blockDim.x) {
+    const bool fl = !(g.flags[c] & F_SOLID);
+    const double r = (fl && rho) ? rho[c] : 0.0;
+    g.rho[par][c] = r;
+    T *sp = g.src[par] + c * kSrcStride;
+    for (int i = 0; i < kSrcStride; ++i) sp[i] = T(0);
+    sp[0] = T(g.nu * r);
+    g.srct[par][c] = T(0);
+    for (int j = 0; j < 3; ++j) {
+      const double uj = (fl && u && j < DIM) ? u[j * g.N + c] : 0.0;
+      if (j < DIM) {
+        g.u[par][j * g.N + c] = uj;
+        sp[1 + j] = T(2.0 * g.nu * uj);
+        // Phi_j^+- = rho D_j +- u_j / 2 for h = rho + 2 u.v
+        g.wall[par][c * 6 + 2 * j] = T((r * g.D[j] + 0.5 * uj) / g.D[j]);
+        g.wall[par][c * 6 + 2 * j + 1] = T((r * g.D[j] - 0.5 * uj) / g.D[j]);
+      } else {
+        g.wall[par][c * 6 + 2 * j] = T(0);
+        g.wall[par][c * 6 + 2 * j + 1] = T(0);
+      }
+    }
+  }
+}
+
+template <typename T, int DIM>
+__global__ void init_h_kernel(Geo<T> g, const double *rho, const double *u) {
+  const int par = g.ctl->par;
+  const int64_t total = g.N * g.Kpad;
+  for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < total; e += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t c = e / g.Kpad;
+    const int k = (int)(e - c * g.Kpad);
+    const int o = k / g.Ko_pad, q = k - o * g.Ko_pad;
+    double v = 0.0;
+    if (q < g.Ko && !(g.flags[c] & F_SOLID)) {
+      v = rho ? rho[c] : 0.0;
+      if (u)
+        for (int j = 0; j < DIM; ++j) {
+          const double vj = ((o >> j) & 1) ? -(double)g.absv[j * g.Ko_pad + q] : (double)g.absv[j * g.Ko_pad + q];
+          v += 2.0 * u[j * g.N + c] * vj;
+        }
+    }
+    g.h[par][e] = T(v);
+  }
+}
+
+// Temperature and heat-flux diagnostics from the stored distribution.
+template <typename T, int DIM>
+__global__ void __launch_bounds__(kMomBlock) diagnostics_kernel(Geo<T> g, double *tau, double *qf) {
+  const int par = g.ctl->par;
+  const T *h = g.h[par];
+  const int lane = threadIdx.x & (kWave - 1), wid = threadIdx.x / kWave;
+  constexpr int WPB = kMomBlock / kWave;
+  for (int64_t c = (int64_t)blockIdx.x * WPB + wid; c < g.N; c += (int64_t)gridDim.x * WPB) {
+    if (g.flags[c] & F_SOLID) {
+      if (lane == 0) {
+        tau[c] = 0;
+        for (int j = 0; j < DIM; ++j) qf[j * g.N + c] = 0;
+      }
+      continue;
+    }
+    double e = 0, r = 0, qq[3] = {0, 0, 0};
+    for (int o = 0; o < (1 << DIM); ++o)
+      for (int q = lane; q < g.Ko; q += kWave) {
+        const double hv = (double)h[c * g.Kpad + o * g.Ko_pad + q];
+        const double w = g.wq[q];
+        double vsq = DIM == 2 ? 0.5 : 0.0;
+        double vj[3];
+        for (int j = 0; j < DIM; ++j) {
+          const double a = (double)g.absv[j * g.Ko_pad + q];
+          vj[j] = ((o >> j) & 1) ? -a : a;
+          vsq += a * a;
+        }
+        r += w * hv;
+        e += w * vsq * hv;
+        for (int j = 0; j < DIM; ++j) qq[j] += w * vj[j] * (vsq - 2.5) * hv;
+      }
+    r = wave_sum(r);
+    e = wave_sum(e);
+    for (int j = 0; j < DIM; ++j) qq[j] = wave_sum(qq[j]);
+    if (lane == 0) {
+      tau[c] = (2.0 / 3.0) * e - r;
+      for (int j = 0; j < DIM; ++j) qf[j * g.N + c] = qq[j];
+    }
+  }
+}
+
+// Copy one boundary layer (all voxels whose coordinate along `axis` is r) of
+// the current distribution to / from a packed buffer (checkpointing).
+template <typename T>
+__global__ void face_copy_kernel(Geo<T> g, int axis, int r, T *buf, int to_buf) {
+  const int par = g.ctl->par;
+  T *h = g.h[par];
+  const int64_t faces = g.N / g.n[axis];
+  const int64_t total = faces * g.Kpad;
+  for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < total; e += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t f = e / g.Kpad;
+    const int k = (int)(e - f * g.Kpad);
+    int x[3];
+    if (axis == 0) { x[0] = r; x[1] = (int)(f % g.n[1]); x[2] = (int)(f / g.n[1]); }
+    else if (axis == 1) { x[1] = r; x[0] = (int)(f % g.n[0]); x[2] = (int)(f / g.n[0]); }
+    else { x[2] = r; x[0] = (int)(f % g.n[0]); x[1] = (int)(f / g.n[0]); }
+    const int64_t c = cell_of(g, x[0], x[1], x[2]);
+    if (to_buf) buf[e] = h[c * g.Kpad + k];
+    else h[c * g.Kpad + k] = buf[e];
+  }
+}
+
+int grid_for(int64_t work, int block) {
+  int64_t b = (work + block - 1) / block;
+  if (b > 65536) b = 65536;
+  return (int)(b < 1 ? 1 : b);
+}
+
+}  // namespace
+
+template <typename T, bool Y2WALL>
+void launch_sweep_rule(const Geo<T> &g, int diag, int items, hipStream_t st) {
+#define PDVM_SWEEP(D, X)                                                                              \
+  hipLaunchKernelGGL((sweep_kernel<T, D, X, Y2WALL>), dim3(items), dim3(kWave), 0, st, g, diag,     \
+                     g.flags, (const T *)g.src[0], (const T *)g.src[1], (const T *)g.srct[0],       \
+                     (const T *)g.srct[1], (const T *)g.wall[0], (const T *)g.wall[1], g.h[0],      \
+                     g.h[1])
+  if (g.dim == 2) {
+    if (g.tile[0] <= 4) PDVM_SWEEP(2, 4);
+    else PDVM_SWEEP(2, 8);
+  } else {
+    if (g.tile[0] <= 4) PDVM_SWEEP(3, 4);
+    else PDVM_SWEEP(3, 8);
+  }
+#undef PDVM_SWEEP
+}
+
+template <typename T>
+hipError_t launch_sweep(const Geo<T> &g, int diag, int items, hipStream_t st) {
+  if (g.y2wall) launch_sweep_rule<T, true>(g, diag, items, st);
+  else launch_sweep_rule<T, false>(g, diag, items, st);
+  return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_moments(const Geo<T> &g, hipStream_t st) {
+  const int ns = (g.Ko + kWave - 1) / kWave;
+#define PDVM_MOM(D, S) hipLaunchKernelGGL((moments_kernel<T, D, S>), dim3(g.mom_blocks), dim3(kMomBlock), 0, st, g)
+  if (g.dim == 2) {
+    if (ns <= 1) PDVM_MOM(2, 1);
+    else if (ns <= 2) PDVM_MOM(2, 2);
+    else if (ns <= 3) PDVM_MOM(2, 3);
+    else if (ns <= 4) PDVM_MOM(2, 4);
+    else if (ns <= 8) PDVM_MOM(2, 8);
+    else PDVM_MOM(2, 16);
+  } else {
+    if (ns <= 1) PDVM_MOM(3, 1);
+    else if (ns <= 2) PDVM_MOM(3, 2);
+    else if (ns <= 4) PDVM_MOM(3, 4);
+    else if (ns <= 8) PDVM_MOM(3, 8);
+    else PDVM_MOM(3, 16);
+  }
+#undef PDVM_MOM
+  return hipGetLastError();
+}
+
+hipError_t launch_reduce(Ctl *ctl, const double *part, int nblocks, int64_t N, hipStream_t st) {
+  hipLaunchKernelGGL(reduce_kernel, dim3(1), dim3(256), 0, st, ctl, part, nblocks, N);
+  return hipGetLastError();
+}
+
+hipError_t launch_arm(Ctl *ctl, double tol, int mode, int64_t max_iters, hipStream_t st) {
+  hipLaunchKernelGGL(arm_kernel, dim3(1), dim3(1), 0, st, ctl, tol, mode, max_iters);
+  return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_init_state(const Geo<T> &g, const double *rho, const double *u, hipStream_t st) {
+  const int gm = grid_for(g.N, 256), gh = grid_for(g.N * g.Kpad, 256);
+  if (g.dim == 2) {
+    hipLaunchKernelGGL((init_moments_kernel<T, 2>), dim3(gm), dim3(256), 0, st, g, rho, u);
+    hipLaunchKernelGGL((init_h_kernel<T, 2>), dim3(gh), dim3(256), 0, st, g, rho, u);
+  } else {
+    hipLaunchKernelGGL((init_moments_kernel<T, 3>), dim3(gm), dim3(256), 0, st, g, rho, u);
+    hipLaunchKernelGGL((init_h_kernel<T, 3>), dim3(gh), dim3(256), 0, st, g, rho, u);
+  }
+  return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_diagnostics(const Geo<T> &g, double *tau, double *q, hipStream_t st) {
+  const int grid = grid_for(g.N, kMomBlock / kWave);
+  if (g.dim == 2) hipLaunchKernelGGL((diagnostics_kernel<T, 2>), dim3(grid), dim3(kMomBlock), 0, st, g, tau, q);
+  else hipLaunchKernelGGL((diagnostics_kernel<T, 3>), dim3(grid), dim3(kMomBlock), 0, st, g, tau, q);
+  return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_face_copy(const Geo<T> &g, int axis, int r, T *buf, int to_buf, hipStream_t st) {
+  const int grid = grid_for(g.N / g.n[axis] * g.Kpad, 256);
+  hipLaunchKernelGGL((face_copy_kernel<T>), dim3(grid), dim3(256), 0, st, g, axis, r, buf, to_buf);
+  return hipGetLastError();
+}
+
+template hipError_t launch_sweep<double>(const Geo<double> &, int, int, hipStream_t);
+template hipError_t launch_sweep<float>(const Geo<float> &, int, int, hipStream_t);
+template hipError_t launch_moments<double>(const Geo<double> &, hipStream_t);
+template hipError_t launch_moments<float>(const Geo<float> &, hipStream_t);
+template hipError_t launch_init_state<double>(const Geo<double> &, const double *, const double *, hipStream_t);
+template hipError_t launch_init_state<float>(const Geo<float> &, const double *, const double *, hipStream_t);
+template hipError_t launch_diagnostics<double>(const Geo<double> &, double *, double *, hipStream_t);
+template hipError_t launch_diagnostics<float>(const Geo<float> &, double *, double *, hipStream_t);
+template hipError_t launch_face_copy<double>(const Geo<double> &, int, int, double *, int, hipStream_t);
+template hipError_t launch_face_copy<float>(const Geo<float> &, int, int, float *, int, hipStream_t);
+
+}  // namespace pdvm

@@ -11,3 +11,19 @@ if ROOT not in sys.path:
 def pytest_configure(config):
     config.addinivalue_line("markers", "gpu: needs an MI355X (gfx950) GPU and the built HIP library")
     config.addinivalue_line("markers", "slow: long-running CPU test")
+
+
+def _gpu_available():
+    try:
+        import torch
+        return torch.cuda.is_available()
+    except Exception:
+        return False
+
+
+def pytest_collection_modifyitems(config, items):
+    if any(item.get_closest_marker("gpu") for item in items) and not _gpu_available():
+        skip = pytest.mark.skip(reason="needs a GPU (run with -m gpu on an MI355X)")
+        for item in items:
+            if item.get_closest_marker("gpu"):
+                item.add_marker(skip)
