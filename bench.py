@@ -1,18 +1,20 @@
 #!/usr/bin/env python3
 """Benchmark of the DVM/BGK iteration on one MI355X.
 
-Workload: 2D synthetic digital rock, 512 x 512 voxels of seeded overlapping
-discs (radii U(4, 20) px, porosity 0.40, pore space percolating along x1),
-Kn = 1 (L = 512 voxels), 32 x 32 half-range Gauss-Hermite velocities, specular
-lateral faces, pressure jump 1. A step is one full iteration of the hot path:
-the upwind sweep of every discrete velocity, the moment / source / wall-density
-kernel and the FP64 residual and permeability reduction.
+Workload (the `value` line): 2D synthetic digital rock, 512 x 512 voxels of
+seeded overlapping discs (radii U(4, 20) px, porosity 0.40, pore space
+percolating along x1), Kn = 1 (L = 512 voxels), 32 x 32 half-range
+Gauss-Hermite velocities, specular lateral faces, pressure jump 1, FP64.
+A step is one full iteration of the hot path: the upwind sweep of every
+discrete velocity, the moment / source / wall-density kernel and the FP64
+residual and permeability reduction.
 
-Prints one JSON line: cell-velocity updates per second (fluid voxels x
+Prints one JSON line with cell-velocity updates per second (fluid voxels x
 velocities x iterations / wall time, inputs resident in HBM), the roofline of
-the dominant kernel (the sweep) from HIP-event timings, the CPU oracle timed on
-a bounded sample of the same workload, and time-to-residual 1e-6 for the FP64
-form and the FP32 form.
+the dominant kernel (the sweep) from HIP-event timings on the solver's stream,
+the CPU oracle timed on a bounded sample of the same workload, and extra
+fields: the FP32 form, the 3D pack (96^3, 16^3 velocities, FP32), the
+64-problem batch (24 x 24 velocities, FP32) and time-to-residual 1e-6.
 """
 import argparse
 import json
@@ -49,19 +51,44 @@ def cpu_baseline(mask, nv, kn, target_s=15.0):
     o.close()
     return {"value": fluid * K * more / dt, "unit": "cell-velocity updates/s", "cores": threads,
             "kind": "oracle",
-            "sample": "%d iterations of the same 512x512 workload after 1 untimed iteration "
-                      "(%.1f s of CPU work)" % (more, dt)}
+            "sample": "%d iterations of the same 512x512 rock (Kn=1, 32x32 velocities) after one "
+                      "untimed iteration, %.1f s of CPU work" % (more, dt)}
+
+
+def timed_updates(solver, fluid, K, steps, warmup):
+    import torch
+    solver.iterate(warmup)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    r = solver.iterate(steps)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    assert r["iters"] == steps, r
+    return fluid * K * steps / dt, dt
+
+
+def roofline(tm, elem):
+    """Sweep kernel: algorithmic bytes = h written once per fluid voxel and
+    velocity; per launch = that over the launches of one iteration."""
+    per_iter = elem * tm["fluid_cells"] * tm["velocities"]
+    per_launch = per_iter / tm["sweep_launches_per_iter"]
+    achieved = per_launch / (tm["sweep_ms_per_launch"] * 1e-3) / 1e9
+    return {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": achieved / HBM_PEAK_GBS, "traffic": None, "kernel": "sweep_kernel",
+            "bytes_per_launch": per_launch, "launch_ms": tm["sweep_ms_per_launch"],
+            "launches_per_iter": tm["sweep_launches_per_iter"],
+            "moments_kernel": {"bytes_per_launch": per_iter, "launch_ms": tm["moments_ms_per_launch"],
+                               "achieved_gbs": per_iter / (tm["moments_ms_per_launch"] * 1e-3) / 1e9}}
 
 
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=300)
-    ap.add_argument("--warmup", type=int, default=30)
-    ap.add_argument("--precision", default="fp64", choices=["fp64", "fp32"])
+    ap.add_argument("--steps", type=int, default=200)
+    ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--kn", type=float, default=1.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--no-ttr", action="store_true")
+    ap.add_argument("--no-extra", action="store_true", help="only the 512^2 FP64 line")
     ap.add_argument("--tile", type=int, nargs="*", default=None)
     args = ap.parse_args()
     if args.gpus != 1:
@@ -69,7 +96,6 @@ def main():
               "(--gpus %d requested)" % args.gpus, file=sys.stderr)
         sys.exit(2)
 
-    import numpy as np
     import torch
     from paper_1712_01132_amd import geometry, poredvm
 
@@ -81,30 +107,15 @@ def main():
     K = nv[0] * nv[1]
     log("porosity %.4f, fluid voxels %d, velocities %d" % (1 - mask.mean(), fluid, K))
 
-    s = poredvm.Solver(mask, nv, args.kn, precision=args.precision, tile=args.tile)
-    s.iterate(args.warmup)
-    torch.cuda.synchronize()
-    log("warmup done (%d iterations)" % args.warmup)
-    t0 = time.perf_counter()
-    r = s.iterate(args.steps)
-    torch.cuda.synchronize()
-    dt = time.perf_counter() - t0
-    assert r["iters"] == args.steps, r
-    ups = fluid * K * args.steps / dt
-    log("timed %d iterations: %.3f ms/iter, %.3e updates/s" % (args.steps, 1e3 * dt / args.steps, ups))
-
+    s = poredvm.Solver(mask, nv, args.kn, precision="fp64", tile=args.tile)
+    ups, dt = timed_updates(s, fluid, K, args.steps, args.warmup)
+    log("FP64: %d iterations in %.3f s: %.3f ms/iter, %.3e updates/s" % (args.steps, dt, 1e3 * dt / args.steps, ups))
     tm = s.time_kernels(10)
-    es = 8 if args.precision == "fp64" else 4
-    sweep_bytes = es * fluid * K  # h written once per fluid voxel and velocity
-    per_launch_bytes = sweep_bytes / tm["sweep_launches_per_iter"]
-    per_launch_s = tm["sweep_ms_per_launch"] * 1e-3
-    achieved = per_launch_bytes / per_launch_s / 1e9
-    log("kernel timing: %s" % json.dumps(tm))
-    mom_gbs = sweep_bytes / (tm["moments_ms_per_launch"] * 1e-3) / 1e9
+    log("FP64 kernel timing: %s" % json.dumps(tm))
     s.close()
 
     out = {
-        "metric": "cell-velocity updates/s (time-to-residual 1e-6 reported alongside)",
+        "metric": "cell-velocity updates/s (time-to-residual 1e-6 alongside)",
         "value": ups,
         "unit": "cell-velocity updates/s",
         "n_gpus": 1,
@@ -114,35 +125,69 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f64" if args.precision == "fp64" else "f32",
+        "dtype": "f64",
         "data": "synthetic",
-        "config": {"workload": "rock2d: 512x512 seeded overlapping discs r~U(4,20), porosity 0.40, "
-                               "Kn=%g, 32x32 half-range Gauss-Hermite velocities, %s sweep" % (args.kn, args.precision),
+        "config": {"workload": "rock2d: 512x512 seeded overlapping discs r~U(4,20), porosity 0.40, Kn=%g, "
+                               "32x32 half-range Gauss-Hermite velocities, FP64" % args.kn,
                    "fluid_voxels": fluid, "velocities": K, "parallelism": "1 GPU"},
-        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": None,
-                     "kernel": "sweep_kernel", "bytes_per_launch": per_launch_bytes,
-                     "launch_ms": tm["sweep_ms_per_launch"],
-                     "launches_per_iter": tm["sweep_launches_per_iter"],
-                     "moments_kernel_gbs": mom_gbs},
+        "roofline": roofline(tm, 8),
     }
-    if not args.no_ttr:
+    if not args.no_extra:
+        extra = {}
+        s = poredvm.Solver(mask, nv, args.kn, precision="fp32", tile=args.tile)
+        u32, d32 = timed_updates(s, fluid, K, args.steps, args.warmup)
+        t32 = s.time_kernels(10)
+        s.close()
+        extra["rock2d_fp32"] = {"updates_per_s": u32, "ms_per_step": 1e3 * d32 / args.steps,
+                                "roofline": roofline(t32, 4)}
+        log("FP32: %.3e updates/s" % u32)
+        # time to residual 1e-6 (cold start), FP64 and FP32
         ttr = {}
         for prec in ("fp64", "fp32"):
             s = poredvm.Solver(mask, nv, args.kn, precision=prec, tile=args.tile)
             torch.cuda.synchronize()
             t0 = time.perf_counter()
-            rr = s.iterate(20000, 1e-6)
+            rr = s.iterate(5000, 1e-6)
             torch.cuda.synchronize()
             ttr[prec] = {"seconds": time.perf_counter() - t0, "iterations": rr["iters"], "k": rr["k"],
                          "converged": rr["converged"]}
             s.close()
             log("time to r<=1e-6 (%s): %s" % (prec, json.dumps(ttr[prec])))
         ttr["k_rel_diff_fp32_vs_fp64"] = abs(ttr["fp32"]["k"] - ttr["fp64"]["k"]) / abs(ttr["fp64"]["k"])
-        out["time_to_residual_1e-6"] = ttr
+        extra["rock2d_time_to_residual_1e-6"] = ttr
+        # 3D pack
+        log("generating the 96^3 sphere pack (seed 7)")
+        m3 = geometry.workload_pack3d(seed=7)
+        f3 = int((m3 == 0).sum())
+        s = poredvm.Solver(m3, [16, 16, 16], 0.5, precision="fp32", tile=[4, 4, 4])
+        u3, d3 = timed_updates(s, f3, 4096, 20, 3)
+        t3 = s.time_kernels(3)
+        s.close()
+        extra["pack3d_fp32"] = {"updates_per_s": u3, "ms_per_step": 1e3 * d3 / 20, "fluid_voxels": f3,
+                                "velocities": 4096, "roofline": roofline(t3, 4)}
+        log("3D pack FP32: %.3e updates/s, %s" % (u3, json.dumps(t3)))
+        # 64-problem batch
+        log("generating the 64-problem batch")
+        probs = geometry.workload_batch(64)
+        fb = sum(int((m == 0).sum()) for m, _ in probs)
+        b = poredvm.Batch(probs, [24, 24], precision="fp32", tile=[8, 8])
+        b.iterate(3)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        rb = b.iterate(30)
+        torch.cuda.synchronize()
+        db = time.perf_counter() - t0
+        tb = b.time_kernels(3)
+        b.close()
+        extra["batch64_fp32"] = {"updates_per_s": fb * 576 * 30 / db, "ms_per_step": 1e3 * db / 30,
+                                 "fluid_voxels": fb, "velocities": 576, "problems": 64,
+                                 "roofline": roofline(tb, 4)}
+        log("batch64 FP32: %.3e updates/s" % (fb * 576 * 30 / db))
+        out["extra"] = extra
     if not args.no_cpu_baseline:
         log("timing the CPU oracle on the same workload")
         out["cpu_baseline"] = cpu_baseline(mask, nv, args.kn)
+        log("CPU oracle: %s" % json.dumps(out["cpu_baseline"]))
     print(json.dumps(out), flush=True)
 
 

@@ -97,7 +97,7 @@ typedef struct {
 /* Half-range Gauss-Hermite velocity grid (Sec. 2.2): n_total/2 nodes of the
  * Gauss rule for exp(-x^2) on [0, inf), mirrored to both signs; weights
  * normalised to sum 1. nodes/weights: host arrays of n_total doubles (caller
- * owned). n_total even, 2..256. Returns PDVM_OK or PDVM_E_INVAL. */
+ * owned). n_total even, 2..64. Returns PDVM_OK or PDVM_E_INVAL. */
 int pdvm_halfrange_gh(int32_t n_total, double *nodes, double *weights);
 
 /* Device bytes the solver needs for cfg (0 if cfg is invalid). */
@@ -107,8 +107,9 @@ size_t pdvm_workspace_bytes(const pdvm_config *cfg);
  * percolation check along x1) and upload it (Sec. 2.3, pre-processing of the
  * (C0, C1, C2) choice). dev_workspace: NULL (the library allocates and frees)
  * or a device buffer of at least pdvm_workspace_bytes(cfg) bytes, owned by the
- * caller, that must outlive the solver. hip_stream: a hipStream_t or NULL (the
- * null stream). The initial state is rest (all perturbations zero).
+ * caller, that must outlive the solver (the library still allocates a few KB
+ * of launch tables). hip_stream: a hipStream_t, or NULL for a private stream
+ * of the library. The initial state is rest (all perturbations zero).
  * PDVM_E_INVAL if no pore component winds around x1. */
 int pdvm_create(const pdvm_config *cfg, void *dev_workspace, size_t ws_bytes,
                 void *hip_stream, pdvm_solver **out);
@@ -156,6 +157,27 @@ typedef struct {
   double fluid_cells, velocities;
 } pdvm_timing;
 int pdvm_time_kernels(pdvm_solver *s, int32_t iters, pdvm_timing *out);
+
+/* ---- Batches ------------------------------------------------------------
+ * Many problems (geometries of uneven size, Kn values, jumps, lateral
+ * conditions) iterated together: each iteration is one replay of a HIP graph
+ * whose sweep launches cover the tiles of every problem on a tile diagonal,
+ * followed by one moment launch and one reduction launch over all problems.
+ * Problems that reach their stop condition retire: their kernels return at
+ * once while the others continue. All configs of a batch share dim,
+ * precision, velocity grid, stencil rule and tau feedback (else
+ * PDVM_E_INVAL); the library allocates each problem's workspace.
+ * The single-problem calls above need a solver of one problem; a batch of
+ * one is an ordinary solver. */
+int pdvm_batch_create(int32_t n, const pdvm_config *cfgs, void *hip_stream, pdvm_solver **out);
+int32_t pdvm_batch_size(const pdvm_solver *s);
+int pdvm_batch_set_initial(pdvm_solver *s, int32_t i, const double *rho, const double *u);
+/* out: n entries (NULL allowed). Returns PDVM_OK when every problem met the
+ * tolerance, PDVM_NOT_CONVERGED if any did not, PDVM_E_NONFINITE if any
+ * diverged (its previous state is kept). */
+int pdvm_batch_iterate(pdvm_solver *s, int64_t max_iters, double tol, int32_t stop_mode, pdvm_stats *out);
+int pdvm_batch_get_moments(pdvm_solver *s, int32_t i, double *rho, double *u, double *tau, double *q);
+int pdvm_batch_get_flux(pdvm_solver *s, int32_t i, double *gp, double *k, double *gp_section);
 
 void pdvm_destroy(pdvm_solver *s);
 

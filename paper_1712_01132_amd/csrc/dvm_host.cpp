@@ -430,159 +430,7 @@ size_t layout_bytes(const Problem &P) {
   return P.precision == PDVM_FP64 ? make_layout<double>(P).total : make_layout<float>(P).total;
 }
 
-}  // namespace
-
-struct pdvm_solver {
-  Problem P;
-  hipStream_t stream = nullptr;
-  char *ws = nullptr;
-  bool own_ws = false;
-  size_t ws_bytes = 0;
-  Geo<double> gd{};
-  Geo<float> gf{};
-  double *scratch = nullptr;
-  Ctl *host_ctl = nullptr;   // pinned mirror of the control block
-  bool own_stream = false;
-  hipGraphExec_t graph = nullptr;
-  int graph_iters = 0;
-  std::string err;
-  int fail(int code, const char *fmt, ...) {
-    char buf[512];
-    va_list ap;
-    va_start(ap, fmt);
-    vsnprintf(buf, sizeof(buf), fmt, ap);
-    va_end(ap);
-    err = buf;
-    g_thread_error = buf;
-    return code;
-  }
-};
-
-#define HIPCHK(s, call)                                                              \
-  do {                                                                               \
-    hipError_t e_ = (call);                                                          \
-    if (e_ != hipSuccess) return (s)->fail(PDVM_E_HIP, "%s: %s", #call, hipGetErrorString(e_)); \
-  } while (0)
-
-namespace {
-
-template <typename T>
-Geo<T> &geo(pdvm_solver *s);
-template <>
-Geo<double> &geo<double>(pdvm_solver *s) { return s->gd; }
-template <>
-Geo<float> &geo<float>(pdvm_solver *s) { return s->gf; }
-
-template <typename T>
-int setup_device(pdvm_solver *s) {
-  const Problem &P = s->P;
-  const Layout<T> L = make_layout<T>(P);
-  Geo<T> &g = geo<T>(s);
-  char *b = s->ws;
-  g.dim = P.dim;
-  for (int a = 0; a < 3; ++a) { g.n[a] = P.n[a]; g.tile[a] = P.tile[a]; g.ntile[a] = P.ntile[a]; }
-  g.N = P.N;
-  g.Ko = P.Ko; g.Ko_pad = P.Ko_pad; g.Kpad = P.Kpad; g.ngroups = P.ngroups;
-  g.lateral_periodic = P.lateral_periodic;
-  g.tau_fb = P.tau_fb;
-  g.y2wall = P.stencil_rule == 0;
-  g.jump = T(P.jump);
-  g.nu = P.nu;
-  for (int j = 0; j < 3; ++j) g.D[j] = P.D[j] > 0 ? P.D[j] : 1.0;
-  g.ctl = (Ctl *)(b + L.ctl);
-  g.flags = (const uint32_t *)(b + L.flags);
-  g.absv = (const T *)(b + L.absv);
-  g.av = (const T *)(b + L.av);
-  g.vsqm = (const T *)(b + L.vsqm);
-  g.rden = (const T *)(b + L.rden);
-  g.wq = (const double *)(b + L.wq);
-  for (int k = 0; k < 2; ++k) {
-    g.h[k] = (T *)(b + L.h[k]);
-    g.src[k] = (T *)(b + L.src[k]);
-    g.srct[k] = (T *)(b + L.srct[k]);
-    g.wall[k] = (T *)(b + L.wall[k]);
-    g.rho[k] = (double *)(b + L.rho[k]);
-    g.u[k] = (double *)(b + L.u[k]);
-  }
-  g.part = (double *)(b + L.part);
-  g.mom_blocks = P.mom_blocks;
-  g.diag_tiles = (const int32_t *)(b + L.tiles);
-  g.diag_off = (const int32_t *)(b + L.offs);
-  g.ndiag = P.ndiag;
-  s->scratch = (double *)(b + L.scratch);
-
-  // tables in the sweep precision
-  std::vector<T> absv(P.absv.size()), av(P.absv.size()), vsqm(P.vsqm.size()), rden(P.rden.size());
-  for (size_t i = 0; i < absv.size(); ++i) { absv[i] = T(P.absv[i]); av[i] = T(P.absv[i] * P.n[0]); }
-  for (size_t i = 0; i < vsqm.size(); ++i) vsqm[i] = T(P.vsqm[i]);
-  for (size_t i = 0; i < rden.size(); ++i) rden[i] = T(P.rden[i]);
-  hipStream_t st = s->stream;
-  HIPCHK(s, hipMemsetAsync(b, 0, L.total, st));
-  HIPCHK(s, hipMemcpyAsync((void *)g.flags, P.flags.data(), P.flags.size() * 4, hipMemcpyHostToDevice, st));
-  HIPCHK(s, hipMemcpyAsync((void *)g.absv, absv.data(), absv.size() * sizeof(T), hipMemcpyHostToDevice, st));
-  HIPCHK(s, hipMemcpyAsync((void *)g.av, av.data(), av.size() * sizeof(T), hipMemcpyHostToDevice, st));
-  HIPCHK(s, hipMemcpyAsync((void *)g.vsqm, vsqm.data(), vsqm.size() * sizeof(T), hipMemcpyHostToDevice, st));
-  HIPCHK(s, hipMemcpyAsync((void *)g.rden, rden.data(), rden.size() * sizeof(T), hipMemcpyHostToDevice, st));
-  HIPCHK(s, hipMemcpyAsync((void *)g.wq, P.wq.data(), P.wq.size() * 8, hipMemcpyHostToDevice, st));
-  HIPCHK(s, hipMemcpyAsync((void *)g.diag_tiles, P.diag_tiles.data(), P.diag_tiles.size() * 4, hipMemcpyHostToDevice, st));
-  HIPCHK(s, hipMemcpyAsync((void *)g.diag_off, P.diag_off.data(), P.diag_off.size() * 4, hipMemcpyHostToDevice, st));
-  Ctl c{};
-  c.kn_coef = 2.0 / std::sqrt(M_PI) * (std::isinf(P.kn) ? 0.0 : P.kn);
-  c.err = -1.0;
-  c.stop = 1;
-  HIPCHK(s, hipMemcpyAsync(g.ctl, &c, sizeof(Ctl), hipMemcpyHostToDevice, st));
-  HIPCHK(s, hipStreamSynchronize(st));
-  return PDVM_OK;
-}
-
-template <typename T>
-int enqueue_iteration(pdvm_solver *s) {
-  const Geo<T> &g = geo<T>(s);
-  const int nsg = s->P.ngroups << s->P.dim;
-  for (int d = 0; d < s->P.ndiag; ++d) {
-    const int items = (s->P.diag_off[d + 1] - s->P.diag_off[d]) * nsg;
-    HIPCHK(s, launch_sweep<T>(g, d, items, s->stream));
-  }
-  HIPCHK(s, launch_moments<T>(g, s->stream));
-  HIPCHK(s, launch_reduce(g.ctl, g.part, g.mom_blocks, g.N, s->stream));
-  return PDVM_OK;
-}
-
-int enqueue_iteration_any(pdvm_solver *s) {
-  return s->P.precision == PDVM_FP64 ? enqueue_iteration<double>(s) : enqueue_iteration<float>(s);
-}
-
-Ctl *dev_ctl(pdvm_solver *s) { return s->P.precision == PDVM_FP64 ? s->gd.ctl : s->gf.ctl; }
-
-int build_graph(pdvm_solver *s) {
-  if (s->graph) return PDVM_OK;
-  // a few iterations per replay amortise the launch of the graph itself
-  const int per = std::max(1, std::min(8, s->P.check_every));
-  hipGraph_t gr;
-  HIPCHK(s, hipStreamBeginCapture(s->stream, hipStreamCaptureModeThreadLocal));
-  int rc = PDVM_OK;
-  for (int i = 0; i < per && rc == PDVM_OK; ++i) rc = enqueue_iteration_any(s);
-  hipError_t e = hipStreamEndCapture(s->stream, &gr);
-  if (rc != PDVM_OK) return rc;
-  if (e != hipSuccess) return s->fail(PDVM_E_HIP, "graph capture: %s", hipGetErrorString(e));
-  e = hipGraphInstantiate(&s->graph, gr, nullptr, nullptr, 0);
-  (void)hipGraphDestroy(gr);
-  if (e != hipSuccess) return s->fail(PDVM_E_HIP, "graph instantiate: %s", hipGetErrorString(e));
-  s->graph_iters = per;
-  return PDVM_OK;
-}
-
-int read_ctl(pdvm_solver *s) {
-  HIPCHK(s, hipMemcpyAsync(s->host_ctl, dev_ctl(s), sizeof(Ctl), hipMemcpyDeviceToHost, s->stream));
-  HIPCHK(s, hipStreamSynchronize(s->stream));
-  return PDVM_OK;
-}
-
-}  // namespace
-
-extern "C" {
-
-int pdvm_halfrange_gh(int32_t n_total, double *nodes, double *weights) {
+int halfrange_gh(int32_t n_total, double *nodes, double *weights) {
   if (n_total < 2 || n_total % 2 || n_total > 64 || !nodes || !weights) {
     set_thread_error("n_total must be even in [2, 64] and outputs non-NULL");
     return PDVM_E_INVAL;
@@ -641,29 +489,269 @@ int pdvm_halfrange_gh(int32_t n_total, double *nodes, double *weights) {
   return PDVM_OK;
 }
 
-size_t pdvm_workspace_bytes(const pdvm_config *cfg) {
-  Problem P;
+}  // namespace
+
+// One or more problems driven together (a single problem is a batch of one).
+struct ProbDev {
+  char *ws = nullptr;
+  bool own_ws = false;
+  size_t bytes = 0;
+  double *scratch = nullptr;
+};
+
+struct pdvm_solver {
+  std::vector<Problem> P;
+  std::vector<ProbDev> D;
+  std::vector<Geo<double>> gd;
+  std::vector<Geo<float>> gf;
+  int precision = 0;
+  hipStream_t stream = nullptr;
+  bool own_stream = false;
+  char *meta = nullptr;            // device: descriptors, offset tables, gathered control blocks
+  Ctl *d_ctl_all = nullptr;
+  std::vector<int> h_item_off, h_blk_off;
+  Batch<double> bd;
+  Batch<float> bf;
+  Ctl *host_ctl = nullptr;         // pinned, one per problem
+  hipGraphExec_t graph = nullptr;
+  int graph_iters = 0;
   std::string err;
-  if (validate_and_build(cfg, P, err) != PDVM_OK) {
-    g_thread_error = err;
-    return 0;
+  int n() const { return (int)P.size(); }
+  int fail(int code, const char *fmt, ...) {
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof(buf), fmt, ap);
+    va_end(ap);
+    err = buf;
+    g_thread_error = buf;
+    return code;
   }
-  return layout_bytes(P);
+};
+
+#define HIPCHK(s, call)                                                                       \
+  do {                                                                                        \
+    hipError_t e_ = (call);                                                                   \
+    if (e_ != hipSuccess) return (s)->fail(PDVM_E_HIP, "%s: %s", #call, hipGetErrorString(e_)); \
+  } while (0)
+
+namespace {
+
+template <typename T>
+std::vector<Geo<T>> &geos(pdvm_solver *s);
+template <>
+std::vector<Geo<double>> &geos<double>(pdvm_solver *s) { return s->gd; }
+template <>
+std::vector<Geo<float>> &geos<float>(pdvm_solver *s) { return s->gf; }
+template <typename T>
+Batch<T> &batch(pdvm_solver *s);
+template <>
+Batch<double> &batch<double>(pdvm_solver *s) { return s->bd; }
+template <>
+Batch<float> &batch<float>(pdvm_solver *s) { return s->bf; }
+
+// Carve problem i's workspace, upload its tables and geometry, rest state.
+template <typename T>
+int setup_problem(pdvm_solver *s, int i) {
+  const Problem &P = s->P[i];
+  const Layout<T> L = make_layout<T>(P);
+  Geo<T> g{};
+  char *b = s->D[i].ws;
+  g.dim = P.dim;
+  for (int a = 0; a < 3; ++a) { g.n[a] = P.n[a]; g.tile[a] = P.tile[a]; g.ntile[a] = P.ntile[a]; }
+  g.N = P.N;
+  g.Ko = P.Ko; g.Ko_pad = P.Ko_pad; g.Kpad = P.Kpad; g.ngroups = P.ngroups;
+  g.lateral_periodic = P.lateral_periodic;
+  g.tau_fb = P.tau_fb;
+  g.y2wall = P.stencil_rule == 0;
+  g.jump = T(P.jump);
+  g.nu = P.nu;
+  for (int j = 0; j < 3; ++j) g.D[j] = P.D[j] > 0 ? P.D[j] : 1.0;
+  g.ctl = (Ctl *)(b + L.ctl);
+  g.flags = (const uint32_t *)(b + L.flags);
+  g.absv = (const T *)(b + L.absv);
+  g.av = (const T *)(b + L.av);
+  g.vsqm = (const T *)(b + L.vsqm);
+  g.rden = (const T *)(b + L.rden);
+  g.wq = (const double *)(b + L.wq);
+  for (int k = 0; k < 2; ++k) {
+    g.h[k] = (T *)(b + L.h[k]);
+    g.src[k] = (T *)(b + L.src[k]);
+    g.srct[k] = (T *)(b + L.srct[k]);
+    g.wall[k] = (T *)(b + L.wall[k]);
+    g.rho[k] = (double *)(b + L.rho[k]);
+    g.u[k] = (double *)(b + L.u[k]);
+  }
+  g.part = (double *)(b + L.part);
+  g.mom_blocks = P.mom_blocks;
+  g.diag_tiles = (const int32_t *)(b + L.tiles);
+  g.diag_off = (const int32_t *)(b + L.offs);
+  g.ndiag = P.ndiag;
+  s->D[i].scratch = (double *)(b + L.scratch);
+  geos<T>(s)[i] = g;
+
+  std::vector<T> absv(P.absv.size()), av(P.absv.size()), vsqm(P.vsqm.size()), rden(P.rden.size());
+  for (size_t k = 0; k < absv.size(); ++k) { absv[k] = T(P.absv[k]); av[k] = T(P.absv[k] * P.n[0]); }
+  for (size_t k = 0; k < vsqm.size(); ++k) vsqm[k] = T(P.vsqm[k]);
+  for (size_t k = 0; k < rden.size(); ++k) rden[k] = T(P.rden[k]);
+  hipStream_t st = s->stream;
+  HIPCHK(s, hipMemsetAsync(b, 0, L.total, st));
+  HIPCHK(s, hipMemcpyAsync((void *)g.flags, P.flags.data(), P.flags.size() * 4, hipMemcpyHostToDevice, st));
+  HIPCHK(s, hipMemcpyAsync((void *)g.absv, absv.data(), absv.size() * sizeof(T), hipMemcpyHostToDevice, st));
+  HIPCHK(s, hipMemcpyAsync((void *)g.av, av.data(), av.size() * sizeof(T), hipMemcpyHostToDevice, st));
+  HIPCHK(s, hipMemcpyAsync((void *)g.vsqm, vsqm.data(), vsqm.size() * sizeof(T), hipMemcpyHostToDevice, st));
+  HIPCHK(s, hipMemcpyAsync((void *)g.rden, rden.data(), rden.size() * sizeof(T), hipMemcpyHostToDevice, st));
+  HIPCHK(s, hipMemcpyAsync((void *)g.wq, P.wq.data(), P.wq.size() * 8, hipMemcpyHostToDevice, st));
+  HIPCHK(s, hipMemcpyAsync((void *)g.diag_tiles, P.diag_tiles.data(), P.diag_tiles.size() * 4, hipMemcpyHostToDevice, st));
+  HIPCHK(s, hipMemcpyAsync((void *)g.diag_off, P.diag_off.data(), P.diag_off.size() * 4, hipMemcpyHostToDevice, st));
+  Ctl c{};
+  c.kn_coef = 2.0 / std::sqrt(M_PI) * (std::isinf(P.kn) ? 0.0 : P.kn);
+  c.err = -1.0;
+  c.stop = 1;
+  HIPCHK(s, hipMemcpyAsync(g.ctl, &c, sizeof(Ctl), hipMemcpyHostToDevice, st));
+  HIPCHK(s, hipStreamSynchronize(st));
+  return PDVM_OK;
 }
 
-int pdvm_create(const pdvm_config *cfg, void *dev_workspace, size_t ws_bytes, void *hip_stream,
-                pdvm_solver **out) {
+// Descriptor array and per-launch block offsets of the whole batch.
+template <typename T>
+int finalize_batch(pdvm_solver *s) {
+  const int n = s->n();
+  const Problem &P0 = s->P[0];
+  int ndmax = 0;
+  for (auto &P : s->P) ndmax = std::max(ndmax, P.ndiag);
+  s->h_item_off.assign((size_t)ndmax * (n + 1), 0);
+  for (int d = 0; d < ndmax; ++d) {
+    int acc = 0;
+    for (int p = 0; p < n; ++p) {
+      s->h_item_off[(size_t)d * (n + 1) + p] = acc;
+      const Problem &P = s->P[p];
+      if (d < P.ndiag) acc += (P.diag_off[d + 1] - P.diag_off[d]) * (P.ngroups << P.dim);
+    }
+    s->h_item_off[(size_t)d * (n + 1) + n] = acc;
+  }
+  s->h_blk_off.assign(n + 1, 0);
+  for (int p = 0; p < n; ++p) s->h_blk_off[p + 1] = s->h_blk_off[p] + s->P[p].mom_blocks;
+  const size_t geo_b = align256(n * sizeof(Geo<T>));
+  const size_t item_b = align256(s->h_item_off.size() * 4);
+  const size_t blk_b = align256(s->h_blk_off.size() * 4);
+  const size_t ctl_b = align256(n * sizeof(Ctl));
+  void *m = nullptr;
+  if (hipMalloc(&m, geo_b + item_b + blk_b + ctl_b) != hipSuccess)
+    return s->fail(PDVM_E_NOMEM, "hipMalloc of the batch tables failed");
+  s->meta = (char *)m;
+  char *geo = s->meta, *item = geo + geo_b, *blk = item + item_b;
+  s->d_ctl_all = (Ctl *)(blk + blk_b);
+  HIPCHK(s, hipMemcpyAsync(geo, geos<T>(s).data(), n * sizeof(Geo<T>), hipMemcpyHostToDevice, s->stream));
+  HIPCHK(s, hipMemcpyAsync(item, s->h_item_off.data(), s->h_item_off.size() * 4, hipMemcpyHostToDevice, s->stream));
+  HIPCHK(s, hipMemcpyAsync(blk, s->h_blk_off.data(), s->h_blk_off.size() * 4, hipMemcpyHostToDevice, s->stream));
+  HIPCHK(s, hipStreamSynchronize(s->stream));
+  Batch<T> &B = batch<T>(s);
+  B.nprob = n;
+  B.dim = P0.dim;
+  B.Ko = P0.Ko;
+  B.tile_edge = P0.tile[0] <= kTileEdge[0] ? kTileEdge[0] : kTileEdge[1];
+  for (auto &P : s->P)
+    if (P.tile[0] > kTileEdge[0]) B.tile_edge = kTileEdge[1];
+  B.y2wall = P0.stencil_rule == 0;
+  B.ndiag_max = ndmax;
+  B.d_geo = (const Geo<T> *)geo;
+  B.d_item_off = (const int *)item;
+  B.d_blk_off = (const int *)blk;
+  B.h_item_off = s->h_item_off.data();
+  B.h_blk_off = s->h_blk_off.data();
+  if (hipHostMalloc((void **)&s->host_ctl, n * sizeof(Ctl), hipHostMallocDefault) != hipSuccess)
+    return s->fail(PDVM_E_NOMEM, "pinned host allocation failed");
+  return PDVM_OK;
+}
+
+template <typename T>
+int enqueue_iteration(pdvm_solver *s) {
+  const Batch<T> &B = batch<T>(s);
+  for (int d = 0; d < B.ndiag_max; ++d) HIPCHK(s, launch_sweep<T>(B, d, s->stream));
+  HIPCHK(s, launch_moments<T>(B, s->stream));
+  HIPCHK(s, launch_reduce<T>(B, s->stream));
+  return PDVM_OK;
+}
+
+int enqueue_iteration_any(pdvm_solver *s) {
+  return s->precision == PDVM_FP64 ? enqueue_iteration<double>(s) : enqueue_iteration<float>(s);
+}
+
+int build_graph(pdvm_solver *s) {
+  if (s->graph) return PDVM_OK;
+  // a few iterations per replay amortise the launch of the graph itself
+  const int per = std::max(1, std::min(8, s->P[0].check_every));
+  hipGraph_t gr;
+  HIPCHK(s, hipStreamBeginCapture(s->stream, hipStreamCaptureModeThreadLocal));
+  int rc = PDVM_OK;
+  for (int i = 0; i < per && rc == PDVM_OK; ++i) rc = enqueue_iteration_any(s);
+  hipError_t e = hipStreamEndCapture(s->stream, &gr);
+  if (rc != PDVM_OK) return rc;
+  if (e != hipSuccess) return s->fail(PDVM_E_HIP, "graph capture: %s", hipGetErrorString(e));
+  e = hipGraphInstantiate(&s->graph, gr, nullptr, nullptr, 0);
+  (void)hipGraphDestroy(gr);
+  if (e != hipSuccess) return s->fail(PDVM_E_HIP, "graph instantiate: %s", hipGetErrorString(e));
+  s->graph_iters = per;
+  return PDVM_OK;
+}
+
+// All control blocks to the pinned host mirror (one gather, one copy).
+int read_ctl(pdvm_solver *s) {
+  if (s->precision == PDVM_FP64) HIPCHK(s, launch_ctl_gather<double>(s->bd, s->d_ctl_all, s->stream));
+  else HIPCHK(s, launch_ctl_gather<float>(s->bf, s->d_ctl_all, s->stream));
+  HIPCHK(s, hipMemcpyAsync(s->host_ctl, s->d_ctl_all, s->n() * sizeof(Ctl), hipMemcpyDeviceToHost, s->stream));
+  HIPCHK(s, hipStreamSynchronize(s->stream));
+  return PDVM_OK;
+}
+
+int arm(pdvm_solver *s, double tol, int mode, int64_t max_iters) {
+  if (s->precision == PDVM_FP64) HIPCHK(s, launch_arm<double>(s->bd, tol, mode, max_iters, s->stream));
+  else HIPCHK(s, launch_arm<float>(s->bf, tol, mode, max_iters, s->stream));
+  return PDVM_OK;
+}
+
+Ctl *dev_ctl(pdvm_solver *s, int i) { return s->precision == PDVM_FP64 ? s->gd[i].ctl : s->gf[i].ctl; }
+
+int check_index(pdvm_solver *s, int i) {
+  if (!s) { set_thread_error("solver is NULL"); return PDVM_E_INVAL; }
+  if (i < 0 || i >= s->n()) return s->fail(PDVM_E_INVAL, "problem index %d outside [0, %d)", i, s->n());
+  return PDVM_OK;
+}
+
+bool same_velocity_grid(const Problem &a, const Problem &b) {
+  return a.dim == b.dim && a.Ko == b.Ko && a.Ko_pad == b.Ko_pad && a.absv == b.absv && a.wq.size() == b.wq.size() &&
+         std::equal(a.wq.begin(), a.wq.begin() + a.Ko_pad, b.wq.begin());
+}
+
+int create_common(const pdvm_config *cfgs, int n, void *dev_workspace, size_t ws_bytes, void *hip_stream,
+                  pdvm_solver **out) {
   if (!out) { set_thread_error("out is NULL"); return PDVM_E_INVAL; }
   *out = nullptr;
+  if (n < 1 || !cfgs) { set_thread_error("need at least one config"); return PDVM_E_INVAL; }
   pdvm_solver *s = new (std::nothrow) pdvm_solver();
   if (!s) { set_thread_error("host allocation failed"); return PDVM_E_NOMEM; }
-  std::string err;
-  int rc = validate_and_build(cfg, s->P, err);
-  if (rc != PDVM_OK) {
-    g_thread_error = err;
-    delete s;
-    return rc;
+  s->P.resize(n);
+  s->D.resize(n);
+  for (int i = 0; i < n; ++i) {
+    std::string err;
+    const int rc = validate_and_build(&cfgs[i], s->P[i], err);
+    if (rc != PDVM_OK) {
+      set_thread_error("config %d: %s", i, err.c_str());
+      delete s;
+      return rc;
+    }
+    const Problem &A = s->P[0], &B = s->P[i];
+    if (B.precision != A.precision || !same_velocity_grid(A, B) || B.stencil_rule != A.stencil_rule ||
+        B.tau_fb != A.tau_fb) {
+      set_thread_error("config %d: a batch shares dimension, precision, velocity grid, stencil rule and tau feedback", i);
+      delete s;
+      return PDVM_E_INVAL;
+    }
   }
+  s->precision = s->P[0].precision;
+  if (s->precision == PDVM_FP64) s->gd.resize(n);
+  else s->gf.resize(n);
   s->stream = (hipStream_t)hip_stream;
   if (!s->stream) {
     // the null stream cannot be captured into a graph: use a private one
@@ -674,31 +762,34 @@ int pdvm_create(const pdvm_config *cfg, void *dev_workspace, size_t ws_bytes, vo
     }
     s->own_stream = true;
   }
-  const size_t need = layout_bytes(s->P);
-  if (dev_workspace) {
-    if (ws_bytes < need || ((uintptr_t)dev_workspace & 255)) {
-      set_thread_error("workspace needs %zu bytes, 256-byte aligned (got %zu)", need, ws_bytes);
-      pdvm_destroy(s);
-      return PDVM_E_NOMEM;
+  for (int i = 0; i < n; ++i) {
+    const size_t need = layout_bytes(s->P[i]);
+    if (dev_workspace) {  // single problem only
+      if (ws_bytes < need || ((uintptr_t)dev_workspace & 255)) {
+        set_thread_error("workspace needs %zu bytes, 256-byte aligned (got %zu)", need, ws_bytes);
+        pdvm_destroy(s);
+        return PDVM_E_NOMEM;
+      }
+      s->D[i].ws = (char *)dev_workspace;
+    } else {
+      void *p = nullptr;
+      if (hipMalloc(&p, need) != hipSuccess) {
+        set_thread_error("hipMalloc of %zu bytes failed (problem %d)", need, i);
+        pdvm_destroy(s);
+        return PDVM_E_NOMEM;
+      }
+      s->D[i].ws = (char *)p;
+      s->D[i].own_ws = true;
     }
-    s->ws = (char *)dev_workspace;
-  } else {
-    void *p = nullptr;
-    if (hipMalloc(&p, need) != hipSuccess) {
-      set_thread_error("hipMalloc of %zu bytes failed", need);
+    s->D[i].bytes = need;
+    const int rc = s->precision == PDVM_FP64 ? setup_problem<double>(s, i) : setup_problem<float>(s, i);
+    if (rc != PDVM_OK) {
+      g_thread_error = s->err;
       pdvm_destroy(s);
-      return PDVM_E_NOMEM;
+      return rc;
     }
-    s->ws = (char *)p;
-    s->own_ws = true;
   }
-  s->ws_bytes = need;
-  if (hipHostMalloc((void **)&s->host_ctl, sizeof(Ctl), hipHostMallocDefault) != hipSuccess) {
-    set_thread_error("pinned host allocation failed");
-    pdvm_destroy(s);
-    return PDVM_E_NOMEM;
-  }
-  rc = s->P.precision == PDVM_FP64 ? setup_device<double>(s) : setup_device<float>(s);
+  const int rc = s->precision == PDVM_FP64 ? finalize_batch<double>(s) : finalize_batch<float>(s);
   if (rc != PDVM_OK) {
     g_thread_error = s->err;
     pdvm_destroy(s);
@@ -708,38 +799,37 @@ int pdvm_create(const pdvm_config *cfg, void *dev_workspace, size_t ws_bytes, vo
   return PDVM_OK;
 }
 
-int pdvm_set_initial(pdvm_solver *s, const double *rho, const double *u) {
-  if (!s) { set_thread_error("solver is NULL"); return PDVM_E_INVAL; }
-  const int64_t N = s->P.N;
+int set_initial_one(pdvm_solver *s, int i, const double *rho, const double *u) {
+  const Problem &P = s->P[i];
+  const int64_t N = P.N;
   double *drho = nullptr, *du = nullptr;
   if (rho) {
-    drho = s->scratch + 4 * N;
+    drho = s->D[i].scratch + 4 * N;
     HIPCHK(s, hipMemcpyAsync(drho, rho, N * 8, hipMemcpyHostToDevice, s->stream));
   }
   if (u) {
-    du = s->scratch + 5 * N;
-    HIPCHK(s, hipMemcpyAsync(du, u, (size_t)s->P.dim * N * 8, hipMemcpyHostToDevice, s->stream));
+    du = s->D[i].scratch + 5 * N;
+    HIPCHK(s, hipMemcpyAsync(du, u, (size_t)P.dim * N * 8, hipMemcpyHostToDevice, s->stream));
   }
-  // reset the counters, keep parity
-  HIPCHK(s, hipMemcpyAsync(s->host_ctl, dev_ctl(s), sizeof(Ctl), hipMemcpyDeviceToHost, s->stream));
-  HIPCHK(s, hipStreamSynchronize(s->stream));
-  Ctl c = *s->host_ctl;
+  int rc = read_ctl(s);
+  if (rc != PDVM_OK) return rc;
+  Ctl c = s->host_ctl[i];
   c.iter = 0;
   c.stop = 1;
   c.status = 0;
   c.err = -1.0;
   c.r = c.k = c.gp = 0;
   for (double &v : c.kring) v = 0;
-  *s->host_ctl = c;
-  HIPCHK(s, hipMemcpyAsync(dev_ctl(s), s->host_ctl, sizeof(Ctl), hipMemcpyHostToDevice, s->stream));
-  if (s->P.precision == PDVM_FP64) HIPCHK(s, launch_init_state<double>(s->gd, drho, du, s->stream));
-  else HIPCHK(s, launch_init_state<float>(s->gf, drho, du, s->stream));
+  s->host_ctl[i] = c;
+  HIPCHK(s, hipMemcpyAsync(dev_ctl(s, i), &s->host_ctl[i], sizeof(Ctl), hipMemcpyHostToDevice, s->stream));
+  if (s->precision == PDVM_FP64) HIPCHK(s, launch_init_state<double>(s->gd[i], drho, du, s->stream));
+  else HIPCHK(s, launch_init_state<float>(s->gf[i], drho, du, s->stream));
   HIPCHK(s, hipStreamSynchronize(s->stream));
   return PDVM_OK;
 }
 
-int pdvm_iterate(pdvm_solver *s, int64_t max_iters, double tol, int32_t stop_mode, pdvm_stats *out) {
-  if (!s) { set_thread_error("solver is NULL"); return PDVM_E_INVAL; }
+// Iterate the whole batch until every problem stopped or max_iters ran.
+int iterate_batch(pdvm_solver *s, int64_t max_iters, double tol, int32_t stop_mode, pdvm_stats *out) {
   if (max_iters < 0 || (stop_mode != PDVM_STOP_FIELD && stop_mode != PDVM_STOP_PAPER_ERR) || std::isnan(tol))
     return s->fail(PDVM_E_INVAL, "max_iters >= 0, a valid stop mode and a non-NaN tol are required");
   const auto t0 = std::chrono::steady_clock::now();
@@ -747,101 +837,105 @@ int pdvm_iterate(pdvm_solver *s, int64_t max_iters, double tol, int32_t stop_mod
   if (rc != PDVM_OK) return rc;
   rc = read_ctl(s);
   if (rc != PDVM_OK) return rc;
-  const int64_t start = s->host_ctl->iter;
-  HIPCHK(s, launch_arm(dev_ctl(s), tol, stop_mode, max_iters, s->stream));
+  const int n = s->n();
+  std::vector<int64_t> start(n);
+  for (int i = 0; i < n; ++i) start[i] = s->host_ctl[i].iter;
+  rc = arm(s, tol, stop_mode, max_iters);
+  if (rc != PDVM_OK) return rc;
   int64_t launched = 0;
   const int per = s->graph_iters;
-  const int poll = std::max(per, s->P.check_every / per * per);
+  const int poll = std::max(per, s->P[0].check_every / per * per);
   while (launched < max_iters) {
-    int64_t batch = 0;
-    while (batch < poll && launched < max_iters) {
+    int64_t b = 0;
+    while (b < poll && launched < max_iters) {
       HIPCHK(s, hipGraphLaunch(s->graph, s->stream));
-      batch += per;
+      b += per;
       launched += per;
     }
     rc = read_ctl(s);
     if (rc != PDVM_OK) return rc;
-    if (s->host_ctl->stop) break;
+    bool all = true;
+    for (int i = 0; i < n; ++i) all = all && s->host_ctl[i].stop;
+    if (all) break;
   }
-  if (launched >= max_iters) {
-    rc = read_ctl(s);
-    if (rc != PDVM_OK) return rc;
+  const double secs = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+  int worst = PDVM_OK;
+  for (int i = 0; i < n; ++i) {
+    const Ctl &c = s->host_ctl[i];
+    if (out) {
+      out[i].iters = c.iter - start[i];
+      out[i].total_iters = c.iter;
+      out[i].r = c.r;
+      out[i].err = c.err;
+      out[i].k = c.k;
+      out[i].gp = c.gp;
+      out[i].seconds = secs;
+      out[i].converged = c.status == 1;
+    }
+    if (c.status == -4) worst = PDVM_E_NONFINITE;
+    else if (c.status != 1 && worst == PDVM_OK) worst = PDVM_NOT_CONVERGED;
   }
-  const Ctl &c = *s->host_ctl;
-  if (out) {
-    out->iters = c.iter - start;
-    out->total_iters = c.iter;
-    out->r = c.r;
-    out->err = c.err;
-    out->k = c.k;
-    out->gp = c.gp;
-    out->seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
-    out->converged = c.status == 1;
-  }
-  if (c.status == -4) return s->fail(PDVM_E_NONFINITE, "residual or permeability became non-finite at iteration %lld; the previous state is kept", (long long)(c.iter + 1));
-  return c.status == 1 ? PDVM_OK : PDVM_NOT_CONVERGED;
+  if (worst == PDVM_E_NONFINITE)
+    return s->fail(PDVM_E_NONFINITE, "residual or permeability became non-finite; the previous state is kept");
+  return worst;
 }
 
-int pdvm_get_moments(pdvm_solver *s, double *rho, double *u, double *tau, double *q) {
-  if (!s) { set_thread_error("solver is NULL"); return PDVM_E_INVAL; }
+int get_moments_one(pdvm_solver *s, int i, double *rho, double *u, double *tau, double *q) {
   int rc = read_ctl(s);
   if (rc != PDVM_OK) return rc;
-  const int par = s->host_ctl->par;
-  const int64_t N = s->P.N;
-  const double *drho = s->P.precision == PDVM_FP64 ? s->gd.rho[par] : s->gf.rho[par];
-  const double *du = s->P.precision == PDVM_FP64 ? s->gd.u[par] : s->gf.u[par];
+  const int par = s->host_ctl[i].par;
+  const Problem &P = s->P[i];
+  const int64_t N = P.N;
+  const double *drho = s->precision == PDVM_FP64 ? s->gd[i].rho[par] : s->gf[i].rho[par];
+  const double *du = s->precision == PDVM_FP64 ? s->gd[i].u[par] : s->gf[i].u[par];
   if (rho) HIPCHK(s, hipMemcpyAsync(rho, drho, N * 8, hipMemcpyDeviceToHost, s->stream));
-  if (u) HIPCHK(s, hipMemcpyAsync(u, du, (size_t)s->P.dim * N * 8, hipMemcpyDeviceToHost, s->stream));
+  if (u) HIPCHK(s, hipMemcpyAsync(u, du, (size_t)P.dim * N * 8, hipMemcpyDeviceToHost, s->stream));
   if (tau || q) {
-    double *dt = s->scratch, *dq = s->scratch + N;
-    if (s->P.precision == PDVM_FP64) HIPCHK(s, launch_diagnostics<double>(s->gd, dt, dq, s->stream));
-    else HIPCHK(s, launch_diagnostics<float>(s->gf, dt, dq, s->stream));
+    double *dt = s->D[i].scratch, *dq = s->D[i].scratch + N;
+    if (s->precision == PDVM_FP64) HIPCHK(s, launch_diagnostics<double>(s->gd[i], dt, dq, s->stream));
+    else HIPCHK(s, launch_diagnostics<float>(s->gf[i], dt, dq, s->stream));
     if (tau) HIPCHK(s, hipMemcpyAsync(tau, dt, N * 8, hipMemcpyDeviceToHost, s->stream));
-    if (q) HIPCHK(s, hipMemcpyAsync(q, dq, (size_t)s->P.dim * N * 8, hipMemcpyDeviceToHost, s->stream));
+    if (q) HIPCHK(s, hipMemcpyAsync(q, dq, (size_t)P.dim * N * 8, hipMemcpyDeviceToHost, s->stream));
   }
   HIPCHK(s, hipStreamSynchronize(s->stream));
-  // solid voxels read 0 (the device buffers never write them after rest)
   return PDVM_OK;
 }
 
-int pdvm_get_flux(pdvm_solver *s, double *gp, double *k, double *gp_section) {
-  if (!s) { set_thread_error("solver is NULL"); return PDVM_E_INVAL; }
-  const int64_t N = s->P.N;
+int get_flux_one(pdvm_solver *s, int i, double *gp, double *k, double *gp_section) {
+  const Problem &P = s->P[i];
+  const int64_t N = P.N;
   std::vector<double> u1(N);
   int rc = read_ctl(s);
   if (rc != PDVM_OK) return rc;
-  const int par = s->host_ctl->par;
-  const double *du = s->P.precision == PDVM_FP64 ? s->gd.u[par] : s->gf.u[par];
+  const int par = s->host_ctl[i].par;
+  const double *du = s->precision == PDVM_FP64 ? s->gd[i].u[par] : s->gf[i].u[par];
   HIPCHK(s, hipMemcpyAsync(u1.data(), du, N * 8, hipMemcpyDeviceToHost, s->stream));
   HIPCHK(s, hipStreamSynchronize(s->stream));
   double tot = 0;
-  for (int64_t c = 0; c < N; ++c) tot += (s->P.flags[c] & F_SOLID) ? 0.0 : u1[c];
+  for (int64_t c = 0; c < N; ++c) tot += (P.flags[c] & F_SOLID) ? 0.0 : u1[c];
   const double G = tot / (double)N;
   if (gp) *gp = G;
-  if (k) *k = 2.0 / std::sqrt(M_PI) * (std::isinf(s->P.kn) ? 0.0 : s->P.kn) * G;
+  if (k) *k = 2.0 / std::sqrt(M_PI) * (std::isinf(P.kn) ? 0.0 : P.kn) * G;
   if (gp_section) {
-    const int n0 = s->P.n[0];
+    const int n0 = P.n[0];
     const int64_t A = N / n0;
-    for (int i = 0; i < n0; ++i) gp_section[i] = 0;
+    for (int x = 0; x < n0; ++x) gp_section[x] = 0;
     for (int64_t c = 0; c < N; ++c)
-      if (!(s->P.flags[c] & F_SOLID)) gp_section[c % n0] += u1[c];
-    for (int i = 0; i < n0; ++i) gp_section[i] /= (double)A;
+      if (!(P.flags[c] & F_SOLID)) gp_section[c % n0] += u1[c];
+    for (int x = 0; x < n0; ++x) gp_section[x] /= (double)A;
   }
   return PDVM_OK;
 }
 
-}  // extern "C"
-
-// checkpoint layout: header, Ctl, then per parity-current buffer: rho, u, src,
+// checkpoint layout: header, Ctl, then the parity-current rho, u, src, srct,
 // wall, then the boundary layers of h.
-namespace {
 struct StateHeader {
   uint64_t magic;
   int32_t dim, n0, n1, n2, Kpad, precision;
   int64_t fluid;
   uint64_t fingerprint;
 };
-constexpr uint64_t kMagic = 0x31504d56444d4150ull;  // "PAMDVMP1"
+constexpr uint64_t kMagic = 0x31504d56444d4150ull;
 
 std::vector<int> face_layers(const Problem &P, int a) {
   std::vector<int> r;
@@ -859,13 +953,13 @@ size_t state_bytes(const Problem &P) {
 }
 
 template <typename T>
-int state_io(pdvm_solver *s, char *buf, bool save) {
-  const Problem &P = s->P;
-  Geo<T> &g = geo<T>(s);
+int state_io(pdvm_solver *s, int i, char *buf, bool save) {
+  const Problem &P = s->P[i];
+  Geo<T> &g = geos<T>(s)[i];
   const size_t N = (size_t)P.N;
   int rc = read_ctl(s);
   if (rc != PDVM_OK) return rc;
-  const int par = s->host_ctl->par;
+  const int par = s->host_ctl[i].par;
   char *p = buf + sizeof(StateHeader) + sizeof(Ctl);
   auto xfer = [&](void *dev, size_t bytes) -> int {
     hipError_t e = save ? hipMemcpyAsync(p, dev, bytes, hipMemcpyDeviceToHost, s->stream)
@@ -894,70 +988,152 @@ int state_io(pdvm_solver *s, char *buf, bool save) {
   HIPCHK(s, hipStreamSynchronize(s->stream));
   return PDVM_OK;
 }
-}  // namespace
 
-extern "C" {
-
-int pdvm_get_state(pdvm_solver *s, void *buf, size_t *bytes) {
-  if (!s || !bytes) { set_thread_error("solver or bytes is NULL"); return PDVM_E_INVAL; }
-  const size_t need = state_bytes(s->P);
+int get_state_one(pdvm_solver *s, int i, void *buf, size_t *bytes) {
+  const Problem &P = s->P[i];
+  const size_t need = state_bytes(P);
   if (!buf) { *bytes = need; return PDVM_OK; }
   if (*bytes < need) return s->fail(PDVM_E_STATE, "state buffer needs %zu bytes", need);
   int rc = read_ctl(s);
   if (rc != PDVM_OK) return rc;
-  StateHeader h{kMagic, s->P.dim, s->P.n[0], s->P.n[1], s->P.n[2], s->P.Kpad, s->P.precision, s->P.fluid,
-                s->P.fingerprint};
+  StateHeader h{kMagic, P.dim, P.n[0], P.n[1], P.n[2], P.Kpad, P.precision, P.fluid, P.fingerprint};
   std::memcpy(buf, &h, sizeof(h));
-  std::memcpy((char *)buf + sizeof(h), s->host_ctl, sizeof(Ctl));
-  rc = s->P.precision == PDVM_FP64 ? state_io<double>(s, (char *)buf, true) : state_io<float>(s, (char *)buf, true);
+  std::memcpy((char *)buf + sizeof(h), &s->host_ctl[i], sizeof(Ctl));
+  rc = s->precision == PDVM_FP64 ? state_io<double>(s, i, (char *)buf, true) : state_io<float>(s, i, (char *)buf, true);
   *bytes = need;
   return rc;
 }
 
-int pdvm_set_state(pdvm_solver *s, const void *buf, size_t bytes) {
-  if (!s || !buf) { set_thread_error("solver or buf is NULL"); return PDVM_E_INVAL; }
-  const size_t need = state_bytes(s->P);
+int set_state_one(pdvm_solver *s, int i, const void *buf, size_t bytes) {
+  const Problem &P = s->P[i];
+  const size_t need = state_bytes(P);
   if (bytes != need) return s->fail(PDVM_E_STATE, "state has %zu bytes, this problem needs %zu", bytes, need);
   StateHeader h;
   std::memcpy(&h, buf, sizeof(h));
-  if (h.magic != kMagic || h.dim != s->P.dim || h.n0 != s->P.n[0] || h.n1 != s->P.n[1] || h.n2 != s->P.n[2] ||
-      h.Kpad != s->P.Kpad || h.precision != s->P.precision || h.fluid != s->P.fluid ||
-      h.fingerprint != s->P.fingerprint)
+  if (h.magic != kMagic || h.dim != P.dim || h.n0 != P.n[0] || h.n1 != P.n[1] || h.n2 != P.n[2] || h.Kpad != P.Kpad ||
+      h.precision != P.precision || h.fluid != P.fluid || h.fingerprint != P.fingerprint)
     return s->fail(PDVM_E_STATE, "state belongs to a different problem");
   Ctl c;
   std::memcpy(&c, (const char *)buf + sizeof(h), sizeof(Ctl));
   int rc = read_ctl(s);
   if (rc != PDVM_OK) return rc;
-  c.par = s->host_ctl->par;  // restore into this solver's current buffers
+  c.par = s->host_ctl[i].par;  // restore into this solver's current buffers
   c.stop = 1;
-  *s->host_ctl = c;
-  HIPCHK(s, hipMemcpyAsync(dev_ctl(s), s->host_ctl, sizeof(Ctl), hipMemcpyHostToDevice, s->stream));
+  s->host_ctl[i] = c;
+  HIPCHK(s, hipMemcpyAsync(dev_ctl(s, i), &s->host_ctl[i], sizeof(Ctl), hipMemcpyHostToDevice, s->stream));
   HIPCHK(s, hipStreamSynchronize(s->stream));
-  return s->P.precision == PDVM_FP64 ? state_io<double>(s, (char *)buf, false)
-                                     : state_io<float>(s, (char *)buf, false);
+  return s->precision == PDVM_FP64 ? state_io<double>(s, i, (char *)buf, false)
+                                   : state_io<float>(s, i, (char *)buf, false);
+}
+
+int single(pdvm_solver *s) {
+  if (!s) { set_thread_error("solver is NULL"); return PDVM_E_INVAL; }
+  if (s->n() != 1) return s->fail(PDVM_E_INVAL, "this call needs a single-problem solver (use the pdvm_batch_* calls)");
+  return PDVM_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int pdvm_halfrange_gh(int32_t n_total, double *nodes, double *weights) { return halfrange_gh(n_total, nodes, weights); }
+
+size_t pdvm_workspace_bytes(const pdvm_config *cfg) {
+  Problem P;
+  std::string err;
+  if (validate_and_build(cfg, P, err) != PDVM_OK) {
+    g_thread_error = err;
+    return 0;
+  }
+  return layout_bytes(P);
+}
+
+int pdvm_create(const pdvm_config *cfg, void *dev_workspace, size_t ws_bytes, void *hip_stream, pdvm_solver **out) {
+  return create_common(cfg, 1, dev_workspace, ws_bytes, hip_stream, out);
+}
+
+int pdvm_set_initial(pdvm_solver *s, const double *rho, const double *u) {
+  int rc = single(s);
+  return rc != PDVM_OK ? rc : set_initial_one(s, 0, rho, u);
+}
+
+int pdvm_iterate(pdvm_solver *s, int64_t max_iters, double tol, int32_t stop_mode, pdvm_stats *out) {
+  int rc = single(s);
+  return rc != PDVM_OK ? rc : iterate_batch(s, max_iters, tol, stop_mode, out);
+}
+
+int pdvm_get_moments(pdvm_solver *s, double *rho, double *u, double *tau, double *q) {
+  int rc = single(s);
+  return rc != PDVM_OK ? rc : get_moments_one(s, 0, rho, u, tau, q);
+}
+
+int pdvm_get_flux(pdvm_solver *s, double *gp, double *k, double *gp_section) {
+  int rc = single(s);
+  return rc != PDVM_OK ? rc : get_flux_one(s, 0, gp, k, gp_section);
+}
+
+int pdvm_get_state(pdvm_solver *s, void *buf, size_t *bytes) {
+  int rc = single(s);
+  if (rc != PDVM_OK) return rc;
+  if (!bytes) return s->fail(PDVM_E_INVAL, "bytes is NULL");
+  return get_state_one(s, 0, buf, bytes);
+}
+
+int pdvm_set_state(pdvm_solver *s, const void *buf, size_t bytes) {
+  int rc = single(s);
+  if (rc != PDVM_OK) return rc;
+  if (!buf) return s->fail(PDVM_E_INVAL, "buf is NULL");
+  return set_state_one(s, 0, buf, bytes);
+}
+
+int pdvm_batch_create(int32_t n, const pdvm_config *cfgs, void *hip_stream, pdvm_solver **out) {
+  return create_common(cfgs, n, nullptr, 0, hip_stream, out);
+}
+
+int32_t pdvm_batch_size(const pdvm_solver *s) { return s ? (int32_t)s->P.size() : 0; }
+
+int pdvm_batch_set_initial(pdvm_solver *s, int32_t i, const double *rho, const double *u) {
+  int rc = check_index(s, i);
+  return rc != PDVM_OK ? rc : set_initial_one(s, i, rho, u);
+}
+
+int pdvm_batch_iterate(pdvm_solver *s, int64_t max_iters, double tol, int32_t stop_mode, pdvm_stats *out) {
+  if (!s) { set_thread_error("solver is NULL"); return PDVM_E_INVAL; }
+  return iterate_batch(s, max_iters, tol, stop_mode, out);
+}
+
+int pdvm_batch_get_moments(pdvm_solver *s, int32_t i, double *rho, double *u, double *tau, double *q) {
+  int rc = check_index(s, i);
+  return rc != PDVM_OK ? rc : get_moments_one(s, i, rho, u, tau, q);
+}
+
+int pdvm_batch_get_flux(pdvm_solver *s, int32_t i, double *gp, double *k, double *gp_section) {
+  int rc = check_index(s, i);
+  return rc != PDVM_OK ? rc : get_flux_one(s, i, gp, k, gp_section);
 }
 
 int pdvm_time_kernels(pdvm_solver *s, int32_t iters, pdvm_timing *out) {
   if (!s || !out || iters <= 0) { set_thread_error("bad arguments"); return PDVM_E_INVAL; }
-  const Problem &P = s->P;
-  HIPCHK(s, launch_arm(dev_ctl(s), 0.0, 0, (int64_t)iters + 1, s->stream));
-  const int nd = P.ndiag;
-  std::vector<hipEvent_t> ev(nd + 3);
+  int rc = arm(s, 0.0, 0, (int64_t)iters + 1);
+  if (rc != PDVM_OK) return rc;
+  const int nd = s->precision == PDVM_FP64 ? s->bd.ndiag_max : s->bf.ndiag_max;
+  hipEvent_t ev[4];
   for (auto &e : ev) HIPCHK(s, hipEventCreate(&e));
   double sweep = 0, mom = 0, red = 0, tot = 0;
-  const int nsg = P.ngroups << P.dim;
+  int launches = 0;
+  for (int d = 0; d < nd; ++d) launches += s->h_item_off[(size_t)d * (s->n() + 1) + s->n()] > 0;
   for (int it = 0; it < iters; ++it) {
     HIPCHK(s, hipEventRecord(ev[0], s->stream));
     for (int d = 0; d < nd; ++d) {
-      const int items = (P.diag_off[d + 1] - P.diag_off[d]) * nsg;
-      if (P.precision == PDVM_FP64) HIPCHK(s, launch_sweep<double>(s->gd, d, items, s->stream));
-      else HIPCHK(s, launch_sweep<float>(s->gf, d, items, s->stream));
+      if (s->precision == PDVM_FP64) HIPCHK(s, launch_sweep<double>(s->bd, d, s->stream));
+      else HIPCHK(s, launch_sweep<float>(s->bf, d, s->stream));
     }
     HIPCHK(s, hipEventRecord(ev[1], s->stream));
-    if (P.precision == PDVM_FP64) HIPCHK(s, launch_moments<double>(s->gd, s->stream));
-    else HIPCHK(s, launch_moments<float>(s->gf, s->stream));
+    if (s->precision == PDVM_FP64) HIPCHK(s, launch_moments<double>(s->bd, s->stream));
+    else HIPCHK(s, launch_moments<float>(s->bf, s->stream));
     HIPCHK(s, hipEventRecord(ev[2], s->stream));
-    HIPCHK(s, launch_reduce(dev_ctl(s), P.precision == PDVM_FP64 ? s->gd.part : s->gf.part, P.mom_blocks, P.N, s->stream));
+    if (s->precision == PDVM_FP64) HIPCHK(s, launch_reduce<double>(s->bd, s->stream));
+    else HIPCHK(s, launch_reduce<float>(s->bf, s->stream));
     HIPCHK(s, hipEventRecord(ev[3], s->stream));
     HIPCHK(s, hipEventSynchronize(ev[3]));
     float a = 0, b = 0, c = 0;
@@ -970,18 +1146,23 @@ int pdvm_time_kernels(pdvm_solver *s, int32_t iters, pdvm_timing *out) {
     tot += a + b + c;
   }
   for (auto &e : ev) (void)hipEventDestroy(e);
-  const double es = P.precision == PDVM_FP64 ? 8.0 : 4.0;
+  const double es = s->precision == PDVM_FP64 ? 8.0 : 4.0;
+  double fluid = 0, vel = 0;
+  for (auto &P : s->P) {
+    fluid += (double)P.fluid;
+    vel = (double)(P.Ko << P.dim);
+  }
   out->sweep_ms_per_iter = sweep / iters;
   out->moments_ms_per_iter = mom / iters;
   out->iter_ms = tot / iters;
-  out->sweep_launches_per_iter = nd;
-  out->sweep_ms_per_launch = sweep / iters / nd;
+  out->sweep_launches_per_iter = launches;
+  out->sweep_ms_per_launch = sweep / iters / std::max(1, launches);
   out->moments_ms_per_launch = mom / iters;
   out->reduce_ms_per_launch = red / iters;
-  out->fluid_cells = (double)P.fluid;
-  out->velocities = (double)(P.Ko << P.dim);
-  out->sweep_bytes_per_iter = es * (double)P.fluid * (double)(P.Ko << P.dim);
-  out->moments_bytes_per_iter = es * (double)P.fluid * (double)(P.Ko << P.dim);
+  out->fluid_cells = fluid;
+  out->velocities = vel;
+  out->sweep_bytes_per_iter = es * fluid * vel;
+  out->moments_bytes_per_iter = es * fluid * vel;
   return PDVM_OK;
 }
 
@@ -989,8 +1170,9 @@ void pdvm_destroy(pdvm_solver *s) {
   if (!s) return;
   if (s->graph) (void)hipGraphExecDestroy(s->graph);
   if (s->stream) (void)hipStreamSynchronize(s->stream);
-  else (void)hipDeviceSynchronize();
-  if (s->own_ws && s->ws) (void)hipFree(s->ws);
+  for (auto &d : s->D)
+    if (d.own_ws && d.ws) (void)hipFree(d.ws);
+  if (s->meta) (void)hipFree(s->meta);
   if (s->host_ctl) (void)hipHostFree(s->host_ctl);
   if (s->own_stream) (void)hipStreamDestroy(s->stream);
   delete s;

@@ -71,16 +71,35 @@ struct Geo {
   int32_t ndiag;
 };
 
-// Kernel launchers (dvm_kernels.hip). All enqueue on `st`.
 // Square sweep tile edges in (x1, x2) compiled into the kernel; the host
 // rounds a requested edge up to one of them.
 constexpr int kTileEdge[2] = {4, 8};
+
+// A batch of problems sharing dimension, precision, velocity grid, tile edge
+// and stencil rule (sizes, geometries and Kn may differ). The hot kernels take
+// the device array of descriptors and locate their problem from per-launch
+// block offsets; a single problem is a batch of one.
 template <typename T>
-hipError_t launch_sweep(const Geo<T> &g, int diag, int items, hipStream_t st);
+struct Batch {
+  int nprob = 0, dim = 2, Ko = 0, tile_edge = 8, y2wall = 0, ndiag_max = 0;
+  const Geo<T> *d_geo = nullptr;
+  const int *d_item_off = nullptr;   // [ndiag_max][nprob + 1] sweep blocks per diagonal
+  const int *d_blk_off = nullptr;    // [nprob + 1] moment-kernel blocks
+  const int *h_item_off = nullptr;   // host copies
+  const int *h_blk_off = nullptr;
+};
+
+// Kernel launchers (dvm_kernels.hip). All enqueue on `st`.
 template <typename T>
-hipError_t launch_moments(const Geo<T> &g, hipStream_t st);
-hipError_t launch_reduce(Ctl *ctl, const double *part, int nblocks, int64_t N, hipStream_t st);
-hipError_t launch_arm(Ctl *ctl, double tol, int mode, int64_t max_iters, hipStream_t st);
+hipError_t launch_sweep(const Batch<T> &B, int diag, hipStream_t st);
+template <typename T>
+hipError_t launch_moments(const Batch<T> &B, hipStream_t st);
+template <typename T>
+hipError_t launch_reduce(const Batch<T> &B, hipStream_t st);
+template <typename T>
+hipError_t launch_arm(const Batch<T> &B, double tol, int mode, int64_t max_iters, hipStream_t st);
+template <typename T>
+hipError_t launch_ctl_gather(const Batch<T> &B, Ctl *out, hipStream_t st);
 template <typename T>
 hipError_t launch_init_state(const Geo<T> &g, const double *rho, const double *u, hipStream_t st);
 template <typename T>

@@ -40,20 +40,52 @@ __device__ __forceinline__ Img image_of(int j, int c, int n, int lat_periodic) {
   return im;
 }
 
+// Pointers read from the problem descriptors carry no address space; casting
+// them to the global one lets the compiler emit global (not flat) accesses,
+// whose completion counters do not alias the LDS ones.
 template <typename T>
-__device__ __forceinline__ int64_t cell_of(const Geo<T> &g, int x, int y, int z) {
+using gptr = __attribute__((address_space(1))) T *;
+template <typename T>
+__device__ __forceinline__ gptr<T> as_global(T *p) {
+  return (gptr<T>)p;
+}
+
+// The few per-problem values the image and indexing helpers need, held in
+// registers by the kernels that use them.
+template <typename T>
+struct Dom {
+  int n[3];
+  int64_t Kpad;
+  int latp;
+  T jump;
+};
+
+template <typename T>
+__device__ __forceinline__ Dom<T> dom_of(const Geo<T> &g) {
+  Dom<T> d;
+  d.n[0] = g.n[0];
+  d.n[1] = g.n[1];
+  d.n[2] = g.n[2];
+  d.Kpad = g.Kpad;
+  d.latp = g.lateral_periodic;
+  d.jump = g.jump;
+  return d;
+}
+
+template <typename T>
+__device__ __forceinline__ int64_t cell_of(const Dom<T> &g, int x, int y, int z) {
   return x + (int64_t)g.n[0] * (y + (int64_t)g.n[1] * z);
 }
 
 // h at an upstream fluid node along axis j: the current sweep inside the
 // domain, the previous iteration's value at the image outside it (with the
 // mirrored velocity across a specular face and the jump across the x1 wrap).
-template <typename T>
-__device__ __forceinline__ T upstream_fluid(const Geo<T> &g, const T *hc, const T *hp, int j,
-                                            int x, int y, int z, int kofs, int kmir) {
+template <typename T, typename PC, typename PP>
+__device__ __forceinline__ T upstream_fluid(const Dom<T> &g, PC hc, PP hp, int j, int x, int y, int z, int kofs,
+                                            int kmir) {
   int c[3] = {x, y, z};
   if (c[j] >= 0 && c[j] < g.n[j]) return hc[cell_of(g, c[0], c[1], c[2]) * g.Kpad + kofs];
-  const Img im = image_of(j, c[j], g.n[j], g.lateral_periodic);
+  const Img im = image_of(j, c[j], g.n[j], g.latp);
   c[j] = im.r;
   const T v = hp[cell_of(g, c[0], c[1], c[2]) * g.Kpad + (im.mir ? kmir : kofs)];
   return im.jmp ? v + T(im.jmp) * g.jump : v;
@@ -62,13 +94,12 @@ __device__ __forceinline__ T upstream_fluid(const Geo<T> &g, const T *hc, const 
 // Wall value of a solid met at the second upstream node along axis j: the wall
 // density seen from the first upstream (fluid) node y1 = x - s e_j, i.e. its
 // incoming half-flux over D_j, carried through y1's image if y1 is outside.
-template <typename T>
-__device__ __forceinline__ T wall_at_y1(const Geo<T> &g, const T *wall, int j, int s, int pin,
-                                                  int x, int y, int z) {
+template <typename T, typename PW>
+__device__ __forceinline__ T wall_at_y1(const Dom<T> &g, PW wall, int j, int s, int pin, int x, int y, int z) {
   int c[3] = {x, y, z};
   c[j] -= s;
   if (c[j] >= 0 && c[j] < g.n[j]) return wall[cell_of(g, c[0], c[1], c[2]) * 6 + 2 * j + pin];
-  const Img im = image_of(j, c[j], g.n[j], g.lateral_periodic);
+  const Img im = image_of(j, c[j], g.n[j], g.latp);
   c[j] = im.r;
   const int p = im.mir ? 1 - pin : pin;
   const T v = wall[cell_of(g, c[0], c[1], c[2]) * 6 + 2 * j + p];
@@ -89,30 +120,56 @@ __device__ __forceinline__ T wall_at_y1(const Geo<T> &g, const T *wall, int j, i
 // lagged images outside the domain.
 constexpr uint32_t R_SKIP = 0x80000000u;  // solid voxel or outside the tile
 
+// Index of the problem owning block b: off[p] <= b < off[p + 1].
+__device__ __forceinline__ int owner_of(const int *off, int nprob, int b) {
+  int lo = 0, hi = nprob;
+  while (hi - lo > 1) {
+    const int mid = (lo + hi) >> 1;
+    if (off[mid] <= b) lo = mid;
+    else hi = mid;
+  }
+  return lo;
+}
+
 template <typename T, int DIM, int TT, bool Y2WALL>
 __global__ void __launch_bounds__(kWave)
-    sweep_kernel(Geo<T> g, int diag, const uint32_t *__restrict__ flags, const T *__restrict__ src0,
-                 const T *__restrict__ src1, const T *__restrict__ srct0, const T *__restrict__ srct1,
-                 const T *__restrict__ wall0, const T *__restrict__ wall1, T *__restrict__ h0,
-                 T *__restrict__ h1) {
+    sweep_kernel(const Geo<T> *__restrict__ G, const int *__restrict__ item_off, int nprob, int diag) {
   constexpr int NC = TT * TT;
   constexpr int RW = 5 + 3 * DIM;  // record: src (4), nu tau, then per axis (c1, c2, w)
   __shared__ T rd_lds[8 * kWave];
   __shared__ T rec[NC * RW];
   __shared__ uint32_t rcode[NC];
-  const Ctl *ctl = g.ctl;
-  if (ctl->stop) return;
+  const int p = owner_of(item_off, nprob, blockIdx.x);
+  const Geo<T> &G_ = G[p];
+  const Ctl *ctl = G_.ctl;
+  if (ctl->stop) return;  // converged problems retire
   const int par = ctl->par;
-  const int d0 = g.diag_off[diag];
-  const int ntd = g.diag_off[diag + 1] - d0;
-  int item = blockIdx.x;
+  // every per-problem value is read once here; the loops below see registers
+  const Dom<T> dm = dom_of(G_);
+  const gptr<const int32_t> diag_off = as_global(G_.diag_off);
+  const gptr<const int32_t> diag_tiles = as_global(G_.diag_tiles);
+  const int ngroups = G_.ngroups, Ko = G_.Ko, Ko_pad = G_.Ko_pad, tau_fb = G_.tau_fb;
+  const int tile[3] = {G_.tile[0], G_.tile[1], G_.tile[2]};
+  const int ntile[3] = {G_.ntile[0], G_.ntile[1], G_.ntile[2]};
+  const gptr<const T> absv = as_global(G_.absv), avv = as_global(G_.av), rden = as_global(G_.rden),
+                      vsq = as_global(G_.vsqm);
+  const gptr<T> hc = as_global(par ? G_.h[0] : G_.h[1]);
+  const gptr<const T> hp = as_global((const T *)(par ? G_.h[1] : G_.h[0]));
+  const gptr<const T> src = as_global((const T *)(par ? G_.src[1] : G_.src[0]));
+  const gptr<const T> srct = as_global((const T *)(par ? G_.srct[1] : G_.srct[0]));
+  const gptr<const T> wall = as_global((const T *)(par ? G_.wall[1] : G_.wall[0]));
+  const gptr<const uint32_t> flags = as_global(G_.flags);
+  const int n0 = dm.n[0], n1 = dm.n[1];
+  const int d0 = diag_off[diag];
+  const int ntd = diag_off[diag + 1] - d0;
+  int item = blockIdx.x - item_off[p];
   const int t = item % ntd;
   item /= ntd;
-  const int grp = item % g.ngroups;
-  const int o = item / g.ngroups;
+  const int grp = item % ngroups;
+  const int o = item / ngroups;
   const int lane = threadIdx.x;
   const int q = grp * kWave + lane;
-  const bool active = q < g.Ko;
+  const bool active = q < Ko;
   const int qq = active ? q : 0;
   int s[3], sidx[3], pin[3];
 #pragma unroll
@@ -124,31 +181,25 @@ __global__ void __launch_bounds__(kWave)
   T vv[3] = {T(0), T(0), T(0)}, aa[3] = {T(0), T(0), T(0)};
 #pragma unroll
   for (int j = 0; j < DIM; ++j) {
-    const T av = g.absv[j * g.Ko_pad + qq];
+    const T av = absv[j * Ko_pad + qq];
     vv[j] = s[j] > 0 ? av : -av;
-    aa[j] = g.av[j * g.Ko_pad + qq];
+    aa[j] = avv[j * Ko_pad + qq];
   }
 #pragma unroll
-  for (int c = 0; c < (1 << DIM); ++c) rd_lds[c * kWave + lane] = g.rden[c * g.Ko_pad + qq];
-  const T vsqm = g.tau_fb ? g.vsqm[qq] : T(0);
-  const int kofs = o * g.Ko_pad + qq;
+  for (int c = 0; c < (1 << DIM); ++c) rd_lds[c * kWave + lane] = rden[c * Ko_pad + qq];
+  const T vsqm = tau_fb ? vsq[qq] : T(0);
+  const int kofs = o * Ko_pad + qq;
   int kmir[3];
 #pragma unroll
-  for (int j = 0; j < 3; ++j) kmir[j] = (o ^ (1 << j)) * g.Ko_pad + qq;
-  T *hc = par ? h0 : h1;
-  const T *hp = par ? h1 : h0;
-  const T *src = par ? src1 : src0;
-  const T *srct = par ? srct1 : srct0;
-  const T *wall = par ? wall1 : wall0;
-  const int n0 = g.n[0], n1 = g.n[1];
+  for (int j = 0; j < 3; ++j) kmir[j] = (o ^ (1 << j)) * Ko_pad + qq;
 
   int lo[3] = {0, 0, 0}, cnt[3] = {1, 1, 1};
 #pragma unroll
   for (int j = 0; j < DIM; ++j) {
-    const int tp = g.diag_tiles[(d0 + t) * 4 + j];
-    const int tj = s[j] > 0 ? tp : g.ntile[j] - 1 - tp;
-    lo[j] = tj * g.tile[j];
-    cnt[j] = min(g.tile[j], g.n[j] - lo[j]);
+    const int tp = diag_tiles[(d0 + t) * 4 + j];
+    const int tj = s[j] > 0 ? tp : ntile[j] - 1 - tp;
+    lo[j] = tj * tile[j];
+    cnt[j] = min(tile[j], dm.n[j] - lo[j]);
   }
   const int xs = s[0] > 0 ? lo[0] : lo[0] + cnt[0] - 1;
   const int ys = s[1] > 0 ? lo[1] : lo[1] + cnt[1] - 1;
@@ -165,12 +216,12 @@ __global__ void __launch_bounds__(kWave)
         const uint32_t f = flags[c];
         if (!(f & F_SOLID)) {
           T *rp = rec + lane * RW;
-          const T *sp = src + c * kSrcStride;
+          const gptr<const T> sp = src + c * kSrcStride;
           rp[0] = sp[0];
           rp[1] = sp[1];
           rp[2] = sp[2];
           rp[3] = DIM == 3 ? sp[3] : T(0);
-          rp[4] = g.tau_fb ? srct[c] : T(0);
+          rp[4] = tau_fb ? srct[c] : T(0);
           code = 0;
 #pragma unroll
           for (int j = 0; j < DIM; ++j) {
@@ -181,7 +232,7 @@ __global__ void __launch_bounds__(kWave)
             T w = (first && y1s) ? wall[c * 6 + 2 * j + pin[j]] : T(0);
             if (Y2WALL && !first && y2s) {
               c2 = T(0);
-              w = T(-0.5) * wall_at_y1(g, wall, j, s[j], pin[j], x, y, z);
+              w = T(-0.5) * wall_at_y1(dm, wall, j, s[j], pin[j], x, y, z);
             }
             rp[5 + 3 * j] = c1;
             rp[6 + 3 * j] = c2;
@@ -196,8 +247,8 @@ __global__ void __launch_bounds__(kWave)
     // Away from the domain faces they are plain loads of the current sweep;
     // only tiles touching a face resolve images.
     T L1[TT], L2[TT], B1[TT], B2[TT];
-    const int64_t Kp = g.Kpad;
-    T *hz = hc + (int64_t)(n1 * z) * n0 * Kp + kofs;  // plane z of the current sweep
+    const int64_t Kp = dm.Kpad;
+    const gptr<T> hz = hc + (int64_t)(n1 * z) * n0 * Kp + kofs;  // plane z of the current sweep
     const bool xin = xs - 2 * s[0] >= 0 && xs - 2 * s[0] < n0;
     const bool yin = ys - 2 * s[1] >= 0 && ys - 2 * s[1] < n1;
 #pragma unroll
@@ -209,8 +260,8 @@ __global__ void __launch_bounds__(kWave)
           L1[k] = hz[(int64_t)(y * n0 + xs - s[0]) * Kp];
           L2[k] = hz[(int64_t)(y * n0 + xs - 2 * s[0]) * Kp];
         } else {
-          L1[k] = upstream_fluid(g, hc, hp, 0, xs - s[0], y, z, kofs, kmir[0]);
-          L2[k] = upstream_fluid(g, hc, hp, 0, xs - 2 * s[0], y, z, kofs, kmir[0]);
+          L1[k] = upstream_fluid(dm, hc, hp, 0, xs - s[0], y, z, kofs, kmir[0]);
+          L2[k] = upstream_fluid(dm, hc, hp, 0, xs - 2 * s[0], y, z, kofs, kmir[0]);
         }
       }
       if (k < cnt[0]) {
@@ -219,12 +270,12 @@ __global__ void __launch_bounds__(kWave)
           B1[k] = hz[(int64_t)((ys - s[1]) * n0 + x) * Kp];
           B2[k] = hz[(int64_t)((ys - 2 * s[1]) * n0 + x) * Kp];
         } else {
-          B1[k] = upstream_fluid(g, hc, hp, 1, x, ys - s[1], z, kofs, kmir[1]);
-          B2[k] = upstream_fluid(g, hc, hp, 1, x, ys - 2 * s[1], z, kofs, kmir[1]);
+          B1[k] = upstream_fluid(dm, hc, hp, 1, x, ys - s[1], z, kofs, kmir[1]);
+          B2[k] = upstream_fluid(dm, hc, hp, 1, x, ys - 2 * s[1], z, kofs, kmir[1]);
         }
       }
     }
-    const bool zin = DIM == 3 && z - 2 * s[2] >= 0 && z - 2 * s[2] < g.n[2];
+    const bool zin = DIM == 3 && z - 2 * s[2] >= 0 && z - 2 * s[2] < dm.n[2];
     const int64_t zstep = (int64_t)n1 * n0 * Kp * s[2];
     __syncthreads();
     // --- the plane's anti-diagonals ---------------------------------------
@@ -243,12 +294,12 @@ __global__ void __launch_bounds__(kWave)
         if (DIM == 3 && i >= 0 && i < TT && i < cnt[0] && r < cnt[1]) {
           const int x = xs + i * s[0], y = ys + r * s[1];
           if (zin) {
-            const T *hv0 = hz + (int64_t)(y * n0 + x) * Kp;
+            const gptr<const T> hv0 = hz + (int64_t)(y * n0 + x) * Kp;
             Z1[r] = hv0[-zstep];
             Z2[r] = hv0[-2 * zstep];
           } else {
-            Z1[r] = upstream_fluid(g, hc, hp, 2, x, y, z - s[2], kofs, kmir[2]);
-            Z2[r] = upstream_fluid(g, hc, hp, 2, x, y, z - 2 * s[2], kofs, kmir[2]);
+            Z1[r] = upstream_fluid(dm, hc, hp, 2, x, y, z - s[2], kofs, kmir[2]);
+            Z2[r] = upstream_fluid(dm, hc, hp, 2, x, y, z - 2 * s[2], kofs, kmir[2]);
           }
         }
       }
@@ -262,7 +313,7 @@ __global__ void __launch_bounds__(kWave)
         T num = fma(rp[1], vv[0], rp[0]);
         num = fma(rp[2], vv[1], num);
         if (DIM == 3) num = fma(rp[3], vv[2], num);
-        if (g.tau_fb) num = fma(rp[4], vsqm, num);
+        if (tau_fb) num = fma(rp[4], vsqm, num);
         const T x1a = i >= 1 ? D1[r] : L1[r];
         const T x1b = i >= 2 ? D2[r] : (i == 1 ? L1[r] : L2[r]);
         const T x2a = r >= 1 ? D1[r >= 1 ? r - 1 : 0] : B1[i];
@@ -297,37 +348,52 @@ __device__ __forceinline__ double wave_sum(double v) {
 // a voxel's whole distribution are independent, so they are all in flight
 // together. Slots past the octant size load nothing and weigh 0.
 template <typename T, int DIM, int NS>
-__global__ void __launch_bounds__(kMomBlock) moments_kernel(Geo<T> g) {
+__global__ void __launch_bounds__(kMomBlock)
+    moments_kernel(const Geo<T> *__restrict__ G, const int *__restrict__ blk_off, int nprob) {
+  const int pb = owner_of(blk_off, nprob, blockIdx.x);
+  const Geo<T> &g = G[pb];
+  const int blk = blockIdx.x - blk_off[pb];
   const Ctl *ctl = g.ctl;
   if (ctl->stop) return;
   const int par = ctl->par, np = par ^ 1;
-  const T *h = g.h[np];
-  const double *uold = g.u[par];
-  double *rho_n = g.rho[np];
-  double *u_n = g.u[np];
-  T *src_n = g.src[np];
-  T *wall_n = g.wall[np];
+  const gptr<const T> h = as_global((const T *)(np ? g.h[1] : g.h[0]));
+  const gptr<const double> uold = as_global((const double *)(par ? g.u[1] : g.u[0]));
+  const gptr<double> rho_n = as_global(np ? g.rho[1] : g.rho[0]);
+  const gptr<double> u_n = as_global(np ? g.u[1] : g.u[0]);
+  const gptr<T> src_n = as_global(np ? g.src[1] : g.src[0]);
+  const gptr<T> srct_n = as_global(np ? g.srct[1] : g.srct[0]);
+  const gptr<T> wall_n = as_global(np ? g.wall[1] : g.wall[0]);
+  const gptr<const uint32_t> flags = as_global(g.flags);
+  const gptr<const double> wq = as_global(g.wq);
+  const gptr<double> part = as_global(g.part);
+  const int64_t N = g.N, Kpad = g.Kpad;
+  const int Ko = g.Ko, Ko_pad = g.Ko_pad, tau_fb = g.tau_fb, mom_blocks = g.mom_blocks;
+  const double nu = g.nu, Dj[3] = {g.D[0], g.D[1], g.D[2]};
   const int lane = threadIdx.x & (kWave - 1), wid = threadIdx.x / kWave;
   constexpr int WPB = kMomBlock / kWave;
-  const int64_t nw = (int64_t)gridDim.x * WPB;
+  const int64_t nw = (int64_t)mom_blocks * WPB;
+  // slots past the octant size read a valid neighbour (same cache lines) and
+  // weigh 0, so every load is unconditional and all of a voxel's loads are
+  // in flight together
   double wr[NS][2 + DIM];
-  bool ok[NS];
+  int qc[NS];
 #pragma unroll
   for (int m = 0; m < NS; ++m) {
     const int q = lane + m * kWave;
-    ok[m] = q < g.Ko;
+    const bool ok = q < Ko;
+    qc[m] = ok ? q : Ko - 1;
 #pragma unroll
-    for (int r = 0; r < 2 + DIM; ++r) wr[m][r] = ok[m] ? g.wq[r * g.Ko_pad + q] : 0.0;
+    for (int r = 0; r < 2 + DIM; ++r) wr[m][r] = ok ? wq[r * Ko_pad + q] : 0.0;
   }
   double mdu = 0, mu = 0, su = 0;
-  for (int64_t c = (int64_t)blockIdx.x * WPB + wid; c < g.N; c += nw) {
-    if (g.flags[c] & F_SOLID) continue;
-    const T *hc = h + c * g.Kpad + lane;
+  for (int64_t c = (int64_t)blk * WPB + wid; c < N; c += nw) {
+    if (flags[c] & F_SOLID) continue;
+    const gptr<const T> hc = h + c * Kpad;
     T hv[1 << DIM][NS];
 #pragma unroll
     for (int o = 0; o < (1 << DIM); ++o)
 #pragma unroll
-      for (int m = 0; m < NS; ++m) hv[o][m] = ok[m] ? hc[o * g.Ko_pad + m * kWave] : T(0);
+      for (int m = 0; m < NS; ++m) hv[o][m] = hc[o * Ko_pad + qc[m]];
     double r = 0, e = 0;
     double ph[3][2] = {{0, 0}, {0, 0}, {0, 0}};
 #pragma unroll
@@ -339,7 +405,7 @@ __global__ void __launch_bounds__(kMomBlock) moments_kernel(Geo<T> g) {
         r = fma(wr[m][0], x, r);
 #pragma unroll
         for (int j = 0; j < DIM; ++j) pj[j] = fma(wr[m][1 + j], x, pj[j]);
-        if (g.tau_fb) e = fma(wr[m][1 + DIM], x, e);
+        if (tau_fb) e = fma(wr[m][1 + DIM], x, e);
       }
 #pragma unroll
       for (int j = 0; j < DIM; ++j) ph[j][(o >> j) & 1] += pj[j];
@@ -350,22 +416,22 @@ __global__ void __launch_bounds__(kMomBlock) moments_kernel(Geo<T> g) {
       ph[j][0] = wave_sum(ph[j][0]);
       ph[j][1] = wave_sum(ph[j][1]);
     }
-    if (g.tau_fb) e = wave_sum(e);
+    if (tau_fb) e = wave_sum(e);
     if (lane == 0) {
       rho_n[c] = r;
-      T *sp = src_n + c * kSrcStride;
-      sp[0] = T(g.nu * r);
+      const gptr<T> sp = src_n + c * kSrcStride;
+      sp[0] = T(nu * r);
 #pragma unroll
       for (int j = 0; j < DIM; ++j) {
         const double uj = ph[j][0] - ph[j][1];
-        mdu = fmax(mdu, fabs(uj - uold[j * g.N + c]));
+        mdu = fmax(mdu, fabs(uj - uold[j * N + c]));
         mu = fmax(mu, fabs(uj));
-        u_n[j * g.N + c] = uj;
-        sp[1 + j] = T(2.0 * g.nu * uj);
-        wall_n[c * 6 + 2 * j] = T(ph[j][0] / g.D[j]);
-        wall_n[c * 6 + 2 * j + 1] = T(ph[j][1] / g.D[j]);
+        u_n[j * N + c] = uj;
+        sp[1 + j] = T(2.0 * nu * uj);
+        wall_n[c * 6 + 2 * j] = T(ph[j][0] / Dj[j]);
+        wall_n[c * 6 + 2 * j + 1] = T(ph[j][1] / Dj[j]);
       }
-      if (g.tau_fb) g.srct[np][c] = T(g.nu * ((2.0 / 3.0) * e - r));
+      if (tau_fb) srct_n[c] = T(nu * ((2.0 / 3.0) * e - r));
       su += ph[0][0] - ph[0][1];
     }
   }
@@ -383,14 +449,20 @@ __global__ void __launch_bounds__(kMomBlock) moments_kernel(Geo<T> g) {
       b = fmax(b, sh[w][1]);
       cc += sh[w][2];
     }
-    g.part[blockIdx.x * 4 + 0] = a;
-    g.part[blockIdx.x * 4 + 1] = b;
-    g.part[blockIdx.x * 4 + 2] = cc;
+    part[blk * 4 + 0] = a;
+    part[blk * 4 + 1] = b;
+    part[blk * 4 + 2] = cc;
   }
 }
 
-__global__ void __launch_bounds__(256) reduce_kernel(Ctl *ctl, const double *part, int nblocks, int64_t N) {
+template <typename T>
+__global__ void __launch_bounds__(256) reduce_kernel(const Geo<T> *__restrict__ G) {
+  const Geo<T> &g = G[blockIdx.x];
+  Ctl *ctl = g.ctl;
   if (ctl->stop) return;
+  const double *part = g.part;
+  const int nblocks = g.mom_blocks;
+  const int64_t N = g.N;
   __shared__ double sa[256], sb[256], sc[256];
   const int t = threadIdx.x;
   double a = 0, b = 0, c = 0;
@@ -445,7 +517,11 @@ __global__ void __launch_bounds__(256) reduce_kernel(Ctl *ctl, const double *par
   }
 }
 
-__global__ void arm_kernel(Ctl *ctl, double tol, int mode, int64_t max_iters) {
+template <typename T>
+__global__ void arm_kernel(const Geo<T> *__restrict__ G, int nprob, double tol, int mode, int64_t max_iters) {
+  const int p = blockIdx.x * blockDim.x + threadIdx.x;
+  if (p >= nprob) return;
+  Ctl *ctl = G[p].ctl;
   ctl->tol = tol;
   ctl->mode = mode;
   ctl->iter_limit = ctl->iter + max_iters;
@@ -559,7 +635,7 @@ __global__ void face_copy_kernel(Geo<T> g, int axis, int r, T *buf, int to_buf) 
     if (axis == 0) { x[0] = r; x[1] = (int)(f % g.n[1]); x[2] = (int)(f / g.n[1]); }
     else if (axis == 1) { x[1] = r; x[0] = (int)(f % g.n[0]); x[2] = (int)(f / g.n[0]); }
     else { x[2] = r; x[0] = (int)(f % g.n[0]); x[1] = (int)(f / g.n[0]); }
-    const int64_t c = cell_of(g, x[0], x[1], x[2]);
+    const int64_t c = cell_of(dom_of(g), x[0], x[1], x[2]);
     if (to_buf) buf[e] = h[c * g.Kpad + k];
     else h[c * g.Kpad + k] = buf[e];
   }
@@ -574,34 +650,38 @@ int grid_for(int64_t work, int block) {
 }  // namespace
 
 template <typename T, bool Y2WALL>
-void launch_sweep_rule(const Geo<T> &g, int diag, int items, hipStream_t st) {
-#define PDVM_SWEEP(D, X)                                                                              \
-  hipLaunchKernelGGL((sweep_kernel<T, D, X, Y2WALL>), dim3(items), dim3(kWave), 0, st, g, diag,     \
-                     g.flags, (const T *)g.src[0], (const T *)g.src[1], (const T *)g.srct[0],       \
-                     (const T *)g.srct[1], (const T *)g.wall[0], (const T *)g.wall[1], g.h[0],      \
-                     g.h[1])
-  if (g.dim == 2) {
-    if (g.tile[0] <= 4) PDVM_SWEEP(2, 4);
+void launch_sweep_rule(const Batch<T> &B, int diag, hipStream_t st) {
+  const int items = B.h_item_off[(size_t)diag * (B.nprob + 1) + B.nprob];
+  if (items == 0) return;
+  const int *off = B.d_item_off + (size_t)diag * (B.nprob + 1);
+#define PDVM_SWEEP(D, X)                                                                             \
+  hipLaunchKernelGGL((sweep_kernel<T, D, X, Y2WALL>), dim3(items), dim3(kWave), 0, st, B.d_geo, off, \
+                     B.nprob, diag)
+  if (B.dim == 2) {
+    if (B.tile_edge <= 4) PDVM_SWEEP(2, 4);
     else PDVM_SWEEP(2, 8);
   } else {
-    if (g.tile[0] <= 4) PDVM_SWEEP(3, 4);
+    if (B.tile_edge <= 4) PDVM_SWEEP(3, 4);
     else PDVM_SWEEP(3, 8);
   }
 #undef PDVM_SWEEP
 }
 
 template <typename T>
-hipError_t launch_sweep(const Geo<T> &g, int diag, int items, hipStream_t st) {
-  if (g.y2wall) launch_sweep_rule<T, true>(g, diag, items, st);
-  else launch_sweep_rule<T, false>(g, diag, items, st);
+hipError_t launch_sweep(const Batch<T> &B, int diag, hipStream_t st) {
+  if (B.y2wall) launch_sweep_rule<T, true>(B, diag, st);
+  else launch_sweep_rule<T, false>(B, diag, st);
   return hipGetLastError();
 }
 
 template <typename T>
-hipError_t launch_moments(const Geo<T> &g, hipStream_t st) {
-  const int ns = (g.Ko + kWave - 1) / kWave;
-#define PDVM_MOM(D, S) hipLaunchKernelGGL((moments_kernel<T, D, S>), dim3(g.mom_blocks), dim3(kMomBlock), 0, st, g)
-  if (g.dim == 2) {
+hipError_t launch_moments(const Batch<T> &B, hipStream_t st) {
+  const int ns = (B.Ko + kWave - 1) / kWave;
+  const int blocks = B.h_blk_off[B.nprob];
+#define PDVM_MOM(D, S)                                                                        \
+  hipLaunchKernelGGL((moments_kernel<T, D, S>), dim3(blocks), dim3(kMomBlock), 0, st, B.d_geo, \
+                     B.d_blk_off, B.nprob)
+  if (B.dim == 2) {
     if (ns <= 1) PDVM_MOM(2, 1);
     else if (ns <= 2) PDVM_MOM(2, 2);
     else if (ns <= 3) PDVM_MOM(2, 3);
@@ -619,13 +699,28 @@ hipError_t launch_moments(const Geo<T> &g, hipStream_t st) {
   return hipGetLastError();
 }
 
-hipError_t launch_reduce(Ctl *ctl, const double *part, int nblocks, int64_t N, hipStream_t st) {
-  hipLaunchKernelGGL(reduce_kernel, dim3(1), dim3(256), 0, st, ctl, part, nblocks, N);
+template <typename T>
+hipError_t launch_reduce(const Batch<T> &B, hipStream_t st) {
+  hipLaunchKernelGGL((reduce_kernel<T>), dim3(B.nprob), dim3(256), 0, st, B.d_geo);
   return hipGetLastError();
 }
 
-hipError_t launch_arm(Ctl *ctl, double tol, int mode, int64_t max_iters, hipStream_t st) {
-  hipLaunchKernelGGL(arm_kernel, dim3(1), dim3(1), 0, st, ctl, tol, mode, max_iters);
+template <typename T>
+__global__ void ctl_gather_kernel(const Geo<T> *__restrict__ G, int nprob, Ctl *out) {
+  const int p = blockIdx.x * blockDim.x + threadIdx.x;
+  if (p < nprob) out[p] = *G[p].ctl;
+}
+
+template <typename T>
+hipError_t launch_ctl_gather(const Batch<T> &B, Ctl *out, hipStream_t st) {
+  hipLaunchKernelGGL((ctl_gather_kernel<T>), dim3((B.nprob + 63) / 64), dim3(64), 0, st, B.d_geo, B.nprob, out);
+  return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_arm(const Batch<T> &B, double tol, int mode, int64_t max_iters, hipStream_t st) {
+  hipLaunchKernelGGL((arm_kernel<T>), dim3((B.nprob + 63) / 64), dim3(64), 0, st, B.d_geo, B.nprob, tol,
+                     mode, max_iters);
   return hipGetLastError();
 }
 
@@ -657,10 +752,16 @@ hipError_t launch_face_copy(const Geo<T> &g, int axis, int r, T *buf, int to_buf
   return hipGetLastError();
 }
 
-template hipError_t launch_sweep<double>(const Geo<double> &, int, int, hipStream_t);
-template hipError_t launch_sweep<float>(const Geo<float> &, int, int, hipStream_t);
-template hipError_t launch_moments<double>(const Geo<double> &, hipStream_t);
-template hipError_t launch_moments<float>(const Geo<float> &, hipStream_t);
+template hipError_t launch_sweep<double>(const Batch<double> &, int, hipStream_t);
+template hipError_t launch_sweep<float>(const Batch<float> &, int, hipStream_t);
+template hipError_t launch_moments<double>(const Batch<double> &, hipStream_t);
+template hipError_t launch_moments<float>(const Batch<float> &, hipStream_t);
+template hipError_t launch_reduce<double>(const Batch<double> &, hipStream_t);
+template hipError_t launch_reduce<float>(const Batch<float> &, hipStream_t);
+template hipError_t launch_arm<double>(const Batch<double> &, double, int, int64_t, hipStream_t);
+template hipError_t launch_ctl_gather<double>(const Batch<double> &, Ctl *, hipStream_t);
+template hipError_t launch_ctl_gather<float>(const Batch<float> &, Ctl *, hipStream_t);
+template hipError_t launch_arm<float>(const Batch<float> &, double, int, int64_t, hipStream_t);
 template hipError_t launch_init_state<double>(const Geo<double> &, const double *, const double *, hipStream_t);
 template hipError_t launch_init_state<float>(const Geo<float> &, const double *, const double *, hipStream_t);
 template hipError_t launch_diagnostics<double>(const Geo<double> &, double *, double *, hipStream_t);

@@ -76,6 +76,8 @@ EXPORTED = [
     "pdvm_halfrange_gh", "pdvm_workspace_bytes", "pdvm_create", "pdvm_set_initial",
     "pdvm_iterate", "pdvm_get_moments", "pdvm_get_flux", "pdvm_get_state",
     "pdvm_set_state", "pdvm_time_kernels", "pdvm_destroy", "pdvm_last_error",
+    "pdvm_batch_create", "pdvm_batch_size", "pdvm_batch_set_initial", "pdvm_batch_iterate",
+    "pdvm_batch_get_moments", "pdvm_batch_get_flux",
 ]
 
 _lib = None
@@ -109,6 +111,14 @@ def load():
     lib.pdvm_get_state.argtypes = [vp, vp, ctypes.POINTER(ctypes.c_size_t)]
     lib.pdvm_set_state.argtypes = [vp, vp, ctypes.c_size_t]
     lib.pdvm_time_kernels.argtypes = [vp, ctypes.c_int32, ctypes.POINTER(PdvmTiming)]
+    lib.pdvm_batch_create.argtypes = [ctypes.c_int32, ctypes.POINTER(PdvmConfig), vp, ctypes.POINTER(vp)]
+    lib.pdvm_batch_size.restype = ctypes.c_int32
+    lib.pdvm_batch_size.argtypes = [vp]
+    lib.pdvm_batch_set_initial.argtypes = [vp, ctypes.c_int32, _dp, _dp]
+    lib.pdvm_batch_iterate.argtypes = [vp, ctypes.c_int64, ctypes.c_double, ctypes.c_int32,
+                                       ctypes.POINTER(PdvmStats)]
+    lib.pdvm_batch_get_moments.argtypes = [vp, ctypes.c_int32, _dp, _dp, _dp, _dp]
+    lib.pdvm_batch_get_flux.argtypes = [vp, ctypes.c_int32, _dp, _dp, _dp]
     lib.pdvm_destroy.argtypes = [vp]
     lib.pdvm_last_error.restype = ctypes.c_char_p
     lib.pdvm_last_error.argtypes = [vp]
@@ -261,6 +271,96 @@ class Solver:
     def set_state(self, blob):
         buf = ctypes.create_string_buffer(blob, len(blob))
         self._check(load().pdvm_set_state(self._h, buf, len(blob)))
+
+    def time_kernels(self, iters=5):
+        t = PdvmTiming()
+        self._check(load().pdvm_time_kernels(self._h, int(iters), ctypes.byref(t)))
+        return {f: getattr(t, f) for f, _ in PdvmTiming._fields_}
+
+
+class Batch:
+    """Many problems iterated together on the current GPU (one graph replay per
+    iteration covers all of them; converged problems retire).
+
+    problems: list of (solid mask, kn) pairs -- masks of any size, same dim.
+    All problems share nv, precision, stencil rule and tau feedback.
+    """
+
+    def __init__(self, problems, nv, precision="fp32", jump=1.0, lateral="specular",
+                 tile=None, check_every=16, grid=None, stencil_rule=1, device=None):
+        import torch
+
+        lib = load()
+        if grid is None:
+            grid = [velocity_grid(int(m)) for m in nv]
+        self.shapes = [np.asarray(m).shape for m, _ in problems]
+        self.kns = [float(k) for _, k in problems]
+        cfgs = (PdvmConfig * len(problems))()
+        self._keep = []
+        for i, (m, kn) in enumerate(problems):
+            c, keep = make_config(m, nv, kn, jump, precision, lateral, False, tile, check_every,
+                                  grid, stencil_rule)
+            cfgs[i] = c
+            self._keep.append(keep)
+        self.device = torch.device("cuda", torch.cuda.current_device() if device is None else device)
+        self.stream = torch.cuda.Stream(device=self.device)
+        h = ctypes.c_void_p()
+        rc = lib.pdvm_batch_create(len(problems), cfgs, ctypes.c_void_p(self.stream.cuda_stream),
+                                   ctypes.byref(h))
+        if rc != PDVM_OK:
+            raise PdvmError(rc, _err())
+        self._h = h
+        self.n = len(problems)
+
+    def _check(self, rc, ok=(PDVM_OK,)):
+        if rc not in ok:
+            raise PdvmError(rc, _err(self._h))
+        return rc
+
+    def close(self):
+        if getattr(self, "_h", None):
+            load().pdvm_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def set_initial(self, i, rho=None, u=None):
+        r = None if rho is None else np.ascontiguousarray(rho, np.float64).reshape(-1)
+        uu = None if u is None else np.ascontiguousarray(u, np.float64).reshape(-1)
+        self._check(load().pdvm_batch_set_initial(self._h, int(i), _ptr(r), _ptr(uu)))
+
+    def iterate(self, max_iters, tol=0.0, stop_mode="field"):
+        st = (PdvmStats * self.n)()
+        mode = {"field": PDVM_STOP_FIELD, "paper": PDVM_STOP_PAPER_ERR}[stop_mode]
+        self._check(load().pdvm_batch_iterate(self._h, int(max_iters), float(tol), mode, st),
+                    ok=(PDVM_OK, PDVM_NOT_CONVERGED))
+        return [{"converged": bool(x.converged), "iters": x.iters, "total_iters": x.total_iters,
+                 "r": x.r, "err": x.err, "k": x.k, "Gp": x.gp, "seconds": x.seconds} for x in st]
+
+    def moments(self, i, diagnostics=False):
+        shape = self.shapes[i]
+        N = int(np.prod(shape))
+        dim = len(shape)
+        rho = np.zeros(N)
+        u = np.zeros(dim * N)
+        tau = np.zeros(N) if diagnostics else None
+        q = np.zeros(dim * N) if diagnostics else None
+        self._check(load().pdvm_batch_get_moments(self._h, int(i), _ptr(rho), _ptr(u), _ptr(tau), _ptr(q)))
+        out = [rho.reshape(shape), u.reshape((dim,) + shape)]
+        if diagnostics:
+            out += [tau.reshape(shape), q.reshape((dim,) + shape)]
+        return tuple(out)
+
+    def flux(self, i):
+        gp = ctypes.c_double()
+        k = ctypes.c_double()
+        sec = np.zeros(self.shapes[i][-1])
+        self._check(load().pdvm_batch_get_flux(self._h, int(i), ctypes.byref(gp), ctypes.byref(k), _ptr(sec)))
+        return gp.value, k.value, sec
 
     def time_kernels(self, iters=5):
         t = PdvmTiming()
