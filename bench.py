@@ -81,6 +81,20 @@ def roofline(tm, elem):
                                "achieved_gbs": per_iter / (tm["moments_ms_per_launch"] * 1e-3) / 1e9}}
 
 
+def copy_calibration(mib):
+    """A plain device copy of known size: each launch reads and writes
+    mib MiB, so FETCH_SIZE / WRITE_SIZE of this kernel give the counters'
+    scale."""
+    import torch
+    n = mib * (1 << 20) // 4
+    a = torch.ones(n, dtype=torch.float32, device="cuda")
+    b = torch.empty_like(a)
+    for _ in range(3):
+        b.copy_(a)
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_bytes_per_launch": n * 4, "launches": 3}), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -90,11 +104,16 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-extra", action="store_true", help="only the 512^2 FP64 line")
     ap.add_argument("--tile", type=int, nargs="*", default=None)
+    ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
+                    help="only copy MIB MiB device-to-device 3 times (scale for HBM byte counters)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU: this build has no multi-GPU path "
               "(--gpus %d requested)" % args.gpus, file=sys.stderr)
         sys.exit(2)
+    if args.copy_calibration:
+        copy_calibration(args.copy_calibration)
+        return
 
     import torch
     from paper_1712_01132_amd import geometry, poredvm

@@ -143,10 +143,13 @@ int pdvm_get_flux(pdvm_solver *s, double *gp, double *k, double *gp_section);
 int pdvm_get_state(pdvm_solver *s, void *buf, size_t *bytes);
 int pdvm_set_state(pdvm_solver *s, const void *buf, size_t bytes);
 
-/* Per-kernel timing over `iters` iterations on the solver's stream with HIP
- * events: average milliseconds per launch of the sweep kernel, of the moment
- * kernel and of the reduction kernel, and the number of sweep launches per
- * iteration; also the algorithmic bytes per iteration of the sweep (h written
+/* Per-kernel timing on the solver's stream with HIP events, over 2*iters
+ * iterations: in the first iters, an event pair brackets every launch, giving
+ * the average milliseconds per launch of the sweep kernel, of the moment kernel
+ * and of the reduction kernel. In the next iters, events bracket the whole
+ * sweep sequence and the whole iteration (sweep_ms_per_iter, iter_ms,
+ * including launch gaps). Also returns the number of sweep launches per
+ * iteration, and the algorithmic bytes per iteration of the sweep (h written
  * once per fluid voxel and velocity) and of the moment kernel (h read once).
  * Runs real iterations (the state advances). */
 typedef struct {

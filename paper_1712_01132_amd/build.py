@@ -1,4 +1,5 @@
-"""Build libporedvm.so (HIP kernels + host C ABI) for gfx950, in-tree."""
+"""Build libporedvm.so (HIP kernels + host C ABI of the solver and of the
+warm-start network) for gfx950, in-tree."""
 import os
 import subprocess
 import sys
@@ -6,11 +7,11 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libporedvm.so")
-SOURCES = ["dvm_kernels.hip", "dvm_host.cpp"]
+SOURCES = ["dvm_kernels.hip", "dvm_host.cpp", "unet_kernels.hip", "unet_host.cpp"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = [
     "-O3", "-std=c++17", "--offload-arch=gfx950", "-fPIC", "-shared",
-    # packed FP32 instructions stay off (see the design notes)
+    # no packed FP32 instructions: FP32 arithmetic stays scalar
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
     "-Wall", "-Wno-unused-function",
 ]

@@ -1114,49 +1114,72 @@ int pdvm_batch_get_flux(pdvm_solver *s, int32_t i, double *gp, double *k, double
 
 int pdvm_time_kernels(pdvm_solver *s, int32_t iters, pdvm_timing *out) {
   if (!s || !out || iters <= 0) { set_thread_error("bad arguments"); return PDVM_E_INVAL; }
-  int rc = arm(s, 0.0, 0, (int64_t)iters + 1);
+  int rc = arm(s, 0.0, 0, 2 * (int64_t)iters + 1);
   if (rc != PDVM_OK) return rc;
-  const int nd = s->precision == PDVM_FP64 ? s->bd.ndiag_max : s->bf.ndiag_max;
-  hipEvent_t ev[4];
+  const bool f64 = s->precision == PDVM_FP64;
+  const int nd = f64 ? s->bd.ndiag_max : s->bf.ndiag_max;
+  auto sweep_launch = [&](int d) { return f64 ? launch_sweep<double>(s->bd, d, s->stream) : launch_sweep<float>(s->bf, d, s->stream); };
+  auto mom_launch = [&]() { return f64 ? launch_moments<double>(s->bd, s->stream) : launch_moments<float>(s->bf, s->stream); };
+  auto red_launch = [&]() { return f64 ? launch_reduce<double>(s->bd, s->stream) : launch_reduce<float>(s->bf, s->stream); };
+  std::vector<hipEvent_t> ev(2 * (size_t)nd + 4, nullptr);
   for (auto &e : ev) HIPCHK(s, hipEventCreate(&e));
-  double sweep = 0, mom = 0, red = 0, tot = 0;
+  auto cleanup = [&]() { for (auto &e : ev) if (e) (void)hipEventDestroy(e); };
+  double sweep_seq = 0, sweep_kern = 0, mom = 0, red = 0, tot = 0;
   int launches = 0;
   for (int d = 0; d < nd; ++d) launches += s->h_item_off[(size_t)d * (s->n() + 1) + s->n()] > 0;
-  for (int it = 0; it < iters; ++it) {
-    HIPCHK(s, hipEventRecord(ev[0], s->stream));
-    for (int d = 0; d < nd; ++d) {
-      if (s->precision == PDVM_FP64) HIPCHK(s, launch_sweep<double>(s->bd, d, s->stream));
-      else HIPCHK(s, launch_sweep<float>(s->bf, d, s->stream));
+  hipError_t e = hipSuccess;
+  // pass 1: an event pair around every launch (kernel durations)
+  for (int it = 0; it < iters && e == hipSuccess; ++it) {
+    for (int d = 0; d < nd && e == hipSuccess; ++d) {
+      e = hipEventRecord(ev[2 * d], s->stream);
+      if (e == hipSuccess) e = sweep_launch(d);
+      if (e == hipSuccess) e = hipEventRecord(ev[2 * d + 1], s->stream);
     }
-    HIPCHK(s, hipEventRecord(ev[1], s->stream));
-    if (s->precision == PDVM_FP64) HIPCHK(s, launch_moments<double>(s->bd, s->stream));
-    else HIPCHK(s, launch_moments<float>(s->bf, s->stream));
-    HIPCHK(s, hipEventRecord(ev[2], s->stream));
-    if (s->precision == PDVM_FP64) HIPCHK(s, launch_reduce<double>(s->bd, s->stream));
-    else HIPCHK(s, launch_reduce<float>(s->bf, s->stream));
-    HIPCHK(s, hipEventRecord(ev[3], s->stream));
-    HIPCHK(s, hipEventSynchronize(ev[3]));
-    float a = 0, b = 0, c = 0;
-    HIPCHK(s, hipEventElapsedTime(&a, ev[0], ev[1]));
-    HIPCHK(s, hipEventElapsedTime(&b, ev[1], ev[2]));
-    HIPCHK(s, hipEventElapsedTime(&c, ev[2], ev[3]));
-    sweep += a;
+    if (e == hipSuccess) e = hipEventRecord(ev[2 * nd], s->stream);
+    if (e == hipSuccess) e = mom_launch();
+    if (e == hipSuccess) e = hipEventRecord(ev[2 * nd + 1], s->stream);
+    if (e == hipSuccess) e = red_launch();
+    if (e == hipSuccess) e = hipEventRecord(ev[2 * nd + 2], s->stream);
+    if (e == hipSuccess) e = hipEventSynchronize(ev[2 * nd + 2]);
+    for (int d = 0; d < nd && e == hipSuccess; ++d) {
+      float a = 0;
+      e = hipEventElapsedTime(&a, ev[2 * d], ev[2 * d + 1]);
+      sweep_kern += a;
+    }
+    float b = 0, c = 0;
+    if (e == hipSuccess) e = hipEventElapsedTime(&b, ev[2 * nd], ev[2 * nd + 1]);
+    if (e == hipSuccess) e = hipEventElapsedTime(&c, ev[2 * nd + 1], ev[2 * nd + 2]);
     mom += b;
     red += c;
-    tot += a + b + c;
   }
-  for (auto &e : ev) (void)hipEventDestroy(e);
-  const double es = s->precision == PDVM_FP64 ? 8.0 : 4.0;
+  // pass 2: the whole sweep sequence and the whole iteration, as replayed
+  for (int it = 0; it < iters && e == hipSuccess; ++it) {
+    e = hipEventRecord(ev[0], s->stream);
+    for (int d = 0; d < nd && e == hipSuccess; ++d) e = sweep_launch(d);
+    if (e == hipSuccess) e = hipEventRecord(ev[1], s->stream);
+    if (e == hipSuccess) e = mom_launch();
+    if (e == hipSuccess) e = red_launch();
+    if (e == hipSuccess) e = hipEventRecord(ev[2], s->stream);
+    if (e == hipSuccess) e = hipEventSynchronize(ev[2]);
+    float a = 0, b = 0;
+    if (e == hipSuccess) e = hipEventElapsedTime(&a, ev[0], ev[1]);
+    if (e == hipSuccess) e = hipEventElapsedTime(&b, ev[0], ev[2]);
+    sweep_seq += a;
+    tot += b;
+  }
+  cleanup();
+  if (e != hipSuccess) return s->fail(PDVM_E_HIP, "kernel timing: %s", hipGetErrorString(e));
+  const double es = f64 ? 8.0 : 4.0;
   double fluid = 0, vel = 0;
   for (auto &P : s->P) {
     fluid += (double)P.fluid;
     vel = (double)(P.Ko << P.dim);
   }
-  out->sweep_ms_per_iter = sweep / iters;
+  out->sweep_ms_per_iter = sweep_seq / iters;
   out->moments_ms_per_iter = mom / iters;
   out->iter_ms = tot / iters;
   out->sweep_launches_per_iter = launches;
-  out->sweep_ms_per_launch = sweep / iters / std::max(1, launches);
+  out->sweep_ms_per_launch = sweep_kern / iters / std::max(1, launches);
   out->moments_ms_per_launch = mom / iters;
   out->reduce_ms_per_launch = red / iters;
   out->fluid_cells = fluid;

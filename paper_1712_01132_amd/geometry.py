@@ -221,3 +221,14 @@ def workload_batch(count=64, seed0=1000, smin=128, smax=384):
         kn = float(np.exp(rng.uniform(np.log(0.05), np.log(20.0))))
         out.append((random_discs(s, s, eps, 4.0, 20.0, seed0 + b), kn))
     return out
+
+
+def workload_warmstart(seed, n=256):
+    """One sample of the warm-start data set: n x n discs r ~ U(4, 20),
+    porosity U(0.3, 0.6), Kn log-uniform in [0.05, 20] (L = n voxels).
+    Training seeds are 10000..11999, held-out seeds 20000..20199.
+    Returns (mask, kn)."""
+    rng = np.random.default_rng(seed)
+    eps = float(rng.uniform(0.3, 0.6))
+    kn = float(np.exp(rng.uniform(np.log(0.05), np.log(20.0))))
+    return random_discs(n, n, eps, 4.0, 20.0, seed), kn

@@ -11,24 +11,42 @@ import numpy as np
 import pytest
 
 from oracle import quadrature
-from paper_1712_01132_amd import geometry, poredvm
+from paper_1712_01132_amd import geometry, poredvm, warmstart
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 
 
-def _declared_symbols():
-    text = open(os.path.join(ROOT, "include", "poredvm.h")).read()
+def _declared_symbols(header):
+    text = open(os.path.join(ROOT, "include", header)).read()
     text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
     return sorted(set(re.findall(r"\b(pdvm_[a-z_]+)\s*\(", text)))
 
 
-def test_library_exports_every_declared_symbol():
+@pytest.mark.parametrize("header,exported", [("poredvm.h", poredvm.EXPORTED),
+                                             ("poredvm_unet.h", warmstart.EXPORTED)])
+def test_library_exports_every_declared_symbol(header, exported):
     lib = poredvm.load()
-    declared = _declared_symbols()
+    declared = _declared_symbols(header)
     assert declared, "no declarations found"
     for name in declared:
         assert hasattr(lib, name), name
-    assert sorted(declared) == sorted(poredvm.EXPORTED)
+    assert sorted(declared) == sorted(exported)
+
+
+def test_network_parameter_count_matches_layer_table():
+    n = sum(c * t * i + c for _, c, t, i in warmstart.LAYERS)
+    assert warmstart.num_params() == n
+    p = warmstart.init_params(0)
+    assert p.shape == (n,) and p.dtype == np.float32
+    assert all(w.shape == (c, t, i) for (w, b), (_, c, t, i) in zip(warmstart.split_params(p), warmstart.LAYERS))
+
+
+def test_network_rejects_bad_shapes_without_a_device():
+    lib = warmstart._lib()
+    h = ctypes.c_void_p()
+    assert lib.pdvm_unet_create(30, 32, 4, 0, None, ctypes.byref(h)) == poredvm.PDVM_E_INVAL
+    assert lib.pdvm_unet_create(32, 32, 64, 0, None, ctypes.byref(h)) == poredvm.PDVM_E_INVAL
+    assert b"multiples of 8" in lib.pdvm_unet_last_error(None)
 
 
 @pytest.mark.parametrize("n", [2, 4, 8, 16, 24, 32, 48, 64])

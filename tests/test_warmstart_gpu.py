@@ -1,0 +1,129 @@
+"""The warm-start network on the GPU (bf16 matrix-core kernels) against the
+CPU float64 reference that rounds to bfloat16 at the same places
+(oracle/unet_oracle.py).
+
+Tolerances. Both sides round the same values to bfloat16. They differ in
+the order and precision of the sums: FP32 on the GPU, exact float64 on the
+CPU.
+* A K-term sum in FP32 moves by about sqrt(K) 2^-24 of the sum of the
+  magnitudes of its terms. With K = 288..3456, and sums that cancel about
+  tenfold, that is about 5e-5 relative.
+* That flips a bfloat16 rounding for about 2 x 5e-5 / 2^-8, or about 2%, of
+  the activations. Each flip is one bfloat16 step (2^-8 relative), so about
+  6e-4 relative L2 per layer. This is the size measured at the output (7e-4
+  to 1e-3).
+* The gradients carry about twice as many rounded layers in their chain
+  (measured: 4e-3 in the worst layer).
+The bounds are 5e-3 for the forward pass and 2e-2 for the gradients."""
+import numpy as np
+import pytest
+
+from oracle import unet_oracle as U
+
+pytestmark = pytest.mark.gpu
+
+
+def _case(seed, n, B):
+    rng = np.random.default_rng(seed)
+    from paper_1712_01132_amd import geometry
+    solids, kns, rhos, us = [], [], [], []
+    for b in range(B):
+        m = geometry.random_discs(n, n, rng.uniform(0.4, 0.7), 2.0, max(3.0, n / 12), seed=seed * 100 + b)
+        solids.append(m)
+        kns.append(float(np.exp(rng.uniform(np.log(0.05), np.log(20)))))
+        rhos.append(rng.standard_normal((n, n)) * 0.2)
+        us.append(rng.standard_normal((2, n, n)) * 0.01)
+    p = U.num_params()
+    params = (rng.standard_normal(p) * 0.05).astype(np.float32)
+    return solids, kns, rhos, us, params
+
+
+def _net(n, B, params, solids, kns, rhos, us):
+    from paper_1712_01132_amd import warmstart
+    net = warmstart.Net(n, n, batch_max=B, dataset_max=B)
+    net.set_params(params)
+    for i in range(B):
+        net.set_sample(i, solids[i], kns[i], rhos[i], us[i])
+    return net
+
+
+def _rel(a, b):
+    return float(np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-300))
+
+
+@pytest.mark.parametrize("n,B", [(32, 2), (256, 1)])
+def test_forward_matches_oracle(n, B):
+    solids, kns, rhos, us, params = _case(1, n, B)
+    from paper_1712_01132_amd import warmstart
+    params = warmstart.init_params(3)
+    params[-3:] = [0.1, -0.2, 0.05]  # nonzero head biases
+    net = _net(n, B, params, solids, kns, rhos, us)
+    out = net.forward(list(range(B)))
+    net.close()
+    ref = U.forward(params, U.make_input(solids, kns)).numpy()
+    got = np.transpose(out[..., :3], (0, 3, 1, 2))
+    rel = _rel(got, ref)
+    mx = float(np.abs(got - ref).max() / np.abs(ref).max())
+    print("forward n=%d rel-L2 %.2e max %.2e" % (n, rel, mx))
+    assert np.all(out[..., 3] == 0)
+    assert rel <= 5e-3 and mx <= 2e-2
+
+
+def test_gradients_and_loss_match_oracle():
+    n, B = 32, 2
+    solids, kns, rhos, us, params = _case(2, n, B)
+    net = _net(n, B, params, solids, kns, rhos, us)
+    loss = net.train_step([0, 1], update=False)
+    g = net.grads()
+    net.close()
+    targets, ws = zip(*[U.make_targets(s, r, u, k) for s, r, u, k in zip(solids, rhos, us, kns)])
+    lref, gref = U.loss_and_grads(params, solids, kns, list(targets), list(ws))
+    print("loss gpu %.8e oracle %.8e" % (loss, lref))
+    assert abs(loss - lref) <= 1e-4 * abs(lref)
+    o = 0
+    worst = 0.0
+    for (cout, taps, cin) in U.ARCH:
+        nw = cout * taps * cin
+        rw = _rel(g[o:o + nw], gref[o:o + nw])
+        rb = _rel(g[o + nw:o + nw + cout], gref[o + nw:o + nw + cout])
+        worst = max(worst, rw, rb)
+        o += nw + cout
+    print("worst per-layer gradient rel-L2 %.2e" % worst)
+    assert worst <= 2e-2
+
+
+def test_adam_step_matches_oracle():
+    n, B = 32, 2
+    solids, kns, rhos, us, params = _case(3, n, B)
+    net = _net(n, B, params, solids, kns, rhos, us)
+    net.train_step([0, 1], lr=1e-3, update=False)
+    g = net.grads()
+    net.train_step([0, 1], lr=1e-3, update=True)  # same gradients, then the update
+    after = net.params()
+    net.close()
+    q, _, _ = U.adam_step(params, g, np.zeros(len(g)), np.zeros(len(g)), 1, 1e-3)
+    assert np.max(np.abs(after - q)) <= 1e-6
+
+
+def test_predict_inverts_the_normalisation():
+    n, B = 32, 1
+    solids, kns, rhos, us, params = _case(4, n, B)
+    net = _net(n, B, params, solids, kns, rhos, us)
+    out = net.forward([0])[0]
+    rho, u = net.predict(solids[0], kns[0], jump=1.0)
+    net.close()
+    r2, u2 = U.fields_from_output(np.transpose(out[..., :3], (2, 0, 1)).astype(np.float64), solids[0], kns[0])
+    assert np.allclose(rho, r2, rtol=1e-6, atol=1e-7) and np.allclose(u, u2, rtol=1e-6, atol=1e-9)
+
+
+def test_training_steps_reduce_the_loss():
+    n, B = 32, 4
+    solids, kns, rhos, us, _ = _case(5, n, B)
+    from paper_1712_01132_amd import warmstart
+    net = _net(n, B, warmstart.init_params(1), solids, kns, rhos, us)
+    first = net.train_step([0, 1, 2, 3], lr=1e-3)
+    for _ in range(30):
+        last = net.train_step([0, 1, 2, 3], lr=1e-3)
+    net.close()
+    print("loss %.4e -> %.4e" % (first, last))
+    assert np.isfinite(last) and last < 0.5 * first
