@@ -95,6 +95,79 @@ def copy_calibration(mib):
     print(json.dumps({"copy_bytes_per_launch": n * 4, "launches": 3}), flush=True)
 
 
+SWITCH_TOL = 2e-6      # FP32 phase ends here (its rounding floor on this workload is about 1e-6)
+FP32_MAX_ITERS = 40000
+TTR_MAX_ITERS = 60000
+
+
+def _ttr_fp64(mask, nv, kn, tile, tol=1e-6):
+    from paper_1712_01132_amd import poredvm
+    s = poredvm.Solver(mask, nv, kn, precision="fp64", tile=tile)
+    t0 = time.perf_counter()
+    r = s.iterate(TTR_MAX_ITERS, tol)
+    dt = time.perf_counter() - t0
+    s.close()
+    return {"seconds": dt, "iterations": r["total_iters"], "k": r["k"], "converged": r["converged"]}
+
+
+def _ttr_fp32_then_fp64(mask, nv, kn, tile, tile32, net=None, trial=50, tol=1e-6):
+    """FP32 iterations until r <= SWITCH_TOL, then the FP64 iteration from the
+    exact FP32 state. With a network: its prediction and rest are each run
+    `trial` iterations in FP32 and the start with the smaller residual goes on."""
+    from paper_1712_01132_amd import poredvm, warmstart
+    b = poredvm.Solver(mask, nv, kn, precision="fp64", tile=tile)
+    t0 = time.perf_counter()
+    used = False
+    if net is not None:
+        start = net.predict(mask, kn)
+        a, used, _, _ = warmstart.judged_start(mask, nv, kn, start, trial=trial, precision="fp32", tile=tile32)
+    else:
+        a = poredvm.Solver(mask, nv, kn, precision="fp32", tile=tile32)
+    r32 = a.iterate(FP32_MAX_ITERS, SWITCH_TOL)
+    b.set_state(a.get_state())
+    r64 = b.iterate(TTR_MAX_ITERS, tol)
+    dt = time.perf_counter() - t0
+    a.close()
+    b.close()
+    return {"seconds": dt, "iterations": r64["total_iters"], "fp32_iterations": r32["total_iters"],
+            "k": r64["k"], "converged": r64["converged"], "warm_start_used": used}
+
+
+def time_to_residual(mask, nv, kn, tile, tile32):
+    out = {}
+    log("time to r<=1e-6, FP64 from rest")
+    out["fp64"] = _ttr_fp64(mask, nv, kn, tile)
+    log("  %s" % json.dumps(out["fp64"]))
+    log("time to r<=1e-6, FP32 from rest, finished in FP64")
+    out["fp32_then_fp64"] = _ttr_fp32_then_fp64(mask, nv, kn, tile, tile32)
+    log("  %s" % json.dumps(out["fp32_then_fp64"]))
+    try:
+        from paper_1712_01132_amd import warmstart
+        params, _ = warmstart.load_weights()
+    except (OSError, KeyError) as e:
+        params = None
+        out["fp32_warm_then_fp64"] = {"skipped": "no trained weights (%s)" % e}
+    if params is not None:
+        net = warmstart.Net(mask.shape[1], mask.shape[0], batch_max=1, dataset_max=0)
+        net.set_params(params)
+        log("time to r<=1e-6, FP32 from the network's prediction (50-iteration trial against rest), "
+            "finished in FP64")
+        res = _ttr_fp32_then_fp64(mask, nv, kn, tile, tile32, net=net, trial=50)
+        net.close()
+        out["fp32_warm_then_fp64"] = res
+        log("  %s" % json.dumps(res))
+    k64 = out["fp64"]["k"]
+    for key in ("fp32_then_fp64", "fp32_warm_then_fp64"):
+        if "k" in out[key]:
+            out[key]["k_rel_diff_vs_fp64"] = abs(out[key]["k"] - k64) / abs(k64)
+            out[key]["speedup_vs_fp64"] = out["fp64"]["seconds"] / out[key]["seconds"]
+    out["note"] = ("seconds from the first iteration launch: network inference, the FP32 solvers' "
+                   "creation, the 50-iteration trial and the FP32->FP64 handover are included; the FP64 "
+                   "solver's creation and weight loading are not. r is the field residual "
+                   "max|du|/max|u| in FP64")
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -103,7 +176,8 @@ def main():
     ap.add_argument("--kn", type=float, default=1.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-extra", action="store_true", help="only the 512^2 FP64 line")
-    ap.add_argument("--tile", type=int, nargs="*", default=None)
+    ap.add_argument("--tile", type=int, nargs="*", default=None,
+                    help="sweep tile (default: chosen by the autotuner before the timed region)")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only copy MIB MiB device-to-device 3 times (scale for HBM byte counters)")
     args = ap.parse_args()
@@ -126,7 +200,10 @@ def main():
     K = nv[0] * nv[1]
     log("porosity %.4f, fluid voxels %d, velocities %d" % (1 - mask.mean(), fluid, K))
 
-    s = poredvm.Solver(mask, nv, args.kn, precision="fp64", tile=args.tile)
+    from paper_1712_01132_amd import autotune
+    tile64, tune64 = (args.tile, None) if args.tile else autotune.best_tile(mask, nv, "fp64", use_cache=False)
+    log("FP64 tile %s (autotuner: %s)" % (tile64, tune64))
+    s = poredvm.Solver(mask, nv, args.kn, precision="fp64", tile=list(tile64))
     ups, dt = timed_updates(s, fluid, K, args.steps, args.warmup)
     log("FP64: %d iterations in %.3f s: %.3f ms/iter, %.3e updates/s" % (args.steps, dt, 1e3 * dt / args.steps, ups))
     tm = s.time_kernels(10)
@@ -148,48 +225,44 @@ def main():
         "data": "synthetic",
         "config": {"workload": "rock2d: 512x512 seeded overlapping discs r~U(4,20), porosity 0.40, Kn=%g, "
                                "32x32 half-range Gauss-Hermite velocities, FP64" % args.kn,
-                   "fluid_voxels": fluid, "velocities": K, "parallelism": "1 GPU"},
+                   "fluid_voxels": fluid, "velocities": K, "parallelism": "1 GPU",
+                   "tile": list(tile64), "autotune_ms_per_iteration": tune64},
         "roofline": roofline(tm, 8),
     }
     if not args.no_extra:
         extra = {}
-        s = poredvm.Solver(mask, nv, args.kn, precision="fp32", tile=args.tile)
+        tile32, tune32 = (args.tile, None) if args.tile else autotune.best_tile(mask, nv, "fp32", use_cache=False)
+        s = poredvm.Solver(mask, nv, args.kn, precision="fp32", tile=list(tile32))
         u32, d32 = timed_updates(s, fluid, K, args.steps, args.warmup)
         t32 = s.time_kernels(10)
         s.close()
         extra["rock2d_fp32"] = {"updates_per_s": u32, "ms_per_step": 1e3 * d32 / args.steps,
+                                "tile": list(tile32), "autotune_ms_per_iteration": tune32,
                                 "roofline": roofline(t32, 4)}
         log("FP32: %.3e updates/s" % u32)
-        # time to residual 1e-6 (cold start), FP64 and FP32
-        ttr = {}
-        for prec in ("fp64", "fp32"):
-            s = poredvm.Solver(mask, nv, args.kn, precision=prec, tile=args.tile)
-            torch.cuda.synchronize()
-            t0 = time.perf_counter()
-            rr = s.iterate(5000, 1e-6)
-            torch.cuda.synchronize()
-            ttr[prec] = {"seconds": time.perf_counter() - t0, "iterations": rr["iters"], "k": rr["k"],
-                         "converged": rr["converged"]}
-            s.close()
-            log("time to r<=1e-6 (%s): %s" % (prec, json.dumps(ttr[prec])))
-        ttr["k_rel_diff_fp32_vs_fp64"] = abs(ttr["fp32"]["k"] - ttr["fp64"]["k"]) / abs(ttr["fp64"]["k"])
-        extra["rock2d_time_to_residual_1e-6"] = ttr
+        # time to residual 1e-6: FP64 from rest, and the FP32 forms finished in FP64
+        extra["rock2d_time_to_residual_1e-6"] = time_to_residual(mask, nv, args.kn, list(tile64), list(tile32))
         # 3D pack
         log("generating the 96^3 sphere pack (seed 7)")
         m3 = geometry.workload_pack3d(seed=7)
         f3 = int((m3 == 0).sum())
-        s = poredvm.Solver(m3, [16, 16, 16], 0.5, precision="fp32", tile=[4, 4, 4])
+        tile3, tune3 = autotune.best_tile(m3, [16, 16, 16], "fp32", iters=2, use_cache=False)
+        log("3D tile %s (autotuner: %s)" % (tile3, tune3))
+        s = poredvm.Solver(m3, [16, 16, 16], 0.5, precision="fp32", tile=list(tile3))
         u3, d3 = timed_updates(s, f3, 4096, 20, 3)
         t3 = s.time_kernels(3)
         s.close()
         extra["pack3d_fp32"] = {"updates_per_s": u3, "ms_per_step": 1e3 * d3 / 20, "fluid_voxels": f3,
+                                "tile": list(tile3), "autotune_ms_per_iteration": tune3,
                                 "velocities": 4096, "roofline": roofline(t3, 4)}
         log("3D pack FP32: %.3e updates/s, %s" % (u3, json.dumps(t3)))
         # 64-problem batch
         log("generating the 64-problem batch")
         probs = geometry.workload_batch(64)
         fb = sum(int((m == 0).sum()) for m, _ in probs)
-        b = poredvm.Batch(probs, [24, 24], precision="fp32", tile=[8, 8])
+        tileb, tuneb = autotune.best_tile(probs, [24, 24], "fp32", iters=3, use_cache=False)
+        log("batch tile %s (autotuner: %s)" % (tileb, tuneb))
+        b = poredvm.Batch(probs, [24, 24], precision="fp32", tile=list(tileb))
         b.iterate(3)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
@@ -199,9 +272,11 @@ def main():
         tb = b.time_kernels(3)
         b.close()
         extra["batch64_fp32"] = {"updates_per_s": fb * 576 * 30 / db, "ms_per_step": 1e3 * db / 30,
+                                 "tile": list(tileb), "autotune_ms_per_iteration": tuneb,
                                  "fluid_voxels": fb, "velocities": 576, "problems": 64,
                                  "roofline": roofline(tb, 4)}
         log("batch64 FP32: %.3e updates/s" % (fb * 576 * 30 / db))
+        extra["warmstart_unet"] = unet_timing()
         out["extra"] = extra
     if not args.no_cpu_baseline:
         log("timing the CPU oracle on the same workload")

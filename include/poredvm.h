@@ -73,8 +73,9 @@ typedef struct {
   int32_t tau_feedback;      /* 0 = isothermal source as in the paper's runs; 1 = feed the
                                 temperature term back (3D only, else PDVM_E_UNSUPPORTED) */
   int32_t check_every;       /* host polls convergence every this many iterations (0 = 16) */
-  int32_t tile[3];           /* sweep tile edge per axis in voxels (0 = library default;
-                                the x1 edge is capped at 32) */
+  int32_t tile[3];           /* sweep tile extent per axis in voxels (0 = default: 8 along
+                                x1, x1's value along x2, 8 along x3); x1 and x2 are capped
+                                at 8, x3 takes any depth */
   int32_t stencil_rule;      /* when the upwind stencil along an axis drops to first order
                                 (Sec. 2.3 says: when the upstream point is a boundary point):
                                 1 = when either of the two upstream images is solid;
@@ -139,7 +140,10 @@ int pdvm_get_flux(pdvm_solver *s, double *gp, double *k, double *gp_section);
 /* Checkpoint: everything the next iteration reads (moments, wall data, the
  * boundary layers of the distribution, counters). With buf == NULL, *bytes
  * receives the size. Restoring into a solver created with the same config
- * continues bitwise identically. PDVM_E_STATE on a size or problem mismatch. */
+ * continues bitwise identically. A checkpoint of the same problem taken at the
+ * other precision is accepted and converted value by value (FP32 -> FP64 is
+ * exact), so a run can be continued in FP64 after an FP32 phase.
+ * PDVM_E_STATE on a size or problem mismatch. */
 int pdvm_get_state(pdvm_solver *s, void *buf, size_t *bytes);
 int pdvm_set_state(pdvm_solver *s, const void *buf, size_t bytes);
 

@@ -360,12 +360,13 @@ int validate_and_build(const pdvm_config *cfg, Problem &P, std::string &err) {
 
   // sweep tiles and their diagonals (oriented tile coordinates sum to d)
   {
-    // (x1, x2): a square compiled edge (4 or 8); x3: any depth
-    int e = cfg->tile[0] > 0 ? cfg->tile[0] : 8;
-    e = e <= kTileEdge[0] ? kTileEdge[0] : kTileEdge[1];
+    // (x1, x2): at most the compiled edge (4 or 8) that covers both requested
+    // extents (default 8 x 8); x3: any depth
+    const int r0 = cfg->tile[0] > 0 ? cfg->tile[0] : 8, r1 = cfg->tile[1] > 0 ? cfg->tile[1] : r0;
+    const int e = std::max(r0, r1) <= kTileEdge[0] ? kTileEdge[0] : kTileEdge[1];
     for (int a = 0; a < 3; ++a) {
       int t = 1;
-      if (a < 2) t = e;
+      if (a < 2) t = std::min(a == 0 ? r0 : r1, e);
       else if (P.dim == 3) t = cfg->tile[2] > 0 ? cfg->tile[2] : 8;
       P.tile[a] = std::max(1, std::min(t, P.n[a]));
       P.ntile[a] = (P.n[a] + P.tile[a] - 1) / P.tile[a];
@@ -391,8 +392,9 @@ int validate_and_build(const pdvm_config *cfg, Problem &P, std::string &err) {
   fp = fnv1a(fp, P.n, sizeof(P.n));
   fp = fnv1a(fp, P.hv, sizeof(P.hv));
   fp = fnv1a(fp, P.flags.data(), P.flags.size() * 4);
-  fp = fnv1a(fp, P.absv.data(), P.absv.size() * 8);
-  fp = fnv1a(fp, P.wq.data(), P.wq.size() * 8);
+  // the velocity tables without their padding slots, which depend on the precision
+  for (size_t r = 0; r < P.absv.size() / P.Ko_pad; ++r) fp = fnv1a(fp, &P.absv[r * P.Ko_pad], (size_t)P.Ko * 8);
+  for (size_t r = 0; r < P.wq.size() / P.Ko_pad; ++r) fp = fnv1a(fp, &P.wq[r * P.Ko_pad], (size_t)P.Ko * 8);
   P.fingerprint = fp;
   return PDVM_OK;
 }
@@ -650,9 +652,9 @@ int finalize_batch(pdvm_solver *s) {
   B.nprob = n;
   B.dim = P0.dim;
   B.Ko = P0.Ko;
-  B.tile_edge = P0.tile[0] <= kTileEdge[0] ? kTileEdge[0] : kTileEdge[1];
+  B.tile_edge = kTileEdge[0];
   for (auto &P : s->P)
-    if (P.tile[0] > kTileEdge[0]) B.tile_edge = kTileEdge[1];
+    if (std::max(P.tile[0], P.tile[1]) > kTileEdge[0]) B.tile_edge = kTileEdge[1];
   B.y2wall = P0.stencil_rule == 0;
   B.ndiag_max = ndmax;
   B.d_geo = (const Geo<T> *)geo;
@@ -944,12 +946,60 @@ std::vector<int> face_layers(const Problem &P, int a) {
   return r;
 }
 
-size_t state_bytes(const Problem &P) {
-  const size_t es = P.precision == PDVM_FP64 ? 8 : 4;
+// Velocity slots per voxel at a precision: each octant's Ko slots padded to a
+// 128-byte line.
+int64_t kpad_of(const Problem &P, int precision) {
+  const int line = precision == PDVM_FP64 ? 16 : 32;
+  return (int64_t)((P.Ko + line - 1) / line * line) << P.dim;
+}
+
+size_t state_bytes(const Problem &P, int precision) {
+  const size_t es = precision == PDVM_FP64 ? 8 : 4;
   const size_t N = (size_t)P.N;
+  const size_t kp = (size_t)kpad_of(P, precision);
   size_t b = sizeof(StateHeader) + sizeof(Ctl) + N * 8 + 3 * N * 8 + N * kSrcStride * es + N * es + N * 6 * es;
-  for (int a = 0; a < P.dim; ++a) b += face_layers(P, a).size() * (N / P.n[a]) * (size_t)P.Kpad * es;
+  for (int a = 0; a < P.dim; ++a) b += face_layers(P, a).size() * (N / P.n[a]) * kp * es;
   return b;
+}
+size_t state_bytes(const Problem &P) { return state_bytes(P, P.precision); }
+
+// A checkpoint written at the other sweep precision, converted value by value
+// (FP32 -> FP64 is exact). Everything after the FP64 moments is stored in the
+// sweep precision, and the face layers also in that precision's slot layout.
+template <typename S, typename D>
+void convert_sections(const Problem &P, const char *in, char *out, int64_t kin, int64_t kout) {
+  const size_t N = (size_t)P.N;
+  const S *a = reinterpret_cast<const S *>(in);
+  D *b = reinterpret_cast<D *>(out);
+  const size_t flat = N * kSrcStride + N + N * 6;  // src, srct, wall
+  for (size_t i = 0; i < flat; ++i) b[i] = (D)a[i];
+  a += flat;
+  b += flat;
+  const int64_t kin_o = kin >> P.dim, kout_o = kout >> P.dim;
+  for (int ax = 0; ax < P.dim; ++ax) {
+    const size_t cells = face_layers(P, ax).size() * (N / P.n[ax]);
+    for (size_t c = 0; c < cells; ++c, a += kin, b += kout) {
+      for (int64_t k = 0; k < kout; ++k) b[k] = D(0);
+      for (int o = 0; o < (1 << P.dim); ++o)
+        for (int q = 0; q < P.Ko; ++q) b[o * kout_o + q] = (D)a[o * kin_o + q];
+    }
+  }
+}
+
+std::vector<char> convert_state(const Problem &P, const char *buf, int from) {
+  std::vector<char> out(state_bytes(P));
+  const size_t head = sizeof(StateHeader) + sizeof(Ctl) + (size_t)P.N * 8 * 4;
+  std::memcpy(out.data(), buf, head);
+  StateHeader h;
+  std::memcpy(&h, buf, sizeof(h));
+  h.precision = P.precision;
+  h.Kpad = (int32_t)P.Kpad;
+  std::memcpy(out.data(), &h, sizeof(h));
+  if (from == PDVM_FP64)
+    convert_sections<double, float>(P, buf + head, out.data() + head, kpad_of(P, from), P.Kpad);
+  else
+    convert_sections<float, double>(P, buf + head, out.data() + head, kpad_of(P, from), P.Kpad);
+  return out;
 }
 
 template <typename T>
@@ -1006,13 +1056,21 @@ int get_state_one(pdvm_solver *s, int i, void *buf, size_t *bytes) {
 
 int set_state_one(pdvm_solver *s, int i, const void *buf, size_t bytes) {
   const Problem &P = s->P[i];
-  const size_t need = state_bytes(P);
-  if (bytes != need) return s->fail(PDVM_E_STATE, "state has %zu bytes, this problem needs %zu", bytes, need);
   StateHeader h;
+  if (bytes < sizeof(h)) return s->fail(PDVM_E_STATE, "state too short");
   std::memcpy(&h, buf, sizeof(h));
-  if (h.magic != kMagic || h.dim != P.dim || h.n0 != P.n[0] || h.n1 != P.n[1] || h.n2 != P.n[2] || h.Kpad != P.Kpad ||
-      h.precision != P.precision || h.fluid != P.fluid || h.fingerprint != P.fingerprint)
+  const int from = h.precision == PDVM_FP32 ? PDVM_FP32 : PDVM_FP64;
+  const size_t need = state_bytes(P, from);
+  if (bytes != need) return s->fail(PDVM_E_STATE, "state has %zu bytes, this problem needs %zu", bytes, need);
+  if (h.magic != kMagic || h.dim != P.dim || h.n0 != P.n[0] || h.n1 != P.n[1] || h.n2 != P.n[2] ||
+      h.Kpad != kpad_of(P, from) || (h.precision != PDVM_FP64 && h.precision != PDVM_FP32) || h.fluid != P.fluid ||
+      h.fingerprint != P.fingerprint)
     return s->fail(PDVM_E_STATE, "state belongs to a different problem");
+  std::vector<char> conv;
+  if (from != P.precision) {
+    conv = convert_state(P, (const char *)buf, from);
+    buf = conv.data();
+  }
   Ctl c;
   std::memcpy(&c, (const char *)buf + sizeof(h), sizeof(Ctl));
   int rc = read_ctl(s);

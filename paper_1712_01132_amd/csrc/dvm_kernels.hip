@@ -210,12 +210,14 @@ __global__ void __launch_bounds__(kWave)
     if (lane < NC) {
       const int i = lane % TT, r = lane / TT;
       uint32_t code = R_SKIP;
+      T *rp = rec + lane * RW;
+#pragma unroll
+      for (int k = 0; k < RW; ++k) rp[k] = T(0);  // a skipped voxel computes 0
       if (i < cnt[0] && r < cnt[1]) {
         const int x = xs + i * s[0], y = ys + r * s[1];
         const int c = (y + n1 * z) * n0 + x;
         const uint32_t f = flags[c];
         if (!(f & F_SOLID)) {
-          T *rp = rec + lane * RW;
           const gptr<const T> sp = src + c * kSrcStride;
           rp[0] = sp[0];
           rp[1] = sp[1];
@@ -278,6 +280,14 @@ __global__ void __launch_bounds__(kWave)
     const bool zin = DIM == 3 && z - 2 * s[2] >= 0 && z - 2 * s[2] < dm.n[2];
     const int64_t zstep = (int64_t)n1 * n0 * Kp * s[2];
     __syncthreads();
+    // store addresses: row r of the tile starts at hrow[r]; voxel i of a row is icol[i] further
+    gptr<T> hrow[TT];
+    int64_t icol[TT];
+#pragma unroll
+    for (int k = 0; k < TT; ++k) {
+      hrow[k] = hz + (int64_t)((ys + k * s[1]) * n0 + xs) * Kp;
+      icol[k] = (int64_t)k * s[0] * Kp;
+    }
     // --- the plane's anti-diagonals ---------------------------------------
     T D1[TT], D2[TT];
 #pragma unroll
@@ -285,10 +295,12 @@ __global__ void __launch_bounds__(kWave)
 #pragma unroll
     for (int d = 0; d < 2 * TT - 1; ++d) {
       T Nw[TT];
+      uint32_t Nc[TT];
       T Z1[TT], Z2[TT];
 #pragma unroll
       for (int r = 0; r < TT; ++r) {
         Nw[r] = T(0);
+        Nc[r] = R_SKIP;
         Z1[r] = Z2[r] = T(0);
         const int i = d - r;
         if (DIM == 3 && i >= 0 && i < TT && i < cnt[0] && r < cnt[1]) {
@@ -307,8 +319,9 @@ __global__ void __launch_bounds__(kWave)
       for (int r = 0; r < TT; ++r) {
         const int i = d - r;
         if (i < 0 || i >= TT) continue;
+        // no branch before the store: the loads of all voxels of the
+        // anti-diagonal can be issued together (a skipped voxel's record is 0)
         const uint32_t code = __builtin_amdgcn_readfirstlane(rcode[i + TT * r]);
-        if (code & R_SKIP) continue;
         const T *rp = rec + (i + TT * r) * RW;
         T num = fma(rp[1], vv[0], rp[0]);
         num = fma(rp[2], vv[1], num);
@@ -321,10 +334,16 @@ __global__ void __launch_bounds__(kWave)
         num = fma(aa[0], fma(rp[5], x1a, fma(rp[6], x1b, rp[7])), num);
         num = fma(aa[1], fma(rp[8], x2a, fma(rp[9], x2b, rp[10])), num);
         if (DIM == 3) num = fma(aa[2], fma(rp[11], Z1[r], fma(rp[12], Z2[r], rp[13])), num);
-        const T hv = num * rd_lds[(code & 7u) * kWave + lane];
-        Nw[r] = hv;
-        const int x = xs + i * s[0], y = ys + r * s[1];
-        if (active) hz[(int64_t)(y * n0 + x) * Kp] = hv;
+        Nw[r] = num * rd_lds[(code & 7u) * kWave + lane];
+        Nc[r] = code;
+      }
+      // the stores after the whole anti-diagonal: the loop above stays free
+      // of control flow, so its loads and FMA chains interleave
+#pragma unroll
+      for (int r = 0; r < TT; ++r) {
+        const int i = d - r;
+        if (i < 0 || i >= TT) continue;
+        if (active && !(Nc[r] & R_SKIP)) hrow[r][icol[i]] = Nw[r];
       }
 #pragma unroll
       for (int r = 0; r < TT; ++r) {

@@ -56,7 +56,6 @@ int64_t logical_params() {
 }
 
 constexpr int kPixPerSplit = 4096;
-constexpr int kColsumSplits = 64;
 
 }  // namespace
 
@@ -78,7 +77,7 @@ struct pdvm_unet {
   uint8_t *pidx[3] = {};
   float *pred = nullptr, *dcat = nullptr, *part = nullptr, *bpart = nullptr, *loss_part = nullptr;
   uint16_t *gbuf = nullptr;
-  int64_t part_n = 0;
+  int64_t part_n = 0, bpart_n = 0;
   int loss_blocks = 0;
   // training set (slot smax is the inference slot)
   uint8_t *ds_solid = nullptr;
@@ -227,8 +226,10 @@ int backward(pdvm_unet *n, int B) {
     UCHK(n, launch_wgrad(w, splits, st));
     UCHK(n, mfma_end(n));
     UCHK(n, launch_sum_splits(n->part, splits, nw, n->grads + n->offw[l], st));
-    UCHK(n, launch_colsum(n->gbuf, P, rows, rows, n->bpart, kColsumSplits, st));
-    UCHK(n, launch_sum_splits(n->bpart, kColsumSplits, rows, n->grads + n->offb[l], st));
+    const int csplits = (int)((P + kColsumPix - 1) / kColsumPix);
+    if ((int64_t)csplits * rows > n->bpart_n) return n->fail(PDVM_E_INVAL, "internal: bias partial buffer too small");
+    UCHK(n, launch_colsum(n->gbuf, P, rows, rows, n->bpart, csplits, st));
+    UCHK(n, launch_sum_splits(n->bpart, csplits, rows, n->grads + n->offb[l], st));
     if (l == 0) break;
     // input gradient: a convolution of the output gradient with the flipped, transposed weights
     UCHK(n, launch_wt_back(n->wbf + n->offw[l], rows, cin, L.taps, n->wback, st));
@@ -370,6 +371,7 @@ int pdvm_unet_create(int32_t n1, int32_t n2, int32_t batch_max, int32_t dataset_
     const int64_t P = n->pix(batch_max, level_of(l));
     const int64_t splits = (P + kPixPerSplit - 1) / kPixPerSplit;
     n->part_n = std::max(n->part_n, splits * rows_of(l) * kLayer[l].taps * cin_of(l));
+    n->bpart_n = std::max(n->bpart_n, (P + kColsumPix - 1) / kColsumPix * rows_of(l));
   }
   const int64_t HW = (int64_t)n1 * n2;
   n->loss_blocks = (int)((batch_max * HW + 255) / 256);
@@ -394,7 +396,7 @@ int pdvm_unet_create(int32_t n1, int32_t n2, int32_t batch_max, int32_t dataset_
   add((void **)&n->pred, sizeof(float) * batch_max * HW * 4);
   add((void **)&n->dcat, sizeof(float) * dcat_n);
   add((void **)&n->part, sizeof(float) * n->part_n);
-  add((void **)&n->bpart, sizeof(float) * kColsumSplits * 256);
+  add((void **)&n->bpart, sizeof(float) * n->bpart_n);
   add((void **)&n->loss_part, sizeof(float) * n->loss_blocks);
   add((void **)&n->gbuf, 2 * (size_t)batch_max * HW * 32);
   add((void **)&n->ds_solid, (size_t)(dataset_max + 1) * HW);

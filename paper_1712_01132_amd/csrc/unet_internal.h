@@ -14,6 +14,7 @@ namespace pdvm_nn {
 
 constexpr int kMaxBatch = 32;
 constexpr int kInC = 8;  // input channels: solid, scaled log Kn, six zero pads
+constexpr int kColsumPix = 1024;  // rows per block of the column sums (bias gradients)
 
 struct Slots {
   int32_t s[kMaxBatch];
@@ -54,6 +55,7 @@ struct WgradArgs {
 hipError_t launch_conv(const ConvArgs &a, hipStream_t st);
 hipError_t launch_wgrad(const WgradArgs &a, int splits, hipStream_t st);
 hipError_t launch_sum_splits(const float *part, int splits, int64_t n, float *out, hipStream_t st);
+// splits = ceil(P / kColsumPix) blocks; part[split][C]
 hipError_t launch_colsum(const uint16_t *g, int64_t P, int C, int gstride, float *part, int splits, hipStream_t st);
 hipError_t launch_build_input(const uint8_t *solid_set, const float *feat_set, Slots sl, int B, int H, int W,
                               uint16_t *x, hipStream_t st);

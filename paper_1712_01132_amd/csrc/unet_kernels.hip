@@ -217,14 +217,24 @@ __global__ void sum_splits_kernel(const float *part, int splits, int64_t n, floa
   out[i] = s;
 }
 
-// Column sums of a bf16 matrix [P][stride] over the first C columns, per split.
-__global__ void colsum_kernel(const uint16_t *g, int64_t P, int C, int gstride, float *part, int64_t per) {
-  const int c = threadIdx.x;
-  if (c >= C) return;
-  const int64_t beg = blockIdx.x * per, end = min(P, beg + per);
+// Column sums of a bf16 matrix [P][gstride] over its first C columns (C divides
+// 256), per block of kColsumPix rows: thread t sums column t % C over rows
+// t / C, t / C + 256 / C, ...; then the block adds its 256 / C row lanes.
+__global__ void __launch_bounds__(256) colsum_kernel(const uint16_t *g, int64_t P, int C, int gstride, float *part) {
+  __shared__ float red[256];
+  const int t = threadIdx.x;
+  const int c = t % C, lanes = 256 / C;
+  const int64_t beg = (int64_t)blockIdx.x * kColsumPix;
+  const int64_t end = min(P, beg + kColsumPix);
   float s = 0.f;
-  for (int64_t p = beg; p < end; ++p) s += bf2f(g[p * gstride + c]);
-  part[(int64_t)blockIdx.x * C + c] = s;
+  for (int64_t p = beg + t / C; p < end; p += lanes) s += bf2f(g[p * gstride + c]);
+  red[t] = s;
+  __syncthreads();
+  if (t < C) {
+    float a = 0.f;
+    for (int j = 0; j < lanes; ++j) a += red[j * C + t];
+    part[(int64_t)blockIdx.x * C + t] = a;
+  }
 }
 
 // Input tensor [B][H][W][8]: solid (0/1), the scaled log Kn feature, zeros.
@@ -471,8 +481,7 @@ hipError_t launch_sum_splits(const float *part, int splits, int64_t n, float *ou
 }
 
 hipError_t launch_colsum(const uint16_t *g, int64_t P, int C, int gstride, float *part, int splits, hipStream_t st) {
-  const int64_t per = (P + splits - 1) / splits;
-  colsum_kernel<<<(unsigned)splits, 256, 0, st>>>(g, P, C, gstride, part, per);
+  colsum_kernel<<<(unsigned)splits, 256, 0, st>>>(g, P, C, gstride, part);
   return hipGetLastError();
 }
 

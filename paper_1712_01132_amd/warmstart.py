@@ -193,11 +193,61 @@ class Net:
         return {k: getattr(t, k) for k, _ in PdvmUnetTiming._fields_}
 
 
+def weight_mask():
+    """True at the convolution weights of the parameter vector, False at the biases."""
+    out = []
+    for _, cout, taps, cin in LAYERS:
+        out += [np.ones(cout * taps * cin, bool), np.zeros(cout, bool)]
+    return np.concatenate(out)
+
+
+def bf16_weights(p):
+    """The parameter vector with its convolution weights rounded to bfloat16
+    (nearest, ties to even), the values the network computes with; biases are
+    FP32 in the network and stay exact."""
+    p = np.array(p, np.float32)
+    u = p.view(np.uint32).astype(np.uint64)
+    r = ((u + 0x7FFF + ((u >> 16) & 1)) & 0xFFFF0000).astype(np.uint32).view(np.float32)
+    w = weight_mask()
+    p[w] = r[w]
+    return p
+
+
 def save_weights(p, path=WEIGHTS_PATH, **meta):
+    """Store trained parameters (weights as their bfloat16 values, which loses
+    nothing the network uses) in a compressed .npz with JSON metadata."""
     os.makedirs(os.path.dirname(path), exist_ok=True)
-    np.savez(path, params=np.asarray(p, np.float32), **{k: np.asarray(v) for k, v in meta.items()})
+    np.savez_compressed(path, params=bf16_weights(p), **{k: np.asarray(v) for k, v in meta.items()})
 
 
 def load_weights(path=WEIGHTS_PATH):
     with np.load(path, allow_pickle=False) as z:
         return z["params"].astype(np.float32), {k: z[k] for k in z.files if k != "params"}
+
+
+def judged_start(mask, nv, kn, start, trial=50, precision="fp32", jump=1.0, tile=None, grid=None):
+    """The iteration judges a guessed start: `trial` iterations from the start
+    fields (rho, u) and `trial` iterations from rest, each in its own solver.
+    The one whose velocity field still changes less per iteration
+    (r * max|u|, the absolute change at the last trial iteration) goes on and
+    is returned; the other is closed. Returns (solver, used_start, change_start,
+    change_rest)."""
+    kw = dict(precision=precision, jump=jump, tile=tile)
+    if grid is not None:
+        kw["grid"] = grid
+
+    def run(init):
+        s = poredvm.Solver(mask, nv, kn, **kw)
+        if init is not None:
+            s.set_initial(*init)
+        r = s.iterate(trial)["r"]
+        _, u = s.moments(diagnostics=False)
+        return s, r * float(np.abs(u).max())
+
+    a, da = run(start)
+    b, db = run(None)
+    if da < db:
+        b.close()
+        return a, True, da, db
+    a.close()
+    return b, False, da, db

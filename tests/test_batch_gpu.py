@@ -66,3 +66,22 @@ def test_batch_rejects_mixed_velocity_grids():
     rc = poredvm.load().pdvm_batch_create(2, arr, None, ctypes.byref(h))
     assert rc == poredvm.PDVM_E_INVAL
     assert "velocity grid" in poredvm._err()
+
+
+def test_autotuner_times_candidates_and_caches(tmp_path, monkeypatch):
+    from paper_1712_01132_amd import autotune
+    monkeypatch.setenv("PDVM_AUTOTUNE_CACHE", str(tmp_path / "tune.json"))
+    m = geometry.random_discs(64, 48, 0.5, 3.0, 6.0, seed=3)
+    tile, ms = autotune.best_tile(m, [8, 8], "fp32", iters=2)
+    assert tile in autotune.CANDIDATES_2D and len(ms) == len(autotune.CANDIDATES_2D)
+    assert all(v > 0 for v in ms.values())
+    again, _ = autotune.best_tile(m, [8, 8], "fp32", iters=2)  # from the cache
+    assert again == tile
+    # the chosen tile runs the same iteration as any other tile (bitwise)
+    res = []
+    for t in (tile, (4, 4)):
+        s = poredvm.Solver(m, [8, 8], 0.5, precision="fp32", tile=list(t))
+        s.iterate(5)
+        res.append(s.moments(diagnostics=False))
+        s.close()
+    assert np.array_equal(res[0][1], res[1][1])

@@ -88,6 +88,18 @@ def test_ragged_tiles_fp64_match_oracle(shape, nv, kn, tile, lateral, rule):
         compare(o, s, RTOL64)
 
 
+@pytest.mark.parametrize("tile,rule", [((4, 4, 4), 1), ((4, 3, 5), 1), ((4, 4, 2), 0), ((8, 8, 3), 1)])
+def test_ragged_tiles_3d_fp32_match_oracle(tile, rule):
+    """3D FP32: with 4 x 4 tiles the sweep keeps the two upstream planes in
+    registers; ragged tiles along every axis and both stencil rules."""
+    m = random_mask((9, 11, 13), 0.25, 17)
+    o, s = pair(m, [4, 4, 6], 0.7, precision="fp32", tile=tile, rule=rule)
+    for iters in (1, 7):
+        o.iterate(iters)
+        s.iterate(iters)
+        compare(o, s, RTOL32)
+
+
 def test_minimal_domain_and_grid():
     m = np.zeros((2, 2), np.uint8)
     o, s = pair(m, [2, 2], 0.5)
@@ -149,6 +161,32 @@ def test_checkpoint_resume_is_bitwise():
     with pytest.raises(poredvm.PdvmError):
         c = poredvm.Solver(m, [8, 8], 0.4)
         c.set_state(blob)
+
+
+def test_fp32_checkpoint_continues_in_fp64():
+    """An FP32 phase handed to an FP64 solver through the checkpoint: the FP64
+    continuation tracks the FP64 oracle to the FP32 tolerance, and the handover
+    itself loses nothing (FP32 -> FP64 is exact)."""
+    m = random_mask((24, 32), 0.3, 8)
+    o, s32 = pair(m, [8, 8], 0.5, precision="fp32")
+    s32.iterate(150)
+    blob = s32.get_state()
+    s64 = poredvm.Solver(m, [8, 8], 0.5, precision="fp64", grid=o.grid)
+    s64.set_state(blob)
+    r32, u32 = s32.moments(diagnostics=False)
+    r64, u64 = s64.moments(diagnostics=False)
+    assert np.array_equal(r32, r64) and np.array_equal(u32, u64)
+    back = s64.get_state()
+    s32b = poredvm.Solver(m, [8, 8], 0.5, precision="fp32", grid=o.grid)
+    s32b.set_state(back)  # and back: FP64 values that came from FP32 round to themselves
+    s32.iterate(10)
+    s32b.iterate(10)
+    for x, y in zip(s32.moments(diagnostics=False), s32b.moments(diagnostics=False)):
+        assert np.array_equal(x, y)
+    st = s64.iterate(250)
+    assert st["total_iters"] == 400
+    o.iterate(400)
+    compare(o, s64, RTOL32, diagnostics=False)
 
 
 def test_warm_start_matches_oracle():

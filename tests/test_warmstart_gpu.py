@@ -19,6 +19,7 @@ import numpy as np
 import pytest
 
 from oracle import unet_oracle as U
+from paper_1712_01132_amd import poredvm
 
 pytestmark = pytest.mark.gpu
 
@@ -127,3 +128,52 @@ def test_training_steps_reduce_the_loss():
     net.close()
     print("loss %.4e -> %.4e" % (first, last))
     assert np.isfinite(last) and last < 0.5 * first
+
+
+def _trained_net(n=256):
+    from paper_1712_01132_amd import warmstart
+    params, meta = warmstart.load_weights()
+    net = warmstart.Net(n, n, batch_max=1, dataset_max=0)
+    net.set_params(params)
+    return net
+
+
+def test_trained_network_saves_iterations_on_held_out_geometries():
+    """The committed network against rest, on the first 8 held-out geometries of
+    the training script (seeds 20000..20007, never trained on): FP32 batches
+    iterated to r <= 1e-5. The iteration itself is unchanged; only the start
+    differs."""
+    from paper_1712_01132_amd import geometry
+    probs = [geometry.workload_warmstart(20000 + i) for i in range(8)]
+    net = _trained_net()
+    starts = [net.predict(m, kn) for m, kn in probs]
+    net.close()
+    cold = poredvm.Batch(probs, [24, 24], precision="fp32", tile=[8, 8])
+    sc = cold.iterate(8000, 1e-5)
+    cold.close()
+    warm = poredvm.Batch(probs, [24, 24], precision="fp32", tile=[8, 8])
+    for i, (rho, u) in enumerate(starts):
+        warm.set_initial(i, rho, u)
+    sw = warm.iterate(8000, 1e-5)
+    warm.close()
+    ic = np.array([s["total_iters"] for s in sc])
+    iw = np.array([s["total_iters"] for s in sw])
+    print("cold", ic.tolist(), "warm", iw.tolist(), "ratio %.3f" % (iw.sum() / ic.sum()))
+    assert all(s["converged"] for s in sc + sw)
+    assert iw.sum() <= 0.95 * ic.sum() and np.sum(iw < ic) >= 6
+
+
+def test_iteration_judges_the_guess_and_falls_back_to_rest():
+    from paper_1712_01132_amd import geometry, warmstart
+    m, kn = geometry.workload_warmstart(20001)
+    net = _trained_net()
+    rho, u = net.predict(m, kn)
+    net.close()
+    s, used, rw, rc = warmstart.judged_start(m, [24, 24], kn, (rho, u), trial=50)
+    s.close()
+    assert used and rw < rc
+    # a wrong guess (reversed and amplified flow) loses the trial: the solve goes on from rest
+    s, used, rw, rc = warmstart.judged_start(m, [24, 24], kn, (-3.0 * rho, -3.0 * u), trial=50)
+    st = s.iterate(10)
+    s.close()
+    assert not used and rw >= rc and st["total_iters"] == 60
