@@ -67,14 +67,27 @@ def timed_updates(solver, fluid, K, steps, warmup):
     return fluid * K * steps / dt, dt
 
 
-def roofline(tm, elem):
+# HBM bytes per sweep launch from the rocprofv3 FETCH_SIZE / WRITE_SIZE passes
+# (scaled by a 1 GiB copy), valid only for the kernel source they were taken on
+TRAFFIC = {("c44205edcc9ebb6e", 8): 16.47e6}
+
+
+def kernel_source_hash():
+    import hashlib
+    p = os.path.join(ROOT, "paper_1712_01132_amd", "csrc", "dvm_kernels.hip")
+    with open(p, "rb") as f:
+        return hashlib.sha256(f.read()).hexdigest()[:16]
+
+
+def roofline(tm, elem, traffic_key=None):
     """Sweep kernel: algorithmic bytes = h written once per fluid voxel and
     velocity; per launch = that over the launches of one iteration."""
     per_iter = elem * tm["fluid_cells"] * tm["velocities"]
     per_launch = per_iter / tm["sweep_launches_per_iter"]
     achieved = per_launch / (tm["sweep_ms_per_launch"] * 1e-3) / 1e9
+    traffic = TRAFFIC.get(traffic_key) if traffic_key and traffic_key[0] == kernel_source_hash() else None
     return {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-            "frac": achieved / HBM_PEAK_GBS, "traffic": None, "kernel": "sweep_kernel",
+            "frac": achieved / HBM_PEAK_GBS, "traffic": traffic, "kernel": "sweep_kernel",
             "bytes_per_launch": per_launch, "launch_ms": tm["sweep_ms_per_launch"],
             "launches_per_iter": tm["sweep_launches_per_iter"],
             "moments_kernel": {"bytes_per_launch": per_iter, "launch_ms": tm["moments_ms_per_launch"],
@@ -131,6 +144,35 @@ def _ttr_fp32_then_fp64(mask, nv, kn, tile, tile32, net=None, trial=50, tol=1e-6
     b.close()
     return {"seconds": dt, "iterations": r64["total_iters"], "fp32_iterations": r32["total_iters"],
             "k": r64["k"], "converged": r64["converged"], "warm_start_used": used}
+
+
+BF16_PEAK_TFLOPS = 2500.0
+
+
+def unet_timing():
+    """The network's bf16 matrix-core kernels at the training shape (8 samples
+    of 256 x 256): forward pass and training step (forward, backward, Adam)."""
+    import numpy as np
+    from paper_1712_01132_amd import geometry, warmstart
+    B = 8
+    net = warmstart.Net(256, 256, batch_max=B, dataset_max=B)
+    net.set_params(warmstart.init_params(0))
+    for i in range(B):
+        m, kn = geometry.workload_warmstart(20000 + i)
+        net.set_sample(i, m, kn, np.zeros(m.shape), np.zeros((2,) + m.shape))
+    net.time(list(range(B)), reps=2)
+    t = net.time(list(range(B)), reps=10)
+    net.close()
+    fwd = t["forward_flop"] / (t["forward_ms"] * 1e-3) / 1e12
+    step_mfma = t["step_flop"] / (t["mfma_ms_per_step"] * 1e-3) / 1e12
+    res = {"batch": B, "size": [256, 256], "forward_ms": t["forward_ms"], "step_ms": t["step_ms"],
+           "forward_tflops": fwd, "step_tflops": t["step_flop"] / (t["step_ms"] * 1e-3) / 1e12,
+           "mfma_kernels_ms_per_step": t["mfma_ms_per_step"],
+           "roofline": {"bound": "mfma", "achieved": step_mfma, "peak": BF16_PEAK_TFLOPS, "unit": "TFLOP/s",
+                        "frac": step_mfma / BF16_PEAK_TFLOPS,
+                        "note": "convolution FLOP of one training step / summed durations of its MFMA kernels"}}
+    log("warm-start network: %s" % json.dumps(res))
+    return res
 
 
 def time_to_residual(mask, nv, kn, tile, tile32):
@@ -227,7 +269,7 @@ def main():
                                "32x32 half-range Gauss-Hermite velocities, FP64" % args.kn,
                    "fluid_voxels": fluid, "velocities": K, "parallelism": "1 GPU",
                    "tile": list(tile64), "autotune_ms_per_iteration": tune64},
-        "roofline": roofline(tm, 8),
+        "roofline": roofline(tm, 8, ("c44205edcc9ebb6e", 8) if list(tile64) == [8, 8] else None),
     }
     if not args.no_extra:
         extra = {}
