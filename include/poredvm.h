@@ -56,6 +56,13 @@ enum {
 enum { PDVM_FP64 = 0, PDVM_FP32 = 1 };                       /* sweep + h storage precision */
 enum { PDVM_LATERAL_SPECULAR = 0, PDVM_LATERAL_PERIODIC = 1 };
 enum { PDVM_STOP_FIELD = 0, PDVM_STOP_PAPER_ERR = 1 };
+/* Sweep schedules (results are bitwise identical between them):
+ * DIAGONALS: one launch per diagonal of sweep tiles (all octants, velocity
+ *            groups and problems of a batch in each launch);
+ * ROWS:      2D, one problem: one launch in which each wavefront pipelines a
+ *            row of tiles behind the row below it;
+ * AUTO:      ROWS for a single 2D problem, DIAGONALS otherwise. */
+enum { PDVM_SCHEDULE_AUTO = 0, PDVM_SCHEDULE_DIAGONALS = 1, PDVM_SCHEDULE_ROWS = 2 };
 
 typedef struct pdvm_solver pdvm_solver;
 
@@ -82,6 +89,8 @@ typedef struct {
                                 0 = only when the first one is (a solid second image then
                                     enters the second-order stencil with its wall value;
                                     this iteration can diverge on some geometries) */
+  int32_t sweep_schedule;    /* PDVM_SCHEDULE_*; ROWS with dim 3 or in a batch is
+                                PDVM_E_UNSUPPORTED */
 } pdvm_config;
 
 typedef struct {
@@ -185,6 +194,12 @@ int pdvm_batch_set_initial(pdvm_solver *s, int32_t i, const double *rho, const d
 int pdvm_batch_iterate(pdvm_solver *s, int64_t max_iters, double tol, int32_t stop_mode, pdvm_stats *out);
 int pdvm_batch_get_moments(pdvm_solver *s, int32_t i, double *rho, double *u, double *tau, double *q);
 int pdvm_batch_get_flux(pdvm_solver *s, int32_t i, double *gp, double *k, double *gp_section);
+
+/* The sweep schedule in use: 0 tile diagonals; 1 row pipeline with
+ * agent-scope synchronisation; 2 row pipeline with every velocity chain on one
+ * XCD (chosen only after a probe of the block placement confirms it);
+ * -1 for NULL. */
+int32_t pdvm_sweep_schedule(const pdvm_solver *s);
 
 void pdvm_destroy(pdvm_solver *s);
 

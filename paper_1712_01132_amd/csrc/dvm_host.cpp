@@ -172,7 +172,8 @@ size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
 
 template <typename T>
 struct Layout {
-  size_t ctl, flags, absv, av, vsqm, rden, wq, h[2], src[2], srct[2], wall[2], rho[2], u[2], part, tiles, offs, scratch, total;
+  size_t ctl, flags, absv, av, vsqm, rden, wq, h[2], src[2], srct[2], wall[2], rho[2], u[2], part, tiles, offs, scratch,
+      progress, total;
 };
 
 struct Problem {
@@ -186,6 +187,7 @@ struct Problem {
   int mom_blocks = 0;
   double nu = 0, kn = 0, jump = 1, D[3] = {0, 0, 0};
   int lateral_periodic = 0, tau_fb = 0, precision = 0, check_every = 16, stencil_rule = 1;
+  int schedule = 0;  // sweep schedule requested (PDVM_SCHEDULE_*)
   std::vector<uint32_t> flags;
   std::vector<double> absv, wq, vsqm, rden;   // host FP64 tables, [rows][Ko_pad]
   std::vector<int32_t> diag_tiles, diag_off;
@@ -224,6 +226,9 @@ int validate_and_build(const pdvm_config *cfg, Problem &P, std::string &err) {
   P.lateral_periodic = cfg->lateral_bc == PDVM_LATERAL_PERIODIC;
   P.tau_fb = cfg->tau_feedback ? 1 : 0;
   P.check_every = cfg->check_every > 0 ? cfg->check_every : 16;
+  if (cfg->sweep_schedule < 0 || cfg->sweep_schedule > 2) { err = "sweep_schedule must be 0, 1 or 2"; return PDVM_E_INVAL; }
+  P.schedule = cfg->sweep_schedule;
+  if (P.schedule == PDVM_SCHEDULE_ROWS && cfg->dim != 2) { err = "the row-pipeline sweep is 2D only"; return PDVM_E_UNSUPPORTED; }
   if (cfg->stencil_rule != 0 && cfg->stencil_rule != 1) { err = "stencil_rule must be 0 or 1"; return PDVM_E_INVAL; }
   P.stencil_rule = cfg->stencil_rule;
 
@@ -424,6 +429,7 @@ Layout<T> make_layout(const Problem &P) {
   L.tiles = take(P.diag_tiles.size() * 4);
   L.offs = take(P.diag_off.size() * 4);
   L.scratch = take(8 * N * 8);  // tau, q (3), rho, u (3) staging
+  L.progress = take((size_t)(P.ngroups << P.dim) * P.ntile[1] * 4);  // row-pipeline counters
   L.total = o;
   return L;
 }
@@ -517,6 +523,8 @@ struct pdvm_solver {
   Ctl *host_ctl = nullptr;         // pinned, one per problem
   hipGraphExec_t graph = nullptr;
   int graph_iters = 0;
+  bool rows = false;               // the sweep is one row-pipeline launch (2D, single problem)
+  bool rows_local = false;         // ... whose chains each run on one XCD (probed)
   std::string err;
   int n() const { return (int)P.size(); }
   int fail(int code, const char *fmt, ...) {
@@ -589,6 +597,7 @@ int setup_problem(pdvm_solver *s, int i) {
   g.diag_tiles = (const int32_t *)(b + L.tiles);
   g.diag_off = (const int32_t *)(b + L.offs);
   g.ndiag = P.ndiag;
+  g.progress = (int32_t *)(b + L.progress);
   s->D[i].scratch = (double *)(b + L.scratch);
   geos<T>(s)[i] = g;
 
@@ -668,9 +677,22 @@ int finalize_batch(pdvm_solver *s) {
 }
 
 template <typename T>
+int enqueue_sweep(pdvm_solver *s) {
+  const Batch<T> &B = batch<T>(s);
+  if (s->rows) {
+    const Problem &P = s->P[0];
+    HIPCHK(s, launch_sweep_rows<T>(B, P.ngroups << P.dim, P.ntile[1], s->rows_local, s->stream));
+  } else {
+    for (int d = 0; d < B.ndiag_max; ++d) HIPCHK(s, launch_sweep<T>(B, d, s->stream));
+  }
+  return PDVM_OK;
+}
+
+template <typename T>
 int enqueue_iteration(pdvm_solver *s) {
   const Batch<T> &B = batch<T>(s);
-  for (int d = 0; d < B.ndiag_max; ++d) HIPCHK(s, launch_sweep<T>(B, d, s->stream));
+  const int rc = enqueue_sweep<T>(s);
+  if (rc != PDVM_OK) return rc;
   HIPCHK(s, launch_moments<T>(B, s->stream));
   HIPCHK(s, launch_reduce<T>(B, s->stream));
   return PDVM_OK;
@@ -724,6 +746,30 @@ int check_index(pdvm_solver *s, int i) {
 bool same_velocity_grid(const Problem &a, const Problem &b) {
   return a.dim == b.dim && a.Ko == b.Ko && a.Ko_pad == b.Ko_pad && a.absv == b.absv && a.wq.size() == b.wq.size() &&
          std::equal(a.wq.begin(), a.wq.begin() + a.Ko_pad, b.wq.begin());
+}
+
+// Whether every chain of the row pipeline (blocks c, c + nchains, ...) runs on
+// a single XCD: run the pipeline's grid once with a kernel that records each
+// block's XCD. Needs at least two distinct XCDs in the record (so the register
+// read is live) and one XCD per chain.
+int probe_xcd_locality(pdvm_solver *s) {
+  const Problem &P = s->P[0];
+  const int nchains = P.ngroups << P.dim, blocks = nchains * P.ntile[1];
+  uint32_t *d = nullptr;
+  if (hipMalloc(&d, sizeof(uint32_t) * blocks) != hipSuccess) return s->fail(PDVM_E_NOMEM, "probe allocation failed");
+  std::vector<uint32_t> h(blocks);
+  hipError_t e = launch_xcd_probe(d, blocks, s->stream);
+  if (e == hipSuccess) e = hipMemcpyAsync(h.data(), d, sizeof(uint32_t) * blocks, hipMemcpyDeviceToHost, s->stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(s->stream);
+  (void)hipFree(d);
+  if (e != hipSuccess) return s->fail(PDVM_E_HIP, "XCD probe: %s", hipGetErrorString(e));
+  bool local = true, several = false;
+  for (int b = 0; b < blocks; ++b) {
+    local = local && h[b] == h[b % nchains];
+    several = several || h[b] != h[0];
+  }
+  s->rows_local = local && several;
+  return PDVM_OK;
 }
 
 int create_common(const pdvm_config *cfgs, int n, void *dev_workspace, size_t ws_bytes, void *hip_stream,
@@ -796,6 +842,23 @@ int create_common(const pdvm_config *cfgs, int n, void *dev_workspace, size_t ws
     g_thread_error = s->err;
     pdvm_destroy(s);
     return rc;
+  }
+  const Problem &P0 = s->P[0];
+  if (P0.schedule == PDVM_SCHEDULE_ROWS && n > 1) {
+    set_thread_error("the row-pipeline sweep serves a single problem; batches sweep by tile diagonals");
+    pdvm_destroy(s);
+    return PDVM_E_UNSUPPORTED;
+  }
+  s->rows = n == 1 && P0.dim == 2 && P0.schedule != PDVM_SCHEDULE_DIAGONALS;
+  if (s->rows) {
+    const int rc2 = probe_xcd_locality(s);
+    if (rc2 != PDVM_OK) {
+      g_thread_error = s->err;
+      pdvm_destroy(s);
+      return rc2;
+    }
+    // automatic choice: the row pipeline only with the cheap XCD-local protocol
+    if (!s->rows_local && P0.schedule == PDVM_SCHEDULE_AUTO) s->rows = false;
   }
   *out = s;
   return PDVM_OK;
@@ -874,6 +937,7 @@ int iterate_batch(pdvm_solver *s, int64_t max_iters, double tol, int32_t stop_mo
       out[i].seconds = secs;
       out[i].converged = c.status == 1;
     }
+    if (c.fault) return s->fail(PDVM_E_HIP, "problem %d: a row-pipeline sweep gave up waiting for its upstream row", i);
     if (c.status == -4) worst = PDVM_E_NONFINITE;
     else if (c.status != 1 && worst == PDVM_OK) worst = PDVM_NOT_CONVERGED;
   }
@@ -1175,8 +1239,15 @@ int pdvm_time_kernels(pdvm_solver *s, int32_t iters, pdvm_timing *out) {
   int rc = arm(s, 0.0, 0, 2 * (int64_t)iters + 1);
   if (rc != PDVM_OK) return rc;
   const bool f64 = s->precision == PDVM_FP64;
-  const int nd = f64 ? s->bd.ndiag_max : s->bf.ndiag_max;
-  auto sweep_launch = [&](int d) { return f64 ? launch_sweep<double>(s->bd, d, s->stream) : launch_sweep<float>(s->bf, d, s->stream); };
+  const int nd = s->rows ? 1 : (f64 ? s->bd.ndiag_max : s->bf.ndiag_max);
+  auto sweep_launch = [&](int d) {
+    if (s->rows) {
+      const Problem &P = s->P[0];
+      return f64 ? launch_sweep_rows<double>(s->bd, P.ngroups << P.dim, P.ntile[1], s->rows_local, s->stream)
+                 : launch_sweep_rows<float>(s->bf, P.ngroups << P.dim, P.ntile[1], s->rows_local, s->stream);
+    }
+    return f64 ? launch_sweep<double>(s->bd, d, s->stream) : launch_sweep<float>(s->bf, d, s->stream);
+  };
   auto mom_launch = [&]() { return f64 ? launch_moments<double>(s->bd, s->stream) : launch_moments<float>(s->bf, s->stream); };
   auto red_launch = [&]() { return f64 ? launch_reduce<double>(s->bd, s->stream) : launch_reduce<float>(s->bf, s->stream); };
   std::vector<hipEvent_t> ev(2 * (size_t)nd + 4, nullptr);
@@ -1184,7 +1255,9 @@ int pdvm_time_kernels(pdvm_solver *s, int32_t iters, pdvm_timing *out) {
   auto cleanup = [&]() { for (auto &e : ev) if (e) (void)hipEventDestroy(e); };
   double sweep_seq = 0, sweep_kern = 0, mom = 0, red = 0, tot = 0;
   int launches = 0;
-  for (int d = 0; d < nd; ++d) launches += s->h_item_off[(size_t)d * (s->n() + 1) + s->n()] > 0;
+  if (s->rows) launches = 1;
+  else
+    for (int d = 0; d < nd; ++d) launches += s->h_item_off[(size_t)d * (s->n() + 1) + s->n()] > 0;
   hipError_t e = hipSuccess;
   // pass 1: an event pair around every launch (kernel durations)
   for (int it = 0; it < iters && e == hipSuccess; ++it) {
@@ -1245,6 +1318,11 @@ int pdvm_time_kernels(pdvm_solver *s, int32_t iters, pdvm_timing *out) {
   out->sweep_bytes_per_iter = es * fluid * vel;
   out->moments_bytes_per_iter = es * fluid * vel;
   return PDVM_OK;
+}
+
+int32_t pdvm_sweep_schedule(const pdvm_solver *s) {
+  if (!s) return -1;
+  return s->rows ? (s->rows_local ? 2 : 1) : 0;
 }
 
 void pdvm_destroy(pdvm_solver *s) {

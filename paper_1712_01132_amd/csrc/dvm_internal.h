@@ -33,6 +33,8 @@ struct Ctl {
   int32_t stop;
   int32_t status;       // 0 running, 1 converged, 2 budget reached, -4 non-finite
   int32_t mode;         // 0 field residual, 1 paper Err(l)
+  int32_t fault;        // 1 if a row-pipeline sweep gave up waiting (results invalid)
+  int32_t pad_;
   int64_t iter;         // iterations since the initial state
   int64_t iter_limit;   // stop (status 2) when iter reaches this
   double tol;
@@ -69,6 +71,17 @@ struct Geo {
   const int32_t *diag_tiles;  // [count][4] oriented tile coordinates (x1, x2, x3, pad)
   const int32_t *diag_off;    // [ndiag + 1]
   int32_t ndiag;
+  // Resolved for the next iteration by the kernels that change the state
+  // (arm: from the control block; reduce: after its parity decision), so that
+  // a sweep or moment launch needs one descriptor read and no control-block
+  // read before its data loads.
+  int32_t run = 0;            // 0 once the problem stopped (converged, budget, non-finite)
+  int32_t cpar = 0;           // the control block's `par`
+  T *hcur = nullptr;          // h being swept this iteration: h[par ^ 1]
+  const T *hprev = nullptr;   // h of the previous iteration: h[par]
+  const T *srccur = nullptr, *srctcur = nullptr, *wallcur = nullptr;  // src, srct, wall [par]
+  int32_t seq = 0;            // advanced by every arm and reduction: stamps of the row pipeline
+  int32_t *progress = nullptr;  // [ntile1][chains] tiles completed per row (row-pipeline sweep)
 };
 
 // Square sweep tile edges in (x1, x2) compiled into the kernel; the host
@@ -92,6 +105,12 @@ struct Batch {
 // Kernel launchers (dvm_kernels.hip). All enqueue on `st`.
 template <typename T>
 hipError_t launch_sweep(const Batch<T> &B, int diag, hipStream_t st);
+// The whole sweep of a single 2D problem as one row-pipeline launch; `local`:
+// every chain's rows run on one XCD (checked with launch_xcd_probe).
+template <typename T>
+hipError_t launch_sweep_rows(const Batch<T> &B, int nchains, int nrows, bool local, hipStream_t st);
+// out[b] = the XCD that block b of a `blocks`-block grid runs on.
+hipError_t launch_xcd_probe(uint32_t *out, int blocks, hipStream_t st);
 template <typename T>
 hipError_t launch_moments(const Batch<T> &B, hipStream_t st);
 template <typename T>

@@ -139,30 +139,35 @@ __global__ void __launch_bounds__(kWave)
   __shared__ T rd_lds[8 * kWave];
   __shared__ T rec[NC * RW];
   __shared__ uint32_t rcode[NC];
-  const int p = owner_of(item_off, nprob, blockIdx.x);
+  const int p = nprob > 1 ? owner_of(item_off, nprob, blockIdx.x) : 0;
   const Geo<T> &G_ = G[p];
-  const Ctl *ctl = G_.ctl;
-  if (ctl->stop) return;  // converged problems retire
-  const int par = ctl->par;
+  if (!G_.run) return;  // converged problems retire
   // every per-problem value is read once here; the loops below see registers
   const Dom<T> dm = dom_of(G_);
-  const gptr<const int32_t> diag_off = as_global(G_.diag_off);
-  const gptr<const int32_t> diag_tiles = as_global(G_.diag_tiles);
   const int ngroups = G_.ngroups, Ko = G_.Ko, Ko_pad = G_.Ko_pad, tau_fb = G_.tau_fb;
   const int tile[3] = {G_.tile[0], G_.tile[1], G_.tile[2]};
   const int ntile[3] = {G_.ntile[0], G_.ntile[1], G_.ntile[2]};
   const gptr<const T> absv = as_global(G_.absv), avv = as_global(G_.av), rden = as_global(G_.rden),
                       vsq = as_global(G_.vsqm);
-  const gptr<T> hc = as_global(par ? G_.h[0] : G_.h[1]);
-  const gptr<const T> hp = as_global((const T *)(par ? G_.h[1] : G_.h[0]));
-  const gptr<const T> src = as_global((const T *)(par ? G_.src[1] : G_.src[0]));
-  const gptr<const T> srct = as_global((const T *)(par ? G_.srct[1] : G_.srct[0]));
-  const gptr<const T> wall = as_global((const T *)(par ? G_.wall[1] : G_.wall[0]));
+  const gptr<T> hc = as_global(G_.hcur);
+  const gptr<const T> hp = as_global(G_.hprev);
+  const gptr<const T> src = as_global(G_.srccur);
+  const gptr<const T> srct = as_global(G_.srctcur);
+  const gptr<const T> wall = as_global(G_.wallcur);
   const gptr<const uint32_t> flags = as_global(G_.flags);
   const int n0 = dm.n[0], n1 = dm.n[1];
-  const int d0 = diag_off[diag];
-  const int ntd = diag_off[diag + 1] - d0;
-  int item = blockIdx.x - item_off[p];
+  // tiles of diagonal `diag`: in 2D (a, b) with a + b = diag, computed; in 3D from the table
+  int d0 = 0, ntd;
+  if (DIM == 2) {
+    const int amin = max(0, diag - (ntile[1] - 1)), amax = min(diag, ntile[0] - 1);
+    d0 = amin;
+    ntd = amax - amin + 1;
+  } else {
+    const gptr<const int32_t> diag_off = as_global(G_.diag_off);
+    d0 = diag_off[diag];
+    ntd = diag_off[diag + 1] - d0;
+  }
+  int item = nprob > 1 ? blockIdx.x - item_off[p] : blockIdx.x;
   const int t = item % ntd;
   item /= ntd;
   const int grp = item % ngroups;
@@ -194,9 +199,18 @@ __global__ void __launch_bounds__(kWave)
   for (int j = 0; j < 3; ++j) kmir[j] = (o ^ (1 << j)) * Ko_pad + qq;
 
   int lo[3] = {0, 0, 0}, cnt[3] = {1, 1, 1};
+  int tpos[3] = {0, 0, 0};
+  if (DIM == 2) {
+    tpos[0] = d0 + t;
+    tpos[1] = diag - tpos[0];
+  } else {
+    const gptr<const int32_t> diag_tiles = as_global(G_.diag_tiles);
+#pragma unroll
+    for (int j = 0; j < 3; ++j) tpos[j] = diag_tiles[(d0 + t) * 4 + j];
+  }
 #pragma unroll
   for (int j = 0; j < DIM; ++j) {
-    const int tp = diag_tiles[(d0 + t) * 4 + j];
+    const int tp = tpos[j];
     const int tj = s[j] > 0 ? tp : ntile[j] - 1 - tp;
     lo[j] = tj * tile[j];
     cnt[j] = min(tile[j], dm.n[j] - lo[j]);
@@ -206,48 +220,9 @@ __global__ void __launch_bounds__(kWave)
 
   for (int c3 = 0; c3 < cnt[2]; ++c3) {
     const int z = s[2] > 0 ? lo[2] + c3 : lo[2] + cnt[2] - 1 - c3;
-    // --- stage: lane = voxel of the plane ---------------------------------
-    if (lane < NC) {
-      const int i = lane % TT, r = lane / TT;
-      uint32_t code = R_SKIP;
-      T *rp = rec + lane * RW;
-#pragma unroll
-      for (int k = 0; k < RW; ++k) rp[k] = T(0);  // a skipped voxel computes 0
-      if (i < cnt[0] && r < cnt[1]) {
-        const int x = xs + i * s[0], y = ys + r * s[1];
-        const int c = (y + n1 * z) * n0 + x;
-        const uint32_t f = flags[c];
-        if (!(f & F_SOLID)) {
-          const gptr<const T> sp = src + c * kSrcStride;
-          rp[0] = sp[0];
-          rp[1] = sp[1];
-          rp[2] = sp[2];
-          rp[3] = DIM == 3 ? sp[3] : T(0);
-          rp[4] = tau_fb ? srct[c] : T(0);
-          code = 0;
-#pragma unroll
-          for (int j = 0; j < DIM; ++j) {
-            const uint32_t fj = f >> fbit(j, sidx[j]);
-            const bool first = fj & 1u, y1s = fj & 2u, y2s = fj & 4u;
-            T c1 = first ? (y1s ? T(0) : T(1)) : T(2);
-            T c2 = first ? T(0) : T(-0.5);
-            T w = (first && y1s) ? wall[c * 6 + 2 * j + pin[j]] : T(0);
-            if (Y2WALL && !first && y2s) {
-              c2 = T(0);
-              w = T(-0.5) * wall_at_y1(dm, wall, j, s[j], pin[j], x, y, z);
-            }
-            rp[5 + 3 * j] = c1;
-            rp[6 + 3 * j] = c2;
-            rp[7 + 3 * j] = w;
-            code |= (first ? 1u : 0u) << j;
-          }
-        }
-      }
-      rcode[lane] = code;
-    }
-    // --- halos of the plane (before any store of this plane) --------------
-    // Away from the domain faces they are plain loads of the current sweep;
-    // only tiles touching a face resolve images.
+    // --- halos of the plane (before any store of this plane), issued first:
+    // they depend on nothing below. Away from the domain faces they are plain
+    // loads of the current sweep; only tiles touching a face resolve images.
     T L1[TT], L2[TT], B1[TT], B2[TT];
     const int64_t Kp = dm.Kpad;
     const gptr<T> hz = hc + (int64_t)(n1 * z) * n0 * Kp + kofs;  // plane z of the current sweep
@@ -276,6 +251,52 @@ __global__ void __launch_bounds__(kWave)
           B2[k] = upstream_fluid(dm, hc, hp, 1, x, ys - 2 * s[1], z, kofs, kmir[1]);
         }
       }
+    }
+    // --- stage: lane = voxel of the plane ---------------------------------
+    // The voxel's sources and wall values are loaded together with its flags
+    // (valid addresses whatever the flags say), so one round trip serves all.
+    if (lane < NC) {
+      const int i = lane % TT, r = lane / TT;
+      uint32_t code = R_SKIP;
+      T *rp = rec + lane * RW;
+#pragma unroll
+      for (int k = 0; k < RW; ++k) rp[k] = T(0);  // a skipped voxel computes 0
+      if (i < cnt[0] && r < cnt[1]) {
+        const int x = xs + i * s[0], y = ys + r * s[1];
+        const int c = (y + n1 * z) * n0 + x;
+        const uint32_t f = flags[c];
+        const gptr<const T> sp = src + c * kSrcStride;
+        const T sv0 = sp[0], sv1 = sp[1], sv2 = sp[2], sv3 = DIM == 3 ? sp[3] : T(0);
+        const T svt = tau_fb ? srct[c] : T(0);
+        T wv[DIM];
+#pragma unroll
+        for (int j = 0; j < DIM; ++j) wv[j] = wall[c * 6 + 2 * j + pin[j]];
+        if (!(f & F_SOLID)) {
+          rp[0] = sv0;
+          rp[1] = sv1;
+          rp[2] = sv2;
+          rp[3] = sv3;
+          rp[4] = svt;
+          code = 0;
+#pragma unroll
+          for (int j = 0; j < DIM; ++j) {
+            const uint32_t fj = f >> fbit(j, sidx[j]);
+            const bool first = fj & 1u, y1s = fj & 2u, y2s = fj & 4u;
+            T c1 = first ? (y1s ? T(0) : T(1)) : T(2);
+            T c2 = first ? T(0) : T(-0.5);
+            T w = (first && y1s) ? wv[j] : T(0);
+            if (Y2WALL && !first && y2s) {
+              c2 = T(0);
+              w = T(-0.5) * wall_at_y1(dm, wall, j, s[j], pin[j], x, y, z);
+            }
+            rp[5 + 3 * j] = c1;
+            rp[6 + 3 * j] = c2;
+            rp[7 + 3 * j] = w;
+            code |= (first ? 1u : 0u) << j;
+          }
+        }
+      }
+      rcode[lane] = code;
     }
     const bool zin = DIM == 3 && z - 2 * s[2] >= 0 && z - 2 * s[2] < dm.n[2];
     const int64_t zstep = (int64_t)n1 * n0 * Kp * s[2];
@@ -343,7 +364,7 @@ __global__ void __launch_bounds__(kWave)
       for (int r = 0; r < TT; ++r) {
         const int i = d - r;
         if (i < 0 || i >= TT) continue;
-        if (active && !(Nc[r] & R_SKIP)) hrow[r][icol[i]] = Nw[r];
+        if (active && !(Nc[r] & R_SKIP)) __builtin_nontemporal_store(Nw[r], &hrow[r][icol[i]]);
       }
 #pragma unroll
       for (int r = 0; r < TT; ++r) {
@@ -352,6 +373,266 @@ __global__ void __launch_bounds__(kWave)
       }
     }
     __syncthreads();  // the next plane's staging overwrites the records
+  }
+}
+
+// Step (i) in 2D as one launch: a row pipeline of tiles. Wavefront (chain c,
+// row j) owns tile row j (in the octant's sweep order) of velocity chain c =
+// (octant, 64-velocity group) and walks its tiles along x1 in sweep order.
+// Within a tile the walk is the one of sweep_kernel (same records, same
+// arithmetic, so both schedules give bitwise identical results). The left
+// halo of a tile is the last two columns of the wavefront's previous tile,
+// kept in registers; the bottom halo is the top two rows of tile (a, j - 1),
+// computed by the wavefront of row j - 1 of the same chain. That wavefront
+// publishes its progress with an agent-scope release after each tile; this
+// one waits for it with a bounded spin and an agent-scope acquire. Stamps
+// never repeat (seq * ntile0 + a + 1, seq advanced by every arm and every
+// reduction), so the counters are never reset. Producers have lower block
+// indices than their consumers (block = j * nchains + c), so in-order dispatch
+// cannot deadlock; a spin that still exceeds its bound flags ctl->fault and
+// lets every wavefront finish.
+constexpr int kSpinLimit = 1 << 20;  // about 50 ms of sleeping polls
+//
+// Two publication protocols. LOCAL (the host has checked that every row of a
+// chain runs on the same XCD, so producer and consumer share one L2): the
+// producer drains its stores into the L2 (s_waitcnt) and then writes the
+// counter with a relaxed agent-scope store; the consumer polls it with relaxed
+// agent-scope loads, which no CU's L1 can serve stale, and then reads the halo
+// through the shared L2. No L2 write-back or invalidation is needed. The halo
+// lines cannot be stale in the consumer's L1: the L1 starts the kernel empty
+// and a chain's 64-velocity segments are read only by the row above them,
+// after the counter. Otherwise: agent-scope release and acquire, correct for
+// any placement.
+
+template <typename T, int TT, bool Y2WALL, bool LOCAL>
+__global__ void __launch_bounds__(kWave) sweep_rows_kernel(const Geo<T> *__restrict__ G) {
+  constexpr int DIM = 2;
+  constexpr int NC = TT * TT;
+  constexpr int RW = 5 + 3 * DIM;
+  __shared__ T rd_lds[4 * kWave];
+  __shared__ T rec[NC * RW];
+  __shared__ uint32_t rcode[NC];
+  const Geo<T> &G_ = G[0];
+  if (!G_.run) return;
+  const Dom<T> dm = dom_of(G_);
+  const int ngroups = G_.ngroups, Ko = G_.Ko, Ko_pad = G_.Ko_pad, tau_fb = G_.tau_fb;
+  const int tile0 = G_.tile[0], tile1 = G_.tile[1];
+  const int ntile0 = G_.ntile[0], ntile1 = G_.ntile[1];
+  const gptr<const T> absv = as_global(G_.absv), avv = as_global(G_.av), rden = as_global(G_.rden),
+                      vsq = as_global(G_.vsqm);
+  const gptr<T> hc = as_global(G_.hcur);
+  const gptr<const T> hp = as_global(G_.hprev);
+  const gptr<const T> src = as_global(G_.srccur);
+  const gptr<const T> srct = as_global(G_.srctcur);
+  const gptr<const T> wall = as_global(G_.wallcur);
+  const gptr<const uint32_t> flags = as_global(G_.flags);
+  const gptr<int32_t> progress = as_global(G_.progress);
+  const uint32_t seq = (uint32_t)G_.seq;
+  const int n0 = dm.n[0], n1 = dm.n[1];
+  const int nchains = ngroups << DIM;
+  const int c = blockIdx.x % nchains;
+  const int j = blockIdx.x / nchains;  // tile row in sweep order
+  const int grp = c % ngroups;
+  const int o = c / ngroups;
+  const int lane = threadIdx.x;
+  const int q = grp * kWave + lane;
+  const bool active = q < Ko;
+  const int qq = active ? q : 0;
+  int s[3], sidx[3], pin[3];
+#pragma unroll
+  for (int k = 0; k < 3; ++k) {
+    sidx[k] = (o >> k) & 1;
+    s[k] = sidx[k] ? -1 : 1;
+    pin[k] = 1 - sidx[k];
+  }
+  T vv[2], aa[2];
+#pragma unroll
+  for (int k = 0; k < DIM; ++k) {
+    const T av = absv[k * Ko_pad + qq];
+    vv[k] = s[k] > 0 ? av : -av;
+    aa[k] = avv[k * Ko_pad + qq];
+  }
+#pragma unroll
+  for (int k = 0; k < 4; ++k) rd_lds[k * kWave + lane] = rden[k * Ko_pad + qq];
+  const T vsqm = tau_fb ? vsq[qq] : T(0);
+  const int kofs = o * Ko_pad + qq;
+  int kmir[3];
+#pragma unroll
+  for (int k = 0; k < 3; ++k) kmir[k] = (o ^ (1 << k)) * Ko_pad + qq;
+  const int64_t Kp = dm.Kpad;
+  // this row's voxel rows
+  const int tj = s[1] > 0 ? j : ntile1 - 1 - j;
+  const int lo1 = tj * tile1, cnt1 = min(tile1, n1 - lo1);
+  const int ys = s[1] > 0 ? lo1 : lo1 + cnt1 - 1;
+  const bool yin = ys - 2 * s[1] >= 0 && ys - 2 * s[1] < n1;
+  const gptr<int32_t> wait_on = progress + (j > 0 ? (j - 1) * nchains + c : 0);
+  const gptr<int32_t> publish = progress + j * nchains + c;
+  const gptr<int32_t> fault = as_global(&G_.ctl->fault);
+  const gptr<T> hz = hc + kofs;  // plane 0 of the current sweep
+  int spins = 0;
+
+  T L1[TT], L2[TT];  // left halo: previous tile's last two columns, or images
+#pragma unroll
+  for (int k = 0; k < TT; ++k) L1[k] = L2[k] = T(0);
+
+  for (int a = 0; a < ntile0; ++a) {
+    const int ta = s[0] > 0 ? a : ntile0 - 1 - a;
+    const int lo0 = ta * tile0, cnt0 = min(tile0, n0 - lo0);
+    const int xs = s[0] > 0 ? lo0 : lo0 + cnt0 - 1;
+    // --- records of this tile (no dependence on other wavefronts) ----------
+    if (lane < NC) {
+      const int i = lane % TT, r = lane / TT;
+      uint32_t code = R_SKIP;
+      T *rp = rec + lane * RW;
+#pragma unroll
+      for (int k = 0; k < RW; ++k) rp[k] = T(0);
+      if (i < cnt0 && r < cnt1) {
+        const int x = xs + i * s[0], y = ys + r * s[1];
+        const int cc = y * n0 + x;
+        const uint32_t f = flags[cc];
+        const gptr<const T> sp = src + cc * kSrcStride;
+        const T sv0 = sp[0], sv1 = sp[1], sv2 = sp[2];
+        const T svt = tau_fb ? srct[cc] : T(0);
+        T wv[DIM];
+#pragma unroll
+        for (int k = 0; k < DIM; ++k) wv[k] = wall[cc * 6 + 2 * k + pin[k]];
+        if (!(f & F_SOLID)) {
+          rp[0] = sv0;
+          rp[1] = sv1;
+          rp[2] = sv2;
+          rp[4] = svt;
+          code = 0;
+#pragma unroll
+          for (int k = 0; k < DIM; ++k) {
+            const uint32_t fj = f >> fbit(k, sidx[k]);
+            const bool first = fj & 1u, y1s = fj & 2u, y2s = fj & 4u;
+            T c1 = first ? (y1s ? T(0) : T(1)) : T(2);
+            T c2 = first ? T(0) : T(-0.5);
+            T w = (first && y1s) ? wv[k] : T(0);
+            if (Y2WALL && !first && y2s) {
+              c2 = T(0);
+              w = T(-0.5) * wall_at_y1(dm, wall, k, s[k], pin[k], x, y, 0);
+            }
+            rp[5 + 3 * k] = c1;
+            rp[6 + 3 * k] = c2;
+            rp[7 + 3 * k] = w;
+            code |= (first ? 1u : 0u) << k;
+          }
+        }
+      }
+      rcode[lane] = code;
+    }
+    // --- left halo of the first tile: images across the x1 wrap ------------
+    if (a == 0) {
+#pragma unroll
+      for (int k = 0; k < TT; ++k)
+        if (k < cnt1) {
+          const int y = ys + k * s[1];
+          L1[k] = upstream_fluid(dm, hc, hp, 0, xs - s[0], y, 0, kofs, kmir[0]);
+          L2[k] = upstream_fluid(dm, hc, hp, 0, xs - 2 * s[0], y, 0, kofs, kmir[0]);
+        }
+    }
+    // --- bottom halo: wait for tile (a, j - 1), then read its top rows -------
+    T B1[TT], B2[TT];
+#pragma unroll
+    for (int k = 0; k < TT; ++k) B1[k] = B2[k] = T(0);
+    if (j > 0) {
+      const int32_t want = (int32_t)(seq * (uint32_t)ntile0 + (uint32_t)(a + 1));
+      while (true) {
+        const int32_t got = __hip_atomic_load(wait_on, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        if ((int32_t)(got - want) >= 0) break;
+        if (++spins > kSpinLimit) {
+          __hip_atomic_store(fault, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+          break;
+        }
+        __builtin_amdgcn_s_sleep(2);
+      }
+      if (!LOCAL) __atomic_thread_fence(__ATOMIC_ACQUIRE);  // agent scope: the producer's stores are visible
+    }
+#pragma unroll
+    for (int k = 0; k < TT; ++k)
+      if (k < cnt0) {
+        const int x = xs + k * s[0];
+        if (yin) {
+          B1[k] = hz[(int64_t)((ys - s[1]) * n0 + x) * Kp];
+          B2[k] = hz[(int64_t)((ys - 2 * s[1]) * n0 + x) * Kp];
+        } else {
+          B1[k] = upstream_fluid(dm, hc, hp, 1, x, ys - s[1], 0, kofs, kmir[1]);
+          B2[k] = upstream_fluid(dm, hc, hp, 1, x, ys - 2 * s[1], 0, kofs, kmir[1]);
+        }
+      }
+    __syncthreads();
+    gptr<T> hrow[TT];
+    int64_t icol[TT];
+#pragma unroll
+    for (int k = 0; k < TT; ++k) {
+      hrow[k] = hz + (int64_t)((ys + k * s[1]) * n0 + xs) * Kp;
+      icol[k] = (int64_t)k * s[0] * Kp;
+    }
+    // --- the tile's anti-diagonals (as in sweep_kernel) ---------------------
+    T D1[TT], D2[TT], LN1[TT], LN2[TT];
+#pragma unroll
+    for (int k = 0; k < TT; ++k) D1[k] = D2[k] = LN1[k] = LN2[k] = T(0);
+#pragma unroll
+    for (int d = 0; d < 2 * TT - 1; ++d) {
+      T Nw[TT];
+      uint32_t Nc[TT];
+#pragma unroll
+      for (int r = 0; r < TT; ++r) {
+        Nw[r] = T(0);
+        Nc[r] = R_SKIP;
+      }
+#pragma unroll
+      for (int r = 0; r < TT; ++r) {
+        const int i = d - r;
+        if (i < 0 || i >= TT) continue;
+        const uint32_t code = __builtin_amdgcn_readfirstlane(rcode[i + TT * r]);
+        const T *rp = rec + (i + TT * r) * RW;
+        T num = fma(rp[1], vv[0], rp[0]);
+        num = fma(rp[2], vv[1], num);
+        if (tau_fb) num = fma(rp[4], vsqm, num);
+        const T x1a = i >= 1 ? D1[r] : L1[r];
+        const T x1b = i >= 2 ? D2[r] : (i == 1 ? L1[r] : L2[r]);
+        const T x2a = r >= 1 ? D1[r >= 1 ? r - 1 : 0] : B1[i];
+        const T x2b = r >= 2 ? D2[r >= 2 ? r - 2 : 0] : (r == 1 ? B1[i] : B2[i]);
+        num = fma(aa[0], fma(rp[5], x1a, fma(rp[6], x1b, rp[7])), num);
+        num = fma(aa[1], fma(rp[8], x2a, fma(rp[9], x2b, rp[10])), num);
+        Nw[r] = num * rd_lds[(code & 7u) * kWave + lane];
+        Nc[r] = code;
+        if (i == cnt0 - 1) LN1[r] = Nw[r];  // the tile's last column in sweep order
+        if (i == cnt0 - 2) LN2[r] = Nw[r];
+      }
+#pragma unroll
+      for (int r = 0; r < TT; ++r) {
+        const int i = d - r;
+        if (i < 0 || i >= TT) continue;
+        if (active && !(Nc[r] & R_SKIP)) hrow[r][icol[i]] = Nw[r];
+      }
+#pragma unroll
+      for (int r = 0; r < TT; ++r) {
+        D2[r] = D1[r];
+        D1[r] = Nw[r];
+      }
+    }
+    // --- publish the tile: its stores before the counter ---------------------
+    __syncthreads();
+    const int32_t stamp = (int32_t)(seq * (uint32_t)ntile0 + (uint32_t)(a + 1));
+    if (LOCAL) {
+      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+      __builtin_amdgcn_s_waitcnt(0);  // every store of the wavefront has reached the L2
+      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+      if (lane == 0) __hip_atomic_store(publish, stamp, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    } else {
+      if (lane == 0) __hip_atomic_store(publish, stamp, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+    }
+    // the next tile's left halo: this tile's last two columns (a tile one
+    // voxel wide passes on its own column and the one before it)
+#pragma unroll
+    for (int k = 0; k < TT; ++k) {
+      L2[k] = cnt0 >= 2 ? LN2[k] : L1[k];
+      L1[k] = LN1[k];
+    }
+    __syncthreads();  // the next tile's records overwrite this tile's
   }
 }
 
@@ -369,12 +650,11 @@ __device__ __forceinline__ double wave_sum(double v) {
 template <typename T, int DIM, int NS>
 __global__ void __launch_bounds__(kMomBlock)
     moments_kernel(const Geo<T> *__restrict__ G, const int *__restrict__ blk_off, int nprob) {
-  const int pb = owner_of(blk_off, nprob, blockIdx.x);
+  const int pb = nprob > 1 ? owner_of(blk_off, nprob, blockIdx.x) : 0;
   const Geo<T> &g = G[pb];
-  const int blk = blockIdx.x - blk_off[pb];
-  const Ctl *ctl = g.ctl;
-  if (ctl->stop) return;
-  const int par = ctl->par, np = par ^ 1;
+  const int blk = nprob > 1 ? blockIdx.x - blk_off[pb] : blockIdx.x;
+  if (!g.run) return;
+  const int par = g.cpar, np = par ^ 1;
   const gptr<const T> h = as_global((const T *)(np ? g.h[1] : g.h[0]));
   const gptr<const double> uold = as_global((const double *)(par ? g.u[1] : g.u[0]));
   const gptr<double> rho_n = as_global(np ? g.rho[1] : g.rho[0]);
@@ -474,9 +754,22 @@ __global__ void __launch_bounds__(kMomBlock)
   }
 }
 
+// The next iteration's buffers and run flag, written into the descriptor.
 template <typename T>
-__global__ void __launch_bounds__(256) reduce_kernel(const Geo<T> *__restrict__ G) {
-  const Geo<T> &g = G[blockIdx.x];
+__device__ void resolve(Geo<T> &g, int par, int run) {
+  g.seq += 1;  // a fresh stamp range for the row pipeline's progress counters
+  g.run = run;
+  g.cpar = par;
+  g.hcur = par ? g.h[0] : g.h[1];
+  g.hprev = par ? g.h[1] : g.h[0];
+  g.srccur = par ? g.src[1] : g.src[0];
+  g.srctcur = par ? g.srct[1] : g.srct[0];
+  g.wallcur = par ? g.wall[1] : g.wall[0];
+}
+
+template <typename T>
+__global__ void __launch_bounds__(256) reduce_kernel(Geo<T> *__restrict__ G) {
+  Geo<T> &g = G[blockIdx.x];
   Ctl *ctl = g.ctl;
   if (ctl->stop) return;
   const double *part = g.part;
@@ -510,6 +803,7 @@ __global__ void __launch_bounds__(256) reduce_kernel(const Geo<T> *__restrict__ 
   if (!isfinite(r) || !isfinite(k) || !isfinite(maxu)) {
     ctl->status = -4;  // keep `par`: the previous iterate stays the state
     ctl->stop = 1;
+    g.run = 0;
     return;
   }
   const int64_t it = ctl->iter + 1;
@@ -534,10 +828,11 @@ __global__ void __launch_bounds__(256) reduce_kernel(const Geo<T> *__restrict__ 
     ctl->status = 2;
     ctl->stop = 1;
   }
+  resolve(g, ctl->par, !ctl->stop);
 }
 
 template <typename T>
-__global__ void arm_kernel(const Geo<T> *__restrict__ G, int nprob, double tol, int mode, int64_t max_iters) {
+__global__ void arm_kernel(Geo<T> *__restrict__ G, int nprob, double tol, int mode, int64_t max_iters) {
   const int p = blockIdx.x * blockDim.x + threadIdx.x;
   if (p >= nprob) return;
   Ctl *ctl = G[p].ctl;
@@ -546,6 +841,8 @@ __global__ void arm_kernel(const Geo<T> *__restrict__ G, int nprob, double tol, 
   ctl->iter_limit = ctl->iter + max_iters;
   ctl->status = 0;
   ctl->stop = max_iters > 0 ? 0 : 1;
+  ctl->fault = 0;
+  resolve(G[p], ctl->par, !ctl->stop);
 }
 
 // Local linearised equilibrium of given fields (moments of the current state
@@ -693,6 +990,37 @@ hipError_t launch_sweep(const Batch<T> &B, int diag, hipStream_t st) {
   return hipGetLastError();
 }
 
+template <typename T, bool LOCAL>
+void launch_rows_local(const Batch<T> &B, dim3 grid, hipStream_t st) {
+  if (B.tile_edge == 4) {
+    if (B.y2wall) hipLaunchKernelGGL((sweep_rows_kernel<T, 4, true, LOCAL>), grid, dim3(kWave), 0, st, B.d_geo);
+    else hipLaunchKernelGGL((sweep_rows_kernel<T, 4, false, LOCAL>), grid, dim3(kWave), 0, st, B.d_geo);
+  } else {
+    if (B.y2wall) hipLaunchKernelGGL((sweep_rows_kernel<T, 8, true, LOCAL>), grid, dim3(kWave), 0, st, B.d_geo);
+    else hipLaunchKernelGGL((sweep_rows_kernel<T, 8, false, LOCAL>), grid, dim3(kWave), 0, st, B.d_geo);
+  }
+}
+
+template <typename T>
+hipError_t launch_sweep_rows(const Batch<T> &B, int nchains, int nrows, bool local, hipStream_t st) {
+  const dim3 grid((unsigned)(nchains * nrows));
+  if (local) launch_rows_local<T, true>(B, grid, st);
+  else launch_rows_local<T, false>(B, grid, st);
+  return hipGetLastError();
+}
+
+// The XCD (accelerator complex die) each block of a grid runs on.
+__global__ void xcd_probe_kernel(uint32_t *out) {
+  uint32_t x;
+  asm volatile("s_getreg_b32 %0, hwreg(HW_REG_XCC_ID)" : "=s"(x));
+  if (threadIdx.x == 0) out[blockIdx.x] = x;
+}
+
+hipError_t launch_xcd_probe(uint32_t *out, int blocks, hipStream_t st) {
+  hipLaunchKernelGGL(xcd_probe_kernel, dim3((unsigned)blocks), dim3(kWave), 0, st, out);
+  return hipGetLastError();
+}
+
 template <typename T>
 hipError_t launch_moments(const Batch<T> &B, hipStream_t st) {
   const int ns = (B.Ko + kWave - 1) / kWave;
@@ -720,7 +1048,7 @@ hipError_t launch_moments(const Batch<T> &B, hipStream_t st) {
 
 template <typename T>
 hipError_t launch_reduce(const Batch<T> &B, hipStream_t st) {
-  hipLaunchKernelGGL((reduce_kernel<T>), dim3(B.nprob), dim3(256), 0, st, B.d_geo);
+  hipLaunchKernelGGL((reduce_kernel<T>), dim3(B.nprob), dim3(256), 0, st, const_cast<Geo<T> *>(B.d_geo));
   return hipGetLastError();
 }
 
@@ -738,7 +1066,7 @@ hipError_t launch_ctl_gather(const Batch<T> &B, Ctl *out, hipStream_t st) {
 
 template <typename T>
 hipError_t launch_arm(const Batch<T> &B, double tol, int mode, int64_t max_iters, hipStream_t st) {
-  hipLaunchKernelGGL((arm_kernel<T>), dim3((B.nprob + 63) / 64), dim3(64), 0, st, B.d_geo, B.nprob, tol,
+  hipLaunchKernelGGL((arm_kernel<T>), dim3((B.nprob + 63) / 64), dim3(64), 0, st, const_cast<Geo<T> *>(B.d_geo), B.nprob, tol,
                      mode, max_iters);
   return hipGetLastError();
 }
@@ -772,6 +1100,8 @@ hipError_t launch_face_copy(const Geo<T> &g, int axis, int r, T *buf, int to_buf
 }
 
 template hipError_t launch_sweep<double>(const Batch<double> &, int, hipStream_t);
+template hipError_t launch_sweep_rows<double>(const Batch<double> &, int, int, bool, hipStream_t);
+template hipError_t launch_sweep_rows<float>(const Batch<float> &, int, int, bool, hipStream_t);
 template hipError_t launch_sweep<float>(const Batch<float> &, int, hipStream_t);
 template hipError_t launch_moments<double>(const Batch<double> &, hipStream_t);
 template hipError_t launch_moments<float>(const Batch<float> &, hipStream_t);

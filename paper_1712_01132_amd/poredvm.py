@@ -19,6 +19,7 @@ PDVM_E_NONFINITE, PDVM_E_STATE, PDVM_E_UNSUPPORTED = -4, -5, -6
 PDVM_FP64, PDVM_FP32 = 0, 1
 PDVM_LATERAL_SPECULAR, PDVM_LATERAL_PERIODIC = 0, 1
 PDVM_STOP_FIELD, PDVM_STOP_PAPER_ERR = 0, 1
+SCHEDULES = {"auto": 0, "diagonals": 1, "rows": 2}
 
 _dp = ctypes.POINTER(ctypes.c_double)
 
@@ -39,6 +40,7 @@ class PdvmConfig(ctypes.Structure):
         ("check_every", ctypes.c_int32),
         ("tile", ctypes.c_int32 * 3),
         ("stencil_rule", ctypes.c_int32),
+        ("sweep_schedule", ctypes.c_int32),
     ]
 
 
@@ -77,7 +79,7 @@ EXPORTED = [
     "pdvm_iterate", "pdvm_get_moments", "pdvm_get_flux", "pdvm_get_state",
     "pdvm_set_state", "pdvm_time_kernels", "pdvm_destroy", "pdvm_last_error",
     "pdvm_batch_create", "pdvm_batch_size", "pdvm_batch_set_initial", "pdvm_batch_iterate",
-    "pdvm_batch_get_moments", "pdvm_batch_get_flux",
+    "pdvm_batch_get_moments", "pdvm_batch_get_flux", "pdvm_sweep_schedule",
 ]
 
 _lib = None
@@ -118,6 +120,8 @@ def load():
     lib.pdvm_batch_iterate.argtypes = [vp, ctypes.c_int64, ctypes.c_double, ctypes.c_int32,
                                        ctypes.POINTER(PdvmStats)]
     lib.pdvm_batch_get_moments.argtypes = [vp, ctypes.c_int32, _dp, _dp, _dp, _dp]
+    lib.pdvm_sweep_schedule.restype = ctypes.c_int32
+    lib.pdvm_sweep_schedule.argtypes = [vp]
     lib.pdvm_batch_get_flux.argtypes = [vp, ctypes.c_int32, _dp, _dp, _dp]
     lib.pdvm_destroy.argtypes = [vp]
     lib.pdvm_last_error.restype = ctypes.c_char_p
@@ -145,7 +149,7 @@ def velocity_grid(n_total):
 
 
 def make_config(solid, nv, kn, jump=1.0, precision="fp64", lateral="specular",
-                tau_feedback=False, tile=None, check_every=16, grid=None, stencil_rule=1):
+                tau_feedback=False, tile=None, check_every=16, grid=None, stencil_rule=1, schedule="auto"):
     """Build a PdvmConfig; returns (config, keepalive) -- keep both alive."""
     solid = np.ascontiguousarray(solid, dtype=np.uint8)
     dim = solid.ndim
@@ -172,6 +176,7 @@ def make_config(solid, nv, kn, jump=1.0, precision="fp64", lateral="specular",
     cfg.tau_feedback = int(bool(tau_feedback))
     cfg.check_every = int(check_every)
     cfg.stencil_rule = int(stencil_rule)
+    cfg.sweep_schedule = SCHEDULES[schedule]
     return cfg, (solid, grid)
 
 
@@ -184,7 +189,7 @@ class Solver:
 
     def __init__(self, solid, nv, kn, jump=1.0, precision="fp64", lateral="specular",
                  tau_feedback=False, tile=None, check_every=16, grid=None, device=None,
-                 stencil_rule=1):
+                 stencil_rule=1, schedule="auto"):
         import torch
 
         lib = load()
@@ -192,7 +197,7 @@ class Solver:
         self.dim = len(self.shape)
         self.N = int(np.prod(self.shape))
         self.cfg, self._keep = make_config(solid, nv, kn, jump, precision, lateral,
-                                           tau_feedback, tile, check_every, grid, stencil_rule)
+                                           tau_feedback, tile, check_every, grid, stencil_rule, schedule)
         nbytes = lib.pdvm_workspace_bytes(ctypes.byref(self.cfg))
         if nbytes == 0:
             raise PdvmError(PDVM_E_INVAL, _err())
@@ -276,6 +281,11 @@ class Solver:
         t = PdvmTiming()
         self._check(load().pdvm_time_kernels(self._h, int(iters), ctypes.byref(t)))
         return {f: getattr(t, f) for f, _ in PdvmTiming._fields_}
+
+    @property
+    def schedule(self):
+        """"diagonals", "rows" (agent-scope) or "rows-xcd" (XCD-local row pipeline)."""
+        return {0: "diagonals", 1: "rows", 2: "rows-xcd"}[load().pdvm_sweep_schedule(self._h)]
 
 
 class Batch:

@@ -100,6 +100,48 @@ def test_ragged_tiles_3d_fp32_match_oracle(tile, rule):
         compare(o, s, RTOL32)
 
 
+@pytest.mark.parametrize("shape,nv,tile,precision,lateral,rule", [
+    ((29, 37), [6, 8], (8, 8), "fp64", "specular", 1),
+    ((29, 37), [6, 8], (8, 5), "fp64", "specular", 0),
+    ((33, 26), [8, 8], (3, 8), "fp32", "periodic", 1),
+    ((17, 40), [4, 4], (4, 4), "fp64", "specular", 1),
+    ((40, 9), [4, 6], (1, 4), "fp64", "specular", 1),
+    ((64, 64), [24, 24], (8, 8), "fp32", "specular", 1),
+    ((72, 56), [32, 32], (8, 8), "fp64", "specular", 1),
+    ((40, 33), [16, 32], (8, 5), "fp32", "periodic", 0),
+])
+def test_row_pipeline_equals_tile_diagonals_bitwise(shape, nv, tile, precision, lateral, rule):
+    """The one-launch row pipeline and the per-diagonal launches run the same
+    arithmetic on the same values: every iterate is bitwise identical. Wide
+    velocity grids give several chains per octant; narrow and ragged tiles
+    exercise the register-carried left halo."""
+    m = random_mask(shape, 0.3, sum(shape) + 7)
+    out = []
+    for sched in ("rows", "diagonals"):
+        s = poredvm.Solver(m, nv, 0.6, precision=precision, lateral=lateral, tile=tile, stencil_rule=rule,
+                           schedule=sched)
+        r = s.iterate(12)
+        out.append((s.moments(diagnostics=False), r["k"], r["r"]))
+        s.close()
+    (a, ka, ra), (b, kb, rb) = out
+    assert np.array_equal(a[0], b[0]) and np.array_equal(a[1], b[1]) and ka == kb and ra == rb
+
+
+def test_row_pipeline_uses_the_xcd_local_protocol_when_chains_fill_xcds():
+    """32 x 32 and 16 x 32 velocities give 16 and 8 velocity chains: every chain
+    lands on one XCD, so the probe selects the XCD-local protocol (the cases
+    above then exercise it); 6 x 8 velocities give 4 chains and the
+    agent-scope protocol."""
+    m = random_mask((40, 48), 0.3, 5)
+    for nv, want in (([32, 32], "rows-xcd"), ([16, 32], "rows-xcd"), ([6, 8], "rows")):
+        s = poredvm.Solver(m, nv, 0.6, schedule="rows")
+        assert s.schedule == want, (nv, s.schedule)
+        s.close()
+    s = poredvm.Solver(m, [6, 8], 0.6)  # automatic: no cheap protocol, tile diagonals
+    assert s.schedule == "diagonals"
+    s.close()
+
+
 def test_minimal_domain_and_grid():
     m = np.zeros((2, 2), np.uint8)
     o, s = pair(m, [2, 2], 0.5)
