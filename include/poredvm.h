@@ -59,10 +59,15 @@ enum { PDVM_STOP_FIELD = 0, PDVM_STOP_PAPER_ERR = 1 };
 /* Sweep schedules (results are bitwise identical between them):
  * DIAGONALS: one launch per diagonal of sweep tiles (all octants, velocity
  *            groups and problems of a batch in each launch);
- * ROWS:      2D, one problem: one launch in which each wavefront pipelines a
- *            row of tiles behind the row below it;
- * AUTO:      ROWS for a single 2D problem, DIAGONALS otherwise. */
-enum { PDVM_SCHEDULE_AUTO = 0, PDVM_SCHEDULE_DIAGONALS = 1, PDVM_SCHEDULE_ROWS = 2 };
+ * ROWS:      2D: one launch for all problems of the batch, in which each
+ *            wavefront pipelines a row of tiles behind the row below it;
+ * ROWS_AGENT: ROWS with agent-scope release/acquire per tile, correct for any
+ *            block placement (slower; ROWS uses it when the probe below fails);
+ * AUTO:      for a single 2D problem, ROWS when a probe of the block placement
+ *            at creation shows that every velocity chain runs on one XCD (cheap
+ *            synchronisation through its L2); DIAGONALS otherwise (batches
+ *            keep the machine fuller with per-diagonal launches). */
+enum { PDVM_SCHEDULE_AUTO = 0, PDVM_SCHEDULE_DIAGONALS = 1, PDVM_SCHEDULE_ROWS = 2, PDVM_SCHEDULE_ROWS_AGENT = 3 };
 
 typedef struct pdvm_solver pdvm_solver;
 
@@ -89,8 +94,8 @@ typedef struct {
                                 0 = only when the first one is (a solid second image then
                                     enters the second-order stencil with its wall value;
                                     this iteration can diverge on some geometries) */
-  int32_t sweep_schedule;    /* PDVM_SCHEDULE_*; ROWS with dim 3 or in a batch is
-                                PDVM_E_UNSUPPORTED */
+  int32_t sweep_schedule;    /* PDVM_SCHEDULE_*; ROWS(_AGENT) with dim 3 is PDVM_E_UNSUPPORTED;
+                                a batch takes the first config's schedule */
 } pdvm_config;
 
 typedef struct {

@@ -226,9 +226,12 @@ int validate_and_build(const pdvm_config *cfg, Problem &P, std::string &err) {
   P.lateral_periodic = cfg->lateral_bc == PDVM_LATERAL_PERIODIC;
   P.tau_fb = cfg->tau_feedback ? 1 : 0;
   P.check_every = cfg->check_every > 0 ? cfg->check_every : 16;
-  if (cfg->sweep_schedule < 0 || cfg->sweep_schedule > 2) { err = "sweep_schedule must be 0, 1 or 2"; return PDVM_E_INVAL; }
+  if (cfg->sweep_schedule < 0 || cfg->sweep_schedule > 3) { err = "sweep_schedule must be 0..3"; return PDVM_E_INVAL; }
   P.schedule = cfg->sweep_schedule;
-  if (P.schedule == PDVM_SCHEDULE_ROWS && cfg->dim != 2) { err = "the row-pipeline sweep is 2D only"; return PDVM_E_UNSUPPORTED; }
+  if ((P.schedule == PDVM_SCHEDULE_ROWS || P.schedule == PDVM_SCHEDULE_ROWS_AGENT) && cfg->dim != 2) {
+    err = "the row-pipeline sweep is 2D only";
+    return PDVM_E_UNSUPPORTED;
+  }
   if (cfg->stencil_rule != 0 && cfg->stencil_rule != 1) { err = "stencil_rule must be 0 or 1"; return PDVM_E_INVAL; }
   P.stencil_rule = cfg->stencil_rule;
 
@@ -517,7 +520,7 @@ struct pdvm_solver {
   bool own_stream = false;
   char *meta = nullptr;            // device: descriptors, offset tables, gathered control blocks
   Ctl *d_ctl_all = nullptr;
-  std::vector<int> h_item_off, h_blk_off;
+  std::vector<int> h_item_off, h_blk_off, h_row_off;
   Batch<double> bd;
   Batch<float> bf;
   Ctl *host_ctl = nullptr;         // pinned, one per problem
@@ -643,16 +646,22 @@ int finalize_batch(pdvm_solver *s) {
   }
   s->h_blk_off.assign(n + 1, 0);
   for (int p = 0; p < n; ++p) s->h_blk_off[p + 1] = s->h_blk_off[p] + s->P[p].mom_blocks;
+  // row pipeline: per problem, tile rows x (chains rounded up to 8) blocks
+  const int stride = ((P0.ngroups << P0.dim) + 7) / 8 * 8;
+  s->h_row_off.assign(n + 1, 0);
+  for (int p = 0; p < n; ++p) s->h_row_off[p + 1] = s->h_row_off[p] + s->P[p].ntile[1] * stride;
   const size_t geo_b = align256(n * sizeof(Geo<T>));
   const size_t item_b = align256(s->h_item_off.size() * 4);
   const size_t blk_b = align256(s->h_blk_off.size() * 4);
+  const size_t row_b = align256(s->h_row_off.size() * 4);
   const size_t ctl_b = align256(n * sizeof(Ctl));
   void *m = nullptr;
-  if (hipMalloc(&m, geo_b + item_b + blk_b + ctl_b) != hipSuccess)
+  if (hipMalloc(&m, geo_b + item_b + blk_b + row_b + ctl_b) != hipSuccess)
     return s->fail(PDVM_E_NOMEM, "hipMalloc of the batch tables failed");
   s->meta = (char *)m;
-  char *geo = s->meta, *item = geo + geo_b, *blk = item + item_b;
-  s->d_ctl_all = (Ctl *)(blk + blk_b);
+  char *geo = s->meta, *item = geo + geo_b, *blk = item + item_b, *rowo = blk + blk_b;
+  s->d_ctl_all = (Ctl *)(rowo + row_b);
+  HIPCHK(s, hipMemcpyAsync(rowo, s->h_row_off.data(), s->h_row_off.size() * 4, hipMemcpyHostToDevice, s->stream));
   HIPCHK(s, hipMemcpyAsync(geo, geos<T>(s).data(), n * sizeof(Geo<T>), hipMemcpyHostToDevice, s->stream));
   HIPCHK(s, hipMemcpyAsync(item, s->h_item_off.data(), s->h_item_off.size() * 4, hipMemcpyHostToDevice, s->stream));
   HIPCHK(s, hipMemcpyAsync(blk, s->h_blk_off.data(), s->h_blk_off.size() * 4, hipMemcpyHostToDevice, s->stream));
@@ -671,6 +680,9 @@ int finalize_batch(pdvm_solver *s) {
   B.d_blk_off = (const int *)blk;
   B.h_item_off = s->h_item_off.data();
   B.h_blk_off = s->h_blk_off.data();
+  B.d_row_off = (const int *)rowo;
+  B.h_row_off = s->h_row_off.data();
+  B.row_stride = stride;
   if (hipHostMalloc((void **)&s->host_ctl, n * sizeof(Ctl), hipHostMallocDefault) != hipSuccess)
     return s->fail(PDVM_E_NOMEM, "pinned host allocation failed");
   return PDVM_OK;
@@ -680,8 +692,7 @@ template <typename T>
 int enqueue_sweep(pdvm_solver *s) {
   const Batch<T> &B = batch<T>(s);
   if (s->rows) {
-    const Problem &P = s->P[0];
-    HIPCHK(s, launch_sweep_rows<T>(B, P.ngroups << P.dim, P.ntile[1], s->rows_local, s->stream));
+    HIPCHK(s, launch_sweep_rows<T>(B, s->rows_local, s->stream));
   } else {
     for (int d = 0; d < B.ndiag_max; ++d) HIPCHK(s, launch_sweep<T>(B, d, s->stream));
   }
@@ -754,7 +765,8 @@ bool same_velocity_grid(const Problem &a, const Problem &b) {
 // read is live) and one XCD per chain.
 int probe_xcd_locality(pdvm_solver *s) {
   const Problem &P = s->P[0];
-  const int nchains = P.ngroups << P.dim, blocks = nchains * P.ntile[1];
+  const int nchains = P.ngroups << P.dim, n = s->n();
+  const int stride = ((nchains + 7) / 8) * 8, blocks = s->h_row_off[n];
   uint32_t *d = nullptr;
   if (hipMalloc(&d, sizeof(uint32_t) * blocks) != hipSuccess) return s->fail(PDVM_E_NOMEM, "probe allocation failed");
   std::vector<uint32_t> h(blocks);
@@ -764,10 +776,12 @@ int probe_xcd_locality(pdvm_solver *s) {
   (void)hipFree(d);
   if (e != hipSuccess) return s->fail(PDVM_E_HIP, "XCD probe: %s", hipGetErrorString(e));
   bool local = true, several = false;
-  for (int b = 0; b < blocks; ++b) {
-    local = local && h[b] == h[b % nchains];
-    several = several || h[b] != h[0];
-  }
+  for (int p = 0; p < n; ++p)
+    for (int b = s->h_row_off[p]; b < s->h_row_off[p + 1]; ++b) {
+      const int c = (b - s->h_row_off[p]) % stride;
+      if (c < nchains) local = local && h[b] == h[s->h_row_off[0] + c];
+      several = several || h[b] != h[0];
+    }
   s->rows_local = local && several;
   return PDVM_OK;
 }
@@ -844,13 +858,11 @@ int create_common(const pdvm_config *cfgs, int n, void *dev_workspace, size_t ws
     return rc;
   }
   const Problem &P0 = s->P[0];
-  if (P0.schedule == PDVM_SCHEDULE_ROWS && n > 1) {
-    set_thread_error("the row-pipeline sweep serves a single problem; batches sweep by tile diagonals");
-    pdvm_destroy(s);
-    return PDVM_E_UNSUPPORTED;
-  }
-  s->rows = n == 1 && P0.dim == 2 && P0.schedule != PDVM_SCHEDULE_DIAGONALS;
-  if (s->rows) {
+  // automatic: the row pipeline for a single 2D problem; a batch fills the
+  // machine better with per-diagonal launches (measured)
+  s->rows = P0.dim == 2 && (P0.schedule == PDVM_SCHEDULE_ROWS || P0.schedule == PDVM_SCHEDULE_ROWS_AGENT ||
+                            (P0.schedule == PDVM_SCHEDULE_AUTO && n == 1));
+  if (s->rows && P0.schedule != PDVM_SCHEDULE_ROWS_AGENT) {
     const int rc2 = probe_xcd_locality(s);
     if (rc2 != PDVM_OK) {
       g_thread_error = s->err;
@@ -1241,11 +1253,9 @@ int pdvm_time_kernels(pdvm_solver *s, int32_t iters, pdvm_timing *out) {
   const bool f64 = s->precision == PDVM_FP64;
   const int nd = s->rows ? 1 : (f64 ? s->bd.ndiag_max : s->bf.ndiag_max);
   auto sweep_launch = [&](int d) {
-    if (s->rows) {
-      const Problem &P = s->P[0];
-      return f64 ? launch_sweep_rows<double>(s->bd, P.ngroups << P.dim, P.ntile[1], s->rows_local, s->stream)
-                 : launch_sweep_rows<float>(s->bf, P.ngroups << P.dim, P.ntile[1], s->rows_local, s->stream);
-    }
+    if (s->rows)
+      return f64 ? launch_sweep_rows<double>(s->bd, s->rows_local, s->stream)
+                 : launch_sweep_rows<float>(s->bf, s->rows_local, s->stream);
     return f64 ? launch_sweep<double>(s->bd, d, s->stream) : launch_sweep<float>(s->bf, d, s->stream);
   };
   auto mom_launch = [&]() { return f64 ? launch_moments<double>(s->bd, s->stream) : launch_moments<float>(s->bf, s->stream); };

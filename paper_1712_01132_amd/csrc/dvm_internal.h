@@ -100,15 +100,21 @@ struct Batch {
   const int *d_blk_off = nullptr;    // [nprob + 1] moment-kernel blocks
   const int *h_item_off = nullptr;   // host copies
   const int *h_blk_off = nullptr;
+  // row-pipeline sweep: problem p owns blocks [row_off[p], row_off[p + 1]),
+  // its tile rows times row_stride (the chain count rounded up to 8); both
+  // multiples of 8
+  const int *d_row_off = nullptr;
+  const int *h_row_off = nullptr;
+  int row_stride = 8;
 };
 
 // Kernel launchers (dvm_kernels.hip). All enqueue on `st`.
 template <typename T>
 hipError_t launch_sweep(const Batch<T> &B, int diag, hipStream_t st);
-// The whole sweep of a single 2D problem as one row-pipeline launch; `local`:
-// every chain's rows run on one XCD (checked with launch_xcd_probe).
+// The whole 2D sweep of every problem of the batch as one row-pipeline launch;
+// `local`: every chain's rows run on one XCD (checked with launch_xcd_probe).
 template <typename T>
-hipError_t launch_sweep_rows(const Batch<T> &B, int nchains, int nrows, bool local, hipStream_t st);
+hipError_t launch_sweep_rows(const Batch<T> &B, bool local, hipStream_t st);
 // out[b] = the XCD that block b of a `blocks`-block grid runs on.
 hipError_t launch_xcd_probe(uint32_t *out, int blocks, hipStream_t st);
 template <typename T>

@@ -401,18 +401,24 @@ constexpr int kSpinLimit = 1 << 20;  // about 50 ms of sleeping polls
 // through the shared L2. No L2 write-back or invalidation is needed. The halo
 // lines cannot be stale in the consumer's L1: the L1 starts the kernel empty
 // and a chain's 64-velocity segments are read only by the row above them,
-// after the counter. Otherwise: agent-scope release and acquire, correct for
-// any placement.
+// after the counter. (A workgroup-scope counter polled after an L1
+// invalidation was never observed on gfx950.) Otherwise: agent-scope release
+// and acquire, correct for any placement.
 
 template <typename T, int TT, bool Y2WALL, bool LOCAL>
-__global__ void __launch_bounds__(kWave) sweep_rows_kernel(const Geo<T> *__restrict__ G) {
+__global__ void __launch_bounds__(kWave)
+    sweep_rows_kernel(const Geo<T> *__restrict__ G, const int *__restrict__ row_off, int nprob, int stride) {
   constexpr int DIM = 2;
   constexpr int NC = TT * TT;
   constexpr int RW = 5 + 3 * DIM;
   __shared__ T rd_lds[4 * kWave];
   __shared__ T rec[NC * RW];
   __shared__ uint32_t rcode[NC];
-  const Geo<T> &G_ = G[0];
+  // block = row_off[p] + j * stride + c: problem p, tile row j, velocity chain
+  // c; stride and row_off[p] are multiples of 8, so chain c of every row runs
+  // on XCD (c mod 8) under round-robin placement
+  const int p = nprob > 1 ? owner_of(row_off, nprob, blockIdx.x) : 0;
+  const Geo<T> &G_ = G[p];
   if (!G_.run) return;
   const Dom<T> dm = dom_of(G_);
   const int ngroups = G_.ngroups, Ko = G_.Ko, Ko_pad = G_.Ko_pad, tau_fb = G_.tau_fb;
@@ -430,8 +436,10 @@ __global__ void __launch_bounds__(kWave) sweep_rows_kernel(const Geo<T> *__restr
   const uint32_t seq = (uint32_t)G_.seq;
   const int n0 = dm.n[0], n1 = dm.n[1];
   const int nchains = ngroups << DIM;
-  const int c = blockIdx.x % nchains;
-  const int j = blockIdx.x / nchains;  // tile row in sweep order
+  const int local_b = nprob > 1 ? blockIdx.x - row_off[p] : blockIdx.x;
+  const int c = local_b % stride;
+  const int j = local_b / stride;  // tile row in sweep order
+  if (c >= nchains) return;        // padding of the row to a multiple of 8 blocks
   const int grp = c % ngroups;
   const int o = c / ngroups;
   const int lane = threadIdx.x;
@@ -475,49 +483,67 @@ __global__ void __launch_bounds__(kWave) sweep_rows_kernel(const Geo<T> *__restr
 #pragma unroll
   for (int k = 0; k < TT; ++k) L1[k] = L2[k] = T(0);
 
+  // raw data of voxel `lane` of tile a of this row, loaded one tile ahead
+  struct Raw {
+    uint32_t f;
+    T sv0, sv1, sv2, svt, wv[2];
+  };
+  auto fetch = [&](int a, Raw &R) {
+    const int ta = s[0] > 0 ? a : ntile0 - 1 - a;
+    const int lo0 = ta * tile0, cnt0 = min(tile0, n0 - lo0);
+    const int xs = s[0] > 0 ? lo0 : lo0 + cnt0 - 1;
+    const int i = lane % TT, r = lane / TT;
+    R.f = F_SOLID;
+    if (lane < NC && i < cnt0 && r < cnt1) {
+      const int cc = (ys + r * s[1]) * n0 + xs + i * s[0];
+      R.f = flags[cc];
+      const gptr<const T> sp = src + cc * kSrcStride;
+      R.sv0 = sp[0];
+      R.sv1 = sp[1];
+      R.sv2 = sp[2];
+      R.svt = tau_fb ? srct[cc] : T(0);
+#pragma unroll
+      for (int k = 0; k < DIM; ++k) R.wv[k] = wall[cc * 6 + 2 * k + pin[k]];
+    }
+  };
+  Raw nxt;
+  fetch(0, nxt);
+
   for (int a = 0; a < ntile0; ++a) {
     const int ta = s[0] > 0 ? a : ntile0 - 1 - a;
     const int lo0 = ta * tile0, cnt0 = min(tile0, n0 - lo0);
     const int xs = s[0] > 0 ? lo0 : lo0 + cnt0 - 1;
-    // --- records of this tile (no dependence on other wavefronts) ----------
+    // --- records of this tile from the prefetched data ----------------------
+    const Raw cur = nxt;
+    if (a + 1 < ntile0) fetch(a + 1, nxt);  // in flight during this tile's wait and walk
     if (lane < NC) {
       const int i = lane % TT, r = lane / TT;
       uint32_t code = R_SKIP;
       T *rp = rec + lane * RW;
 #pragma unroll
       for (int k = 0; k < RW; ++k) rp[k] = T(0);
-      if (i < cnt0 && r < cnt1) {
+      if (i < cnt0 && r < cnt1 && !(cur.f & F_SOLID)) {
         const int x = xs + i * s[0], y = ys + r * s[1];
-        const int cc = y * n0 + x;
-        const uint32_t f = flags[cc];
-        const gptr<const T> sp = src + cc * kSrcStride;
-        const T sv0 = sp[0], sv1 = sp[1], sv2 = sp[2];
-        const T svt = tau_fb ? srct[cc] : T(0);
-        T wv[DIM];
+        rp[0] = cur.sv0;
+        rp[1] = cur.sv1;
+        rp[2] = cur.sv2;
+        rp[4] = cur.svt;
+        code = 0;
 #pragma unroll
-        for (int k = 0; k < DIM; ++k) wv[k] = wall[cc * 6 + 2 * k + pin[k]];
-        if (!(f & F_SOLID)) {
-          rp[0] = sv0;
-          rp[1] = sv1;
-          rp[2] = sv2;
-          rp[4] = svt;
-          code = 0;
-#pragma unroll
-          for (int k = 0; k < DIM; ++k) {
-            const uint32_t fj = f >> fbit(k, sidx[k]);
-            const bool first = fj & 1u, y1s = fj & 2u, y2s = fj & 4u;
-            T c1 = first ? (y1s ? T(0) : T(1)) : T(2);
-            T c2 = first ? T(0) : T(-0.5);
-            T w = (first && y1s) ? wv[k] : T(0);
-            if (Y2WALL && !first && y2s) {
-              c2 = T(0);
-              w = T(-0.5) * wall_at_y1(dm, wall, k, s[k], pin[k], x, y, 0);
-            }
-            rp[5 + 3 * k] = c1;
-            rp[6 + 3 * k] = c2;
-            rp[7 + 3 * k] = w;
-            code |= (first ? 1u : 0u) << k;
+        for (int k = 0; k < DIM; ++k) {
+          const uint32_t fj = cur.f >> fbit(k, sidx[k]);
+          const bool first = fj & 1u, y1s = fj & 2u, y2s = fj & 4u;
+          T c1 = first ? (y1s ? T(0) : T(1)) : T(2);
+          T c2 = first ? T(0) : T(-0.5);
+          T w = (first && y1s) ? cur.wv[k] : T(0);
+          if (Y2WALL && !first && y2s) {
+            c2 = T(0);
+            w = T(-0.5) * wall_at_y1(dm, wall, k, s[k], pin[k], x, y, 0);
           }
+          rp[5 + 3 * k] = c1;
+          rp[6 + 3 * k] = c2;
+          rp[7 + 3 * k] = w;
+          code |= (first ? 1u : 0u) << k;
         }
       }
       rcode[lane] = code;
@@ -992,18 +1018,22 @@ hipError_t launch_sweep(const Batch<T> &B, int diag, hipStream_t st) {
 
 template <typename T, bool LOCAL>
 void launch_rows_local(const Batch<T> &B, dim3 grid, hipStream_t st) {
+#define PDVM_ROWS(TTV, Y2)                                                                                   \
+  hipLaunchKernelGGL((sweep_rows_kernel<T, TTV, Y2, LOCAL>), grid, dim3(kWave), 0, st, B.d_geo, B.d_row_off, \
+                     B.nprob, B.row_stride)
   if (B.tile_edge == 4) {
-    if (B.y2wall) hipLaunchKernelGGL((sweep_rows_kernel<T, 4, true, LOCAL>), grid, dim3(kWave), 0, st, B.d_geo);
-    else hipLaunchKernelGGL((sweep_rows_kernel<T, 4, false, LOCAL>), grid, dim3(kWave), 0, st, B.d_geo);
+    if (B.y2wall) PDVM_ROWS(4, true);
+    else PDVM_ROWS(4, false);
   } else {
-    if (B.y2wall) hipLaunchKernelGGL((sweep_rows_kernel<T, 8, true, LOCAL>), grid, dim3(kWave), 0, st, B.d_geo);
-    else hipLaunchKernelGGL((sweep_rows_kernel<T, 8, false, LOCAL>), grid, dim3(kWave), 0, st, B.d_geo);
+    if (B.y2wall) PDVM_ROWS(8, true);
+    else PDVM_ROWS(8, false);
   }
+#undef PDVM_ROWS
 }
 
 template <typename T>
-hipError_t launch_sweep_rows(const Batch<T> &B, int nchains, int nrows, bool local, hipStream_t st) {
-  const dim3 grid((unsigned)(nchains * nrows));
+hipError_t launch_sweep_rows(const Batch<T> &B, bool local, hipStream_t st) {
+  const dim3 grid((unsigned)B.h_row_off[B.nprob]);
   if (local) launch_rows_local<T, true>(B, grid, st);
   else launch_rows_local<T, false>(B, grid, st);
   return hipGetLastError();
@@ -1100,8 +1130,8 @@ hipError_t launch_face_copy(const Geo<T> &g, int axis, int r, T *buf, int to_buf
 }
 
 template hipError_t launch_sweep<double>(const Batch<double> &, int, hipStream_t);
-template hipError_t launch_sweep_rows<double>(const Batch<double> &, int, int, bool, hipStream_t);
-template hipError_t launch_sweep_rows<float>(const Batch<float> &, int, int, bool, hipStream_t);
+template hipError_t launch_sweep_rows<double>(const Batch<double> &, bool, hipStream_t);
+template hipError_t launch_sweep_rows<float>(const Batch<float> &, bool, hipStream_t);
 template hipError_t launch_sweep<float>(const Batch<float> &, int, hipStream_t);
 template hipError_t launch_moments<double>(const Batch<double> &, hipStream_t);
 template hipError_t launch_moments<float>(const Batch<float> &, hipStream_t);

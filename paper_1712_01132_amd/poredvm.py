@@ -19,7 +19,7 @@ PDVM_E_NONFINITE, PDVM_E_STATE, PDVM_E_UNSUPPORTED = -4, -5, -6
 PDVM_FP64, PDVM_FP32 = 0, 1
 PDVM_LATERAL_SPECULAR, PDVM_LATERAL_PERIODIC = 0, 1
 PDVM_STOP_FIELD, PDVM_STOP_PAPER_ERR = 0, 1
-SCHEDULES = {"auto": 0, "diagonals": 1, "rows": 2}
+SCHEDULES = {"auto": 0, "diagonals": 1, "rows": 2, "rows-agent": 3}
 
 _dp = ctypes.POINTER(ctypes.c_double)
 
@@ -297,7 +297,7 @@ class Batch:
     """
 
     def __init__(self, problems, nv, precision="fp32", jump=1.0, lateral="specular",
-                 tile=None, check_every=16, grid=None, stencil_rule=1, device=None):
+                 tile=None, check_every=16, grid=None, stencil_rule=1, device=None, schedule="auto"):
         import torch
 
         lib = load()
@@ -309,7 +309,7 @@ class Batch:
         self._keep = []
         for i, (m, kn) in enumerate(problems):
             c, keep = make_config(m, nv, kn, jump, precision, lateral, False, tile, check_every,
-                                  grid, stencil_rule)
+                                  grid, stencil_rule, schedule)
             cfgs[i] = c
             self._keep.append(keep)
         self.device = torch.device("cuda", torch.cuda.current_device() if device is None else device)
@@ -364,6 +364,10 @@ class Batch:
         if diagnostics:
             out += [tau.reshape(shape), q.reshape((dim,) + shape)]
         return tuple(out)
+
+    @property
+    def schedule(self):
+        return {0: "diagonals", 1: "rows", 2: "rows-xcd"}[load().pdvm_sweep_schedule(self._h)]
 
     def flux(self, i):
         gp = ctypes.c_double()

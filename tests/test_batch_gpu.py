@@ -85,3 +85,19 @@ def test_autotuner_times_candidates_and_caches(tmp_path, monkeypatch):
         res.append(s.moments(diagnostics=False))
         s.close()
     assert np.array_equal(res[0][1], res[1][1])
+
+
+@pytest.mark.parametrize("nv,precision", [([6, 6], "fp64"), ([24, 24], "fp32")])
+def test_batch_row_pipeline_equals_tile_diagonals_bitwise(nv, precision):
+    """All problems of a batch in one row-pipeline launch (each problem's
+    blocks padded to multiples of 8) against the per-diagonal launches."""
+    probs = masks()
+    res = []
+    for sched in ("rows", "diagonals"):
+        b = poredvm.Batch(probs, nv, precision=precision, tile=[8, 8], schedule=sched)
+        assert b.schedule.startswith(sched[:4])
+        b.iterate(9)
+        res.append([b.moments(i) for i in range(len(probs))])
+        b.close()
+    for (ra, ua), (rb, ub) in zip(res[0], res[1]):
+        assert np.array_equal(ra, rb) and np.array_equal(ua, ub)

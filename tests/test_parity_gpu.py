@@ -127,20 +127,22 @@ def test_row_pipeline_equals_tile_diagonals_bitwise(shape, nv, tile, precision, 
     assert np.array_equal(a[0], b[0]) and np.array_equal(a[1], b[1]) and ka == kb and ra == rb
 
 
-def test_row_pipeline_uses_the_xcd_local_protocol_when_chains_fill_xcds():
-    """32 x 32 and 16 x 32 velocities give 16 and 8 velocity chains: every chain
-    lands on one XCD, so the probe selects the XCD-local protocol (the cases
-    above then exercise it); 6 x 8 velocities give 4 chains and the
-    agent-scope protocol."""
+def test_row_pipeline_protocols():
+    """Every tile row is padded to a multiple of 8 blocks, so under round-robin
+    placement each velocity chain runs on one XCD whatever the velocity grid:
+    the creation probe confirms it and the automatic choice is the XCD-local
+    row pipeline. ROWS_AGENT forces the agent-scope protocol; all three give
+    the same iterates."""
     m = random_mask((40, 48), 0.3, 5)
-    for nv, want in (([32, 32], "rows-xcd"), ([16, 32], "rows-xcd"), ([6, 8], "rows")):
-        s = poredvm.Solver(m, nv, 0.6, schedule="rows")
-        assert s.schedule == want, (nv, s.schedule)
-        s.close()
-    s = poredvm.Solver(m, [6, 8], 0.6)  # automatic: no cheap protocol, tile diagonals
-    assert s.schedule == "diagonals"
-    s.close()
-
+    res = []
+    for nv in ([32, 32], [6, 8], [24, 24]):
+        for sched, want in (("auto", "rows-xcd"), ("rows-agent", "rows"), ("diagonals", "diagonals")):
+            s = poredvm.Solver(m, nv, 0.6, schedule=sched)
+            assert s.schedule == want, (nv, sched, s.schedule)
+            s.iterate(5)
+            res.append(s.moments(diagnostics=False)[1])
+            s.close()
+        assert np.array_equal(res[-3], res[-2]) and np.array_equal(res[-3], res[-1])
 
 def test_minimal_domain_and_grid():
     m = np.zeros((2, 2), np.uint8)
