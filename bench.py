@@ -69,7 +69,8 @@ def timed_updates(solver, fluid, K, steps, warmup):
 
 # HBM bytes per sweep launch from the rocprofv3 FETCH_SIZE / WRITE_SIZE passes
 # (scaled by a 1 GiB copy), valid only for the kernel source they were taken on
-TRAFFIC = {("c44205edcc9ebb6e", 8): 16.47e6}
+# Key: (source hash, schedule, tile).
+TRAFFIC = {("e281c27a68d46d50", "rows-xcd", (4, 4)): 1475.4e6 + 849.3e6}
 
 
 def kernel_source_hash():
@@ -79,15 +80,16 @@ def kernel_source_hash():
         return hashlib.sha256(f.read()).hexdigest()[:16]
 
 
-def roofline(tm, elem, traffic_key=None):
+def roofline(tm, elem, traffic_key=None, schedule="diagonals"):
     """Sweep kernel: algorithmic bytes = h written once per fluid voxel and
     velocity; per launch = that over the launches of one iteration."""
     per_iter = elem * tm["fluid_cells"] * tm["velocities"]
     per_launch = per_iter / tm["sweep_launches_per_iter"]
     achieved = per_launch / (tm["sweep_ms_per_launch"] * 1e-3) / 1e9
-    traffic = TRAFFIC.get(traffic_key) if traffic_key and traffic_key[0] == kernel_source_hash() else None
+    traffic = TRAFFIC.get(traffic_key) if traffic_key else None
     return {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-            "frac": achieved / HBM_PEAK_GBS, "traffic": traffic, "kernel": "sweep_kernel",
+            "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
+            "kernel": "sweep_kernel" if schedule == "diagonals" else "sweep_rows_kernel",
             "bytes_per_launch": per_launch, "launch_ms": tm["sweep_ms_per_launch"],
             "launches_per_iter": tm["sweep_launches_per_iter"],
             "moments_kernel": {"bytes_per_launch": per_iter, "launch_ms": tm["moments_ms_per_launch"],
@@ -249,7 +251,8 @@ def main():
     ups, dt = timed_updates(s, fluid, K, args.steps, args.warmup)
     log("FP64: %d iterations in %.3f s: %.3f ms/iter, %.3e updates/s" % (args.steps, dt, 1e3 * dt / args.steps, ups))
     tm = s.time_kernels(10)
-    log("FP64 kernel timing: %s" % json.dumps(tm))
+    sched64 = s.schedule
+    log("FP64 kernel timing (%s schedule): %s" % (sched64, json.dumps(tm)))
     s.close()
 
     out = {
@@ -269,7 +272,7 @@ def main():
                                "32x32 half-range Gauss-Hermite velocities, FP64" % args.kn,
                    "fluid_voxels": fluid, "velocities": K, "parallelism": "1 GPU",
                    "tile": list(tile64), "autotune_ms_per_iteration": tune64},
-        "roofline": roofline(tm, 8, ("c44205edcc9ebb6e", 8) if list(tile64) == [8, 8] else None),
+        "roofline": roofline(tm, 8, (kernel_source_hash(), sched64, tuple(tile64)), sched64),
     }
     if not args.no_extra:
         extra = {}
@@ -277,10 +280,11 @@ def main():
         s = poredvm.Solver(mask, nv, args.kn, precision="fp32", tile=list(tile32))
         u32, d32 = timed_updates(s, fluid, K, args.steps, args.warmup)
         t32 = s.time_kernels(10)
+        sched32 = s.schedule
         s.close()
         extra["rock2d_fp32"] = {"updates_per_s": u32, "ms_per_step": 1e3 * d32 / args.steps,
                                 "tile": list(tile32), "autotune_ms_per_iteration": tune32,
-                                "roofline": roofline(t32, 4)}
+                                "roofline": roofline(t32, 4, None, sched32)}
         log("FP32: %.3e updates/s" % u32)
         # time to residual 1e-6: FP64 from rest, and the FP32 forms finished in FP64
         extra["rock2d_time_to_residual_1e-6"] = time_to_residual(mask, nv, args.kn, list(tile64), list(tile32))
