@@ -601,6 +601,14 @@ int setup_problem(pdvm_solver *s, int i) {
   g.diag_off = (const int32_t *)(b + L.offs);
   g.ndiag = P.ndiag;
   g.progress = (int32_t *)(b + L.progress);
+  {
+    int khz = 0;
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess || hipDeviceGetAttribute(&khz, hipDeviceAttributeWallClockRate, dev) != hipSuccess ||
+        khz <= 0)
+      khz = 100000;  // the 100 MHz of CDNA parts
+    g.wait_ticks = (int64_t)khz * 2000;
+  }
   s->D[i].scratch = (double *)(b + L.scratch);
   geos<T>(s)[i] = g;
 
@@ -646,10 +654,14 @@ int finalize_batch(pdvm_solver *s) {
   }
   s->h_blk_off.assign(n + 1, 0);
   for (int p = 0; p < n; ++p) s->h_blk_off[p + 1] = s->h_blk_off[p] + s->P[p].mom_blocks;
-  // row pipeline: per problem, tile rows x (chains rounded up to 8) blocks
-  const int stride = ((P0.ngroups << P0.dim) + 7) / 8 * 8;
+  int tile_edge = kTileEdge[0];
+  for (auto &P : s->P)
+    if (std::max(P.tile[0], P.tile[1]) > kTileEdge[0]) tile_edge = kTileEdge[1];
+  // row pipeline: per problem, bands of band_waves tile rows x (chains
+  // rounded up to 8) blocks
+  const int stride = ((P0.ngroups << P0.dim) + 7) / 8 * 8, nw = band_waves(tile_edge);
   s->h_row_off.assign(n + 1, 0);
-  for (int p = 0; p < n; ++p) s->h_row_off[p + 1] = s->h_row_off[p] + s->P[p].ntile[1] * stride;
+  for (int p = 0; p < n; ++p) s->h_row_off[p + 1] = s->h_row_off[p] + (s->P[p].ntile[1] + nw - 1) / nw * stride;
   const size_t geo_b = align256(n * sizeof(Geo<T>));
   const size_t item_b = align256(s->h_item_off.size() * 4);
   const size_t blk_b = align256(s->h_blk_off.size() * 4);
@@ -670,9 +682,7 @@ int finalize_batch(pdvm_solver *s) {
   B.nprob = n;
   B.dim = P0.dim;
   B.Ko = P0.Ko;
-  B.tile_edge = kTileEdge[0];
-  for (auto &P : s->P)
-    if (std::max(P.tile[0], P.tile[1]) > kTileEdge[0]) B.tile_edge = kTileEdge[1];
+  B.tile_edge = tile_edge;
   B.y2wall = P0.stencil_rule == 0;
   B.ndiag_max = ndmax;
   B.d_geo = (const Geo<T> *)geo;
@@ -759,9 +769,9 @@ bool same_velocity_grid(const Problem &a, const Problem &b) {
          std::equal(a.wq.begin(), a.wq.begin() + a.Ko_pad, b.wq.begin());
 }
 
-// Whether every chain of the row pipeline (blocks c, c + nchains, ...) runs on
-// a single XCD: run the pipeline's grid once with a kernel that records each
-// block's XCD. Needs at least two distinct XCDs in the record (so the register
+// Whether every chain of the row pipeline (blocks c, c + stride, ...) runs on
+// a single XCD: run the pipeline's grid (same blocks, same block size) once
+// with a kernel that records each block's XCD. Needs at least two distinct XCDs in the record (so the register
 // read is live) and one XCD per chain.
 int probe_xcd_locality(pdvm_solver *s) {
   const Problem &P = s->P[0];
@@ -770,7 +780,8 @@ int probe_xcd_locality(pdvm_solver *s) {
   uint32_t *d = nullptr;
   if (hipMalloc(&d, sizeof(uint32_t) * blocks) != hipSuccess) return s->fail(PDVM_E_NOMEM, "probe allocation failed");
   std::vector<uint32_t> h(blocks);
-  hipError_t e = launch_xcd_probe(d, blocks, s->stream);
+  const int tile_edge = s->precision == PDVM_FP64 ? s->bd.tile_edge : s->bf.tile_edge;
+  hipError_t e = launch_xcd_probe(d, blocks, kWave * band_waves(tile_edge), s->stream);
   if (e == hipSuccess) e = hipMemcpyAsync(h.data(), d, sizeof(uint32_t) * blocks, hipMemcpyDeviceToHost, s->stream);
   if (e == hipSuccess) e = hipStreamSynchronize(s->stream);
   (void)hipFree(d);

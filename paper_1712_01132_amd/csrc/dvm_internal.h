@@ -7,6 +7,9 @@
 namespace pdvm {
 
 constexpr int kWave = 64;     // CDNA wavefront width: one discrete velocity per lane
+// Tile rows (one wavefront each) per block of the 2D row-pipeline sweep, by
+// compiled tile edge: the LDS ring between them fits twice in one CU's LDS.
+constexpr int band_waves(int tile_edge) { return tile_edge == 4 ? 8 : 4; }
 constexpr int kRing = 64;     // permeability history kept at multiples of 100 iterations
 constexpr int kMomBlock = 256;
 constexpr int kSrcStride = 4; // per-voxel source record: nu rho, 2 nu u_1, 2 nu u_2, 2 nu u_3 (0 in 2D)
@@ -81,7 +84,8 @@ struct Geo {
   const T *hprev = nullptr;   // h of the previous iteration: h[par]
   const T *srccur = nullptr, *srctcur = nullptr, *wallcur = nullptr;  // src, srct, wall [par]
   int32_t seq = 0;            // advanced by every arm and reduction: stamps of the row pipeline
-  int32_t *progress = nullptr;  // [ntile1][chains] tiles completed per row (row-pipeline sweep)
+  int32_t *progress = nullptr;  // [bands][chains] tiles completed per band (row-pipeline sweep)
+  int64_t wait_ticks = 0;       // a row-pipeline wait gives up after this many wall-clock ticks (2 s)
 };
 
 // Square sweep tile edges in (x1, x2) compiled into the kernel; the host
@@ -111,12 +115,13 @@ struct Batch {
 // Kernel launchers (dvm_kernels.hip). All enqueue on `st`.
 template <typename T>
 hipError_t launch_sweep(const Batch<T> &B, int diag, hipStream_t st);
-// The whole 2D sweep of every problem of the batch as one row-pipeline launch;
-// `local`: every chain's rows run on one XCD (checked with launch_xcd_probe).
+// The whole 2D sweep of every problem of the batch as one row-pipeline launch
+// of bands of band_waves(tile edge) tile rows per block; `local`: every
+// chain's bands run on one XCD (checked with launch_xcd_probe).
 template <typename T>
 hipError_t launch_sweep_rows(const Batch<T> &B, bool local, hipStream_t st);
 // out[b] = the XCD that block b of a `blocks`-block grid runs on.
-hipError_t launch_xcd_probe(uint32_t *out, int blocks, hipStream_t st);
+hipError_t launch_xcd_probe(uint32_t *out, int blocks, int threads, hipStream_t st);
 template <typename T>
 hipError_t launch_moments(const Batch<T> &B, hipStream_t st);
 template <typename T>

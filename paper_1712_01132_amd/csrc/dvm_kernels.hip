@@ -14,6 +14,8 @@
 //                     coefficients, and per-block FP64 residual / flux partials.
 //   reduce_kernel     steps (iv)-(v): FP64 residual, G_p, k (Eq. k_Gp), Err(l)
 //                     (Eq. convergence_criterion), stop decision, state flip.
+#include <type_traits>
+
 #include "dvm_internal.h"
 
 namespace pdvm {
@@ -89,6 +91,20 @@ __device__ __forceinline__ T upstream_fluid(const Dom<T> &g, PC hc, PP hp, int j
   c[j] = im.r;
   const T v = hp[cell_of(g, c[0], c[1], c[2]) * g.Kpad + (im.mir ? kmir : kofs)];
   return im.jmp ? v + T(im.jmp) * g.jump : v;
+}
+
+// Address of h at an upstream node (x, y) along lateral axis 1 in 2D, as in
+// upstream_fluid: the current sweep inside the domain, the previous
+// iteration's image (mirrored velocity, no jump) outside it.
+template <typename T>
+__device__ __forceinline__ gptr<const T> upstream_addr(const Dom<T> &g, gptr<const T> hc, gptr<const T> hp, int j,
+                                                       int x, int y, int kofs, int kmir) {
+  int c[2] = {x, y};
+  const bool in = c[j] >= 0 && c[j] < g.n[j];
+  const Img im = image_of(j, c[j], g.n[j], g.latp);
+  if (!in) c[j] = im.r;
+  const int k = (!in && im.mir) ? kmir : kofs;
+  return (in ? hc : hp) + cell_of(g, c[0], c[1], 0) * g.Kpad + k;
 }
 
 // Wall value of a solid met at the second upstream node along axis j: the wall
@@ -347,7 +363,7 @@ __global__ void __launch_bounds__(kWave)
         T num = fma(rp[1], vv[0], rp[0]);
         num = fma(rp[2], vv[1], num);
         if (DIM == 3) num = fma(rp[3], vv[2], num);
-        if (tau_fb) num = fma(rp[4], vsqm, num);
+        num = fma(rp[4], vsqm, num);  // rp[4] = vsqm = 0 without the feedback
         const T x1a = i >= 1 ? D1[r] : L1[r];
         const T x1b = i >= 2 ? D2[r] : (i == 1 ? L1[r] : L2[r]);
         const T x2a = r >= 1 ? D1[r >= 1 ? r - 1 : 0] : B1[i];
@@ -376,47 +392,55 @@ __global__ void __launch_bounds__(kWave)
   }
 }
 
-// Step (i) in 2D as one launch: a row pipeline of tiles. Wavefront (chain c,
-// row j) owns tile row j (in the octant's sweep order) of velocity chain c =
-// (octant, 64-velocity group) and walks its tiles along x1 in sweep order.
-// Within a tile the walk is the one of sweep_kernel (same records, same
-// arithmetic, so both schedules give bitwise identical results). The left
-// halo of a tile is the last two columns of the wavefront's previous tile,
-// kept in registers; the bottom halo is the top two rows of tile (a, j - 1),
-// computed by the wavefront of row j - 1 of the same chain. That wavefront
-// publishes its progress with an agent-scope release after each tile; this
-// one waits for it with a bounded spin and an agent-scope acquire. Stamps
-// never repeat (seq * ntile0 + a + 1, seq advanced by every arm and every
-// reduction), so the counters are never reset. Producers have lower block
-// indices than their consumers (block = j * nchains + c), so in-order dispatch
-// cannot deadlock; a spin that still exceeds its bound flags ctl->fault and
-// lets every wavefront finish.
-constexpr int kSpinLimit = 1 << 20;  // about 50 ms of sleeping polls
+// Step (i) in 2D as one launch: a pipeline of tile rows. Block (problem p,
+// band b, chain c) holds NW wavefronts; wavefront w owns tile row j = b NW + w
+// (in the octant's sweep order) of velocity chain c = (octant, 64-velocity
+// group) and walks its tiles along x1 in sweep order. Within a tile the walk
+// is the one of sweep_kernel (same records, same arithmetic, so both
+// schedules give bitwise identical iterates). The left halo of a tile is the
+// last two columns of the wavefront's previous tile, kept in registers. The
+// bottom halo is the top two rows of tile (a, j - 1):
+// * inside a band the wavefront below hands them over through an LDS ring of
+//   two slots, with per-wavefront tile counters in LDS: `made` by the
+//   producer after its slot writes, `used` by the consumer after its reads,
+//   so a slot is rewritten only once it has been read. No global store is
+//   waited for on this path;
+// * across bands they are read from h once the band below has published its
+//   progress counter. Stamps (seq * ntile0 + a + 1) never repeat, since seq
+//   advances with every arm and every reduction, so counters are never reset.
+// Producers have lower block indices than their consumers (block = row_off[p]
+// + b * stride + c), so in-order dispatch cannot deadlock. Every wait is
+// bounded in wall-clock time (Geo::wait_ticks): one that exceeds it flags
+// ctl->fault and lets every wavefront finish.
 //
-// Two publication protocols. LOCAL (the host has checked that every row of a
-// chain runs on the same XCD, so producer and consumer share one L2): the
-// producer drains its stores into the L2 (s_waitcnt) and then writes the
-// counter with a relaxed agent-scope store; the consumer polls it with relaxed
-// agent-scope loads, which no CU's L1 can serve stale, and then reads the halo
-// through the shared L2. No L2 write-back or invalidation is needed. The halo
-// lines cannot be stale in the consumer's L1: the L1 starts the kernel empty
-// and a chain's 64-velocity segments are read only by the row above them,
-// after the counter. (A workgroup-scope counter polled after an L1
-// invalidation was never observed on gfx950.) Otherwise: agent-scope release
-// and acquire, correct for any placement.
-
-template <typename T, int TT, bool Y2WALL, bool LOCAL>
-__global__ void __launch_bounds__(kWave)
+// Two publication protocols between bands. LOCAL (the host has checked that
+// every band of a chain runs on the same XCD, so producer and consumer share
+// one L2): the producer drains its stores into the L2 (s_waitcnt) and then
+// writes the counter with a relaxed agent-scope store; the consumer polls it
+// with relaxed agent-scope loads, which no CU's L1 can serve stale, and then
+// reads the halo through the shared L2. No L2 write-back or invalidation is
+// needed. The halo lines cannot be stale in the consumer's L1: the L1 starts
+// the kernel empty and a chain's 64-velocity segments of a band's top rows
+// are read only by the band above, after the counter. (A workgroup-scope
+// counter polled after an L1 invalidation was never observed on gfx950.)
+// Otherwise: agent-scope release and acquire, correct for any placement.
+//
+// Lanes past the octant size read every per-velocity value and every halo
+// from slot 0, so they compute bit-exact copies of lane 0 and store them to
+// lane 0's slot: every store is then decided by the voxel alone (uniform),
+// without a per-lane mask.
+template <typename T, int TT, bool Y2WALL, bool LOCAL, int NW>
+__global__ void __launch_bounds__(kWave * NW)
     sweep_rows_kernel(const Geo<T> *__restrict__ G, const int *__restrict__ row_off, int nprob, int stride) {
   constexpr int DIM = 2;
   constexpr int NC = TT * TT;
   constexpr int RW = 5 + 3 * DIM;
+  constexpr int RING = 2;
   __shared__ T rd_lds[4 * kWave];
-  __shared__ T rec[NC * RW];
-  __shared__ uint32_t rcode[NC];
-  // block = row_off[p] + j * stride + c: problem p, tile row j, velocity chain
-  // c; stride and row_off[p] are multiples of 8, so chain c of every row runs
-  // on XCD (c mod 8) under round-robin placement
+  __shared__ T rec_lds[NW][NC * RW];
+  __shared__ uint32_t rcode_lds[NW][NC];
+  __shared__ T ring[NW > 1 ? NW - 1 : 1][RING][2 * TT][kWave];
+  __shared__ int32_t made[NW], used[NW];
   const int p = nprob > 1 ? owner_of(row_off, nprob, blockIdx.x) : 0;
   const Geo<T> &G_ = G[p];
   if (!G_.run) return;
@@ -427,22 +451,30 @@ __global__ void __launch_bounds__(kWave)
   const gptr<const T> absv = as_global(G_.absv), avv = as_global(G_.av), rden = as_global(G_.rden),
                       vsq = as_global(G_.vsqm);
   const gptr<T> hc = as_global(G_.hcur);
+  const gptr<const T> hcc = hc;
   const gptr<const T> hp = as_global(G_.hprev);
   const gptr<const T> src = as_global(G_.srccur);
   const gptr<const T> srct = as_global(G_.srctcur);
   const gptr<const T> wall = as_global(G_.wallcur);
   const gptr<const uint32_t> flags = as_global(G_.flags);
   const gptr<int32_t> progress = as_global(G_.progress);
+  const gptr<int32_t> fault = as_global(&G_.ctl->fault);
   const uint32_t seq = (uint32_t)G_.seq;
   const int n0 = dm.n[0], n1 = dm.n[1];
   const int nchains = ngroups << DIM;
+  // block = row_off[p] + band * stride + c; stride and row_off[p] are
+  // multiples of 8, so chain c of every band runs on XCD (c mod 8) under
+  // round-robin placement
   const int local_b = nprob > 1 ? blockIdx.x - row_off[p] : blockIdx.x;
   const int c = local_b % stride;
-  const int j = local_b / stride;  // tile row in sweep order
-  if (c >= nchains) return;        // padding of the row to a multiple of 8 blocks
+  const int band = local_b / stride;
+  if (c >= nchains) return;  // padding of the band to a multiple of 8 blocks
+  // the wavefront index, held in a scalar register so that everything that
+  // depends on the row is wavefront-uniform to the compiler
+  const int w = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave), lane = threadIdx.x % kWave;
+  const int j = band * NW + w;  // tile row in sweep order
   const int grp = c % ngroups;
   const int o = c / ngroups;
-  const int lane = threadIdx.x;
   const int q = grp * kWave + lane;
   const bool active = q < Ko;
   const int qq = active ? q : 0;
@@ -460,10 +492,23 @@ __global__ void __launch_bounds__(kWave)
     vv[k] = s[k] > 0 ? av : -av;
     aa[k] = avv[k * Ko_pad + qq];
   }
+  if (w == 0) {
 #pragma unroll
-  for (int k = 0; k < 4; ++k) rd_lds[k * kWave + lane] = rden[k * Ko_pad + qq];
+    for (int k = 0; k < 4; ++k) rd_lds[k * kWave + lane] = rden[k * Ko_pad + qq];
+  }
+  if (lane == 0) {
+    made[w] = 0;
+    used[w] = 0;
+  }
+  __syncthreads();          // the only block-wide barrier
+  if (j >= ntile1) return;  // the last band may be partial
+  T *const rec = rec_lds[w];
+  uint32_t *const rcode = rcode_lds[w];
   const T vsqm = tau_fb ? vsq[qq] : T(0);
   const int kofs = o * Ko_pad + qq;
+  // byte offset of this lane's slot in a voxel's distribution, for stores
+  // from a wavefront-uniform voxel address
+  const uint32_t kst = (uint32_t)kofs * (uint32_t)sizeof(T);
   int kmir[3];
 #pragma unroll
   for (int k = 0; k < 3; ++k) kmir[k] = (o ^ (1 << k)) * Ko_pad + qq;
@@ -472,18 +517,53 @@ __global__ void __launch_bounds__(kWave)
   const int tj = s[1] > 0 ? j : ntile1 - 1 - j;
   const int lo1 = tj * tile1, cnt1 = min(tile1, n1 - lo1);
   const int ys = s[1] > 0 ? lo1 : lo1 + cnt1 - 1;
-  const bool yin = ys - 2 * s[1] >= 0 && ys - 2 * s[1] < n1;
-  const gptr<int32_t> wait_on = progress + (j > 0 ? (j - 1) * nchains + c : 0);
-  const gptr<int32_t> publish = progress + j * nchains + c;
-  const gptr<int32_t> fault = as_global(&G_.ctl->fault);
-  const gptr<T> hz = hc + kofs;  // plane 0 of the current sweep
-  int spins = 0;
+  const bool lwait = w > 0;                          // bottom halo from the wavefront below (LDS)
+  const bool gwait = w == 0 && band > 0;             // from the band below (h)
+  const bool lmake = w < NW - 1 && j + 1 < ntile1;   // top rows to the wavefront above (LDS)
+  const bool gmake = w == NW - 1 && j + 1 < ntile1;  // progress to the band above
+  const gptr<int32_t> wait_on = progress + (band > 0 ? (band - 1) * nchains + c : 0);
+  const gptr<int32_t> publish = progress + band * nchains + c;
+  const gptr<T> hz = hc;  // plane 0 of the current sweep
+  const int64_t wait_ticks = G_.wait_ticks;
+  // Bounded wait: polls `ready` until it holds; after wait_ticks of the
+  // wall clock (checked every 64 polls) it flags ctl->fault and gives up.
+  auto bounded_wait = [&](auto ready, int sleep2) __attribute__((always_inline)) {
+    int n = 0;
+    int64_t t0 = 0;
+    while (!ready()) {
+      if ((++n & 63) == 0) {
+        const int64_t t = wall_clock64();
+        if (n == 64) {
+          t0 = t;
+        } else if (t - t0 > wait_ticks) {
+          __hip_atomic_store(fault, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+          break;
+        }
+      }
+      if (sleep2) __builtin_amdgcn_s_sleep(2);
+      else __builtin_amdgcn_s_sleep(1);
+    }
+  };
+  auto lds_wait = [&](int32_t *ctr, int32_t want) __attribute__((always_inline)) {
+    bounded_wait([&] { return __hip_atomic_load(ctr, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP) >= want; }, 0);
+    __atomic_signal_fence(__ATOMIC_SEQ_CST);  // no LDS access below is moved above the poll
+  };
+  auto lds_post = [&](int32_t *ctr, int32_t v) __attribute__((always_inline)) {
+    __atomic_signal_fence(__ATOMIC_SEQ_CST);
+    __builtin_amdgcn_s_waitcnt(0xC07F);  // lgkmcnt(0): this wavefront's LDS accesses are done
+    __atomic_signal_fence(__ATOMIC_SEQ_CST);
+    __hip_atomic_store(ctr, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+  };
 
   T L1[TT], L2[TT];  // left halo: previous tile's last two columns, or images
 #pragma unroll
   for (int k = 0; k < TT; ++k) L1[k] = L2[k] = T(0);
 
-  // raw data of voxel `lane` of tile a of this row, loaded one tile ahead
+  // raw data of voxel `lane` of tile a of this row, loaded one tile ahead.
+  // The loads are unconditional (lanes outside the tile read voxel 0 and
+  // discard it), so the code is straight-line and the compiler can count the
+  // loads in flight exactly: vector-memory loads complete in issue order, and
+  // a wait for the halo must not also wait for this prefetch.
   struct Raw {
     uint32_t f;
     T sv0, sv1, sv2, svt, wv[2];
@@ -493,29 +573,44 @@ __global__ void __launch_bounds__(kWave)
     const int lo0 = ta * tile0, cnt0 = min(tile0, n0 - lo0);
     const int xs = s[0] > 0 ? lo0 : lo0 + cnt0 - 1;
     const int i = lane % TT, r = lane / TT;
-    R.f = F_SOLID;
-    if (lane < NC && i < cnt0 && r < cnt1) {
-      const int cc = (ys + r * s[1]) * n0 + xs + i * s[0];
-      R.f = flags[cc];
-      const gptr<const T> sp = src + cc * kSrcStride;
-      R.sv0 = sp[0];
-      R.sv1 = sp[1];
-      R.sv2 = sp[2];
-      R.svt = tau_fb ? srct[cc] : T(0);
+    const bool in = lane < NC && i < cnt0 && r < cnt1;
+    const int cc = in ? (ys + r * s[1]) * n0 + xs + i * s[0] : 0;
+    const uint32_t f = flags[cc];
+    const gptr<const T> sp = src + cc * kSrcStride;
+    R.sv0 = sp[0];
+    R.sv1 = sp[1];
+    R.sv2 = sp[2];
+    const T st = srct[cc];
+    R.svt = tau_fb ? st : T(0);
 #pragma unroll
-      for (int k = 0; k < DIM; ++k) R.wv[k] = wall[cc * 6 + 2 * k + pin[k]];
-    }
+    for (int k = 0; k < DIM; ++k) R.wv[k] = wall[cc * 6 + 2 * k + pin[k]];
+    R.f = in ? f : F_SOLID;
   };
   Raw nxt;
   fetch(0, nxt);
+
+  // left halo of the first tile: images across the x1 wrap
+  {
+    const int lo0 = (s[0] > 0 ? 0 : ntile0 - 1) * tile0, cnt0 = min(tile0, n0 - lo0);
+    const int xs = s[0] > 0 ? lo0 : lo0 + cnt0 - 1;
+#pragma unroll
+    for (int k = 0; k < TT; ++k)
+      if (k < cnt1) {
+        const int y = ys + k * s[1];
+        L1[k] = upstream_fluid(dm, hc, hp, 0, xs - s[0], y, 0, kofs, kmir[0]);
+        L2[k] = upstream_fluid(dm, hc, hp, 0, xs - 2 * s[0], y, 0, kofs, kmir[0]);
+      }
+  }
+  // uniform byte address of row r's first voxel in the current tile
+  gptr<char> hrow[TT];
 
   for (int a = 0; a < ntile0; ++a) {
     const int ta = s[0] > 0 ? a : ntile0 - 1 - a;
     const int lo0 = ta * tile0, cnt0 = min(tile0, n0 - lo0);
     const int xs = s[0] > 0 ? lo0 : lo0 + cnt0 - 1;
+    const int slot = a % RING;
     // --- records of this tile from the prefetched data ----------------------
     const Raw cur = nxt;
-    if (a + 1 < ntile0) fetch(a + 1, nxt);  // in flight during this tile's wait and walk
     if (lane < NC) {
       const int i = lane % TT, r = lane / TT;
       uint32_t code = R_SKIP;
@@ -535,130 +630,164 @@ __global__ void __launch_bounds__(kWave)
           const bool first = fj & 1u, y1s = fj & 2u, y2s = fj & 4u;
           T c1 = first ? (y1s ? T(0) : T(1)) : T(2);
           T c2 = first ? T(0) : T(-0.5);
-          T w = (first && y1s) ? cur.wv[k] : T(0);
+          T wl = (first && y1s) ? cur.wv[k] : T(0);
           if (Y2WALL && !first && y2s) {
             c2 = T(0);
-            w = T(-0.5) * wall_at_y1(dm, wall, k, s[k], pin[k], x, y, 0);
+            wl = T(-0.5) * wall_at_y1(dm, wall, k, s[k], pin[k], x, y, 0);
           }
           rp[5 + 3 * k] = c1;
           rp[6 + 3 * k] = c2;
-          rp[7 + 3 * k] = w;
+          rp[7 + 3 * k] = wl;
           code |= (first ? 1u : 0u) << k;
         }
       }
       rcode[lane] = code;
     }
-    // --- left halo of the first tile: images across the x1 wrap ------------
-    if (a == 0) {
-#pragma unroll
-      for (int k = 0; k < TT; ++k)
-        if (k < cnt1) {
-          const int y = ys + k * s[1];
-          L1[k] = upstream_fluid(dm, hc, hp, 0, xs - s[0], y, 0, kofs, kmir[0]);
-          L2[k] = upstream_fluid(dm, hc, hp, 0, xs - 2 * s[0], y, 0, kofs, kmir[0]);
-        }
-    }
-    // --- bottom halo: wait for tile (a, j - 1), then read its top rows -------
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    // --- bottom halo ------------------------------------------------------------
     T B1[TT], B2[TT];
+    if (lwait) {
+      lds_wait(&made[w - 1], a + 1);
 #pragma unroll
-    for (int k = 0; k < TT; ++k) B1[k] = B2[k] = T(0);
-    if (j > 0) {
-      const int32_t want = (int32_t)(seq * (uint32_t)ntile0 + (uint32_t)(a + 1));
-      while (true) {
-        const int32_t got = __hip_atomic_load(wait_on, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        if ((int32_t)(got - want) >= 0) break;
-        if (++spins > kSpinLimit) {
-          __hip_atomic_store(fault, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-          break;
-        }
-        __builtin_amdgcn_s_sleep(2);
+      for (int k = 0; k < TT; ++k) {
+        B1[k] = ring[w - 1][slot][k][lane];
+        B2[k] = ring[w - 1][slot][TT + k][lane];
       }
-      if (!LOCAL) __atomic_thread_fence(__ATOMIC_ACQUIRE);  // agent scope: the producer's stores are visible
-    }
-#pragma unroll
-    for (int k = 0; k < TT; ++k)
-      if (k < cnt0) {
-        const int x = xs + k * s[0];
-        if (yin) {
-          B1[k] = hz[(int64_t)((ys - s[1]) * n0 + x) * Kp];
-          B2[k] = hz[(int64_t)((ys - 2 * s[1]) * n0 + x) * Kp];
-        } else {
-          B1[k] = upstream_fluid(dm, hc, hp, 1, x, ys - s[1], 0, kofs, kmir[1]);
-          B2[k] = upstream_fluid(dm, hc, hp, 1, x, ys - 2 * s[1], 0, kofs, kmir[1]);
-        }
-      }
-    __syncthreads();
-    gptr<T> hrow[TT];
-    int64_t icol[TT];
-#pragma unroll
-    for (int k = 0; k < TT; ++k) {
-      hrow[k] = hz + (int64_t)((ys + k * s[1]) * n0 + xs) * Kp;
-      icol[k] = (int64_t)k * s[0] * Kp;
-    }
-    // --- the tile's anti-diagonals (as in sweep_kernel) ---------------------
-    T D1[TT], D2[TT], LN1[TT], LN2[TT];
-#pragma unroll
-    for (int k = 0; k < TT; ++k) D1[k] = D2[k] = LN1[k] = LN2[k] = T(0);
-#pragma unroll
-    for (int d = 0; d < 2 * TT - 1; ++d) {
-      T Nw[TT];
-      uint32_t Nc[TT];
-#pragma unroll
-      for (int r = 0; r < TT; ++r) {
-        Nw[r] = T(0);
-        Nc[r] = R_SKIP;
-      }
-#pragma unroll
-      for (int r = 0; r < TT; ++r) {
-        const int i = d - r;
-        if (i < 0 || i >= TT) continue;
-        const uint32_t code = __builtin_amdgcn_readfirstlane(rcode[i + TT * r]);
-        const T *rp = rec + (i + TT * r) * RW;
-        T num = fma(rp[1], vv[0], rp[0]);
-        num = fma(rp[2], vv[1], num);
-        if (tau_fb) num = fma(rp[4], vsqm, num);
-        const T x1a = i >= 1 ? D1[r] : L1[r];
-        const T x1b = i >= 2 ? D2[r] : (i == 1 ? L1[r] : L2[r]);
-        const T x2a = r >= 1 ? D1[r >= 1 ? r - 1 : 0] : B1[i];
-        const T x2b = r >= 2 ? D2[r >= 2 ? r - 2 : 0] : (r == 1 ? B1[i] : B2[i]);
-        num = fma(aa[0], fma(rp[5], x1a, fma(rp[6], x1b, rp[7])), num);
-        num = fma(aa[1], fma(rp[8], x2a, fma(rp[9], x2b, rp[10])), num);
-        Nw[r] = num * rd_lds[(code & 7u) * kWave + lane];
-        Nc[r] = code;
-        if (i == cnt0 - 1) LN1[r] = Nw[r];  // the tile's last column in sweep order
-        if (i == cnt0 - 2) LN2[r] = Nw[r];
-      }
-#pragma unroll
-      for (int r = 0; r < TT; ++r) {
-        const int i = d - r;
-        if (i < 0 || i >= TT) continue;
-        if (active && !(Nc[r] & R_SKIP)) hrow[r][icol[i]] = Nw[r];
-      }
-#pragma unroll
-      for (int r = 0; r < TT; ++r) {
-        D2[r] = D1[r];
-        D1[r] = Nw[r];
-      }
-    }
-    // --- publish the tile: its stores before the counter ---------------------
-    __syncthreads();
-    const int32_t stamp = (int32_t)(seq * (uint32_t)ntile0 + (uint32_t)(a + 1));
-    if (LOCAL) {
-      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
-      __builtin_amdgcn_s_waitcnt(0);  // every store of the wavefront has reached the L2
-      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
-      if (lane == 0) __hip_atomic_store(publish, stamp, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     } else {
-      if (lane == 0) __hip_atomic_store(publish, stamp, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+      if (gwait) {
+        const int32_t want = (int32_t)(seq * (uint32_t)ntile0 + (uint32_t)(a + 1));
+        bounded_wait(
+            [&] {
+              const int32_t got = __hip_atomic_load(wait_on, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+              return (int32_t)(got - want) >= 0;
+            },
+            1);
+        if (!LOCAL) __atomic_thread_fence(__ATOMIC_ACQUIRE);  // agent scope: the producer's stores are visible
+      }
+      __atomic_signal_fence(__ATOMIC_SEQ_CST);  // no load below is moved above the poll
+#pragma unroll
+      for (int k = 0; k < TT; ++k) {
+        // straight-line: columns past the tile re-read its last one; only
+        // voxels outside the tile, which are never stored, see them
+        const int x = xs + min(k, cnt0 - 1) * s[0];
+        B1[k] = *upstream_addr(dm, hcc, hp, 1, x, ys - s[1], kofs, kmir[1]);
+        B2[k] = *upstream_addr(dm, hcc, hp, 1, x, ys - 2 * s[1], kofs, kmir[1]);
+      }
     }
+    // the next tile's records, in flight during this tile's walk; issued after
+    // the halo loads so that the walk waits only for the halo (the last tile
+    // fetches itself again, which keeps the code free of branches)
+    fetch(min(a + 1, ntile0 - 1), nxt);
+#pragma unroll
+    for (int k = 0; k < TT; ++k) hrow[k] = (gptr<char>)(hz + (int64_t)((ys + k * s[1]) * n0 + xs) * Kp);
+    const int64_t colb = (int64_t)s[0] * Kp * (int64_t)sizeof(T);  // bytes from one column to the next
+
+    // --- the tile's anti-diagonals (as in sweep_kernel) ---------------------
+    // FULL: a whole TT x TT tile, so the columns and rows handed on are
+    // compile-time ones; otherwise they are selected by the tile's extent.
+    struct Out {
+      T LN1[TT], LN2[TT], T1[TT], T2[TT];  // last two columns, top two rows
+    };
+    auto walk = [&](auto full) __attribute__((always_inline)) {
+      constexpr bool FULL = decltype(full)::value;
+      Out out;
+      T D1[TT], D2[TT];
+#pragma unroll
+      for (int k = 0; k < TT; ++k) D1[k] = D2[k] = out.LN1[k] = out.LN2[k] = out.T1[k] = out.T2[k] = T(0);
+#pragma unroll
+      for (int d = 0; d < 2 * TT - 1; ++d) {
+        T Nw[TT];
+        uint32_t Nc[TT];
+#pragma unroll
+        for (int r = 0; r < TT; ++r) {
+          Nw[r] = T(0);
+          Nc[r] = R_SKIP;
+        }
+#pragma unroll
+        for (int r = 0; r < TT; ++r) {
+          const int i = d - r;
+          if (i < 0 || i >= TT) continue;
+          const uint32_t code = __builtin_amdgcn_readfirstlane(rcode[i + TT * r]);
+          const T *rp = rec + (i + TT * r) * RW;
+          T num = fma(rp[1], vv[0], rp[0]);
+          num = fma(rp[2], vv[1], num);
+          num = fma(rp[4], vsqm, num);
+          const T x1a = i >= 1 ? D1[r] : L1[r];
+          const T x1b = i >= 2 ? D2[r] : (i == 1 ? L1[r] : L2[r]);
+          const T x2a = r >= 1 ? D1[r >= 1 ? r - 1 : 0] : B1[i];
+          const T x2b = r >= 2 ? D2[r >= 2 ? r - 2 : 0] : (r == 1 ? B1[i] : B2[i]);
+          num = fma(aa[0], fma(rp[5], x1a, fma(rp[6], x1b, rp[7])), num);
+          num = fma(aa[1], fma(rp[8], x2a, fma(rp[9], x2b, rp[10])), num);
+          Nw[r] = num * rd_lds[(code & 7u) * kWave + lane];
+          Nc[r] = code;
+          if (FULL) {
+            if (i == TT - 1) out.LN1[r] = Nw[r];
+            if (i == TT - 2) out.LN2[r] = Nw[r];
+            if (r == TT - 1) out.T1[i] = Nw[r];
+            if (r == TT - 2) out.T2[i] = Nw[r];
+          } else {
+            if (i == cnt0 - 1) out.LN1[r] = Nw[r];  // the tile's last column in sweep order
+            if (i == cnt0 - 2) out.LN2[r] = Nw[r];
+            if (r == cnt1 - 1) out.T1[i] = Nw[r];  // its top row
+            if (r == cnt1 - 2) out.T2[i] = Nw[r];
+          }
+        }
+#pragma unroll
+        for (int r = 0; r < TT; ++r) {
+          const int i = d - r;
+          if (i < 0 || i >= TT) continue;
+          if (!(Nc[r] & R_SKIP)) *(gptr<T>)(hrow[r] + i * colb + kst) = Nw[r];
+        }
+#pragma unroll
+        for (int r = 0; r < TT; ++r) {
+          D2[r] = D1[r];
+          D1[r] = Nw[r];
+        }
+      }
+      return out;
+    };
+    const Out res = (cnt0 == TT && cnt1 == TT) ? walk(std::true_type{}) : walk(std::false_type{});
+    T T2[TT];
+#pragma unroll
+    for (int k = 0; k < TT; ++k) T2[k] = res.T2[k];
+    // --- hand the tile on ---------------------------------------------------------
+    if (lmake) {
+      if (cnt1 == 1) {  // a one-row tile passes on its own row and the one below it
+#pragma unroll
+        for (int k = 0; k < TT; ++k) T2[k] = B1[k];
+      }
+      lds_wait(&used[w + 1], a + 1 - RING);  // the slot's previous tile has been read
+#pragma unroll
+      for (int k = 0; k < TT; ++k) {
+        ring[w][slot][k][lane] = res.T1[k];
+        ring[w][slot][TT + k][lane] = T2[k];
+      }
+      lds_post(&made[w], a + 1);
+    }
+    if (gmake) {
+      const int32_t stamp = (int32_t)(seq * (uint32_t)ntile0 + (uint32_t)(a + 1));
+      if (LOCAL) {
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+        __builtin_amdgcn_s_waitcnt(0);  // every store of the wavefront has reached the L2
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+        if (lane == 0) __hip_atomic_store(publish, stamp, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      } else {
+        if (lane == 0) __hip_atomic_store(publish, stamp, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+      }
+    }
+    if (lwait) lds_post(&used[w], a + 1);  // the ring slot has been read (the walk used it)
     // the next tile's left halo: this tile's last two columns (a tile one
     // voxel wide passes on its own column and the one before it)
 #pragma unroll
     for (int k = 0; k < TT; ++k) {
-      L2[k] = cnt0 >= 2 ? LN2[k] : L1[k];
-      L1[k] = LN1[k];
+      L2[k] = cnt0 >= 2 ? res.LN2[k] : L1[k];
+      L1[k] = res.LN1[k];
     }
-    __syncthreads();  // the next tile's records overwrite this tile's
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();  // the next tile's records overwrite this tile's
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
   }
 }
 
@@ -1018,9 +1147,9 @@ hipError_t launch_sweep(const Batch<T> &B, int diag, hipStream_t st) {
 
 template <typename T, bool LOCAL>
 void launch_rows_local(const Batch<T> &B, dim3 grid, hipStream_t st) {
-#define PDVM_ROWS(TTV, Y2)                                                                                   \
-  hipLaunchKernelGGL((sweep_rows_kernel<T, TTV, Y2, LOCAL>), grid, dim3(kWave), 0, st, B.d_geo, B.d_row_off, \
-                     B.nprob, B.row_stride)
+#define PDVM_ROWS(TTV, Y2)                                                                        \
+  hipLaunchKernelGGL((sweep_rows_kernel<T, TTV, Y2, LOCAL, band_waves(TTV)>), grid,              \
+                     dim3(kWave * band_waves(TTV)), 0, st, B.d_geo, B.d_row_off, B.nprob, B.row_stride)
   if (B.tile_edge == 4) {
     if (B.y2wall) PDVM_ROWS(4, true);
     else PDVM_ROWS(4, false);
@@ -1046,8 +1175,8 @@ __global__ void xcd_probe_kernel(uint32_t *out) {
   if (threadIdx.x == 0) out[blockIdx.x] = x;
 }
 
-hipError_t launch_xcd_probe(uint32_t *out, int blocks, hipStream_t st) {
-  hipLaunchKernelGGL(xcd_probe_kernel, dim3((unsigned)blocks), dim3(kWave), 0, st, out);
+hipError_t launch_xcd_probe(uint32_t *out, int blocks, int threads, hipStream_t st) {
+  hipLaunchKernelGGL(xcd_probe_kernel, dim3((unsigned)blocks), dim3((unsigned)threads), 0, st, out);
   return hipGetLastError();
 }
 
