@@ -684,6 +684,7 @@ int finalize_batch(pdvm_solver *s) {
   B.Ko = P0.Ko;
   B.tile_edge = tile_edge;
   B.y2wall = P0.stencil_rule == 0;
+  B.tau_fb = P0.tau_fb;
   B.ndiag_max = ndmax;
   B.d_geo = (const Geo<T> *)geo;
   B.d_item_off = (const int *)item;
@@ -873,6 +874,22 @@ int create_common(const pdvm_config *cfgs, int n, void *dev_workspace, size_t ws
   // machine better with per-diagonal launches (measured)
   s->rows = P0.dim == 2 && (P0.schedule == PDVM_SCHEDULE_ROWS || P0.schedule == PDVM_SCHEDULE_ROWS_AGENT ||
                             (P0.schedule == PDVM_SCHEDULE_AUTO && n == 1));
+  if (s->rows) {
+    // the row pipeline stores a tile through 32-bit byte offsets from its
+    // lowest-addressed voxel
+    const int edge = s->precision == PDVM_FP64 ? s->bd.tile_edge : s->bf.tile_edge;
+    const int64_t elem = s->precision == PDVM_FP64 ? 8 : 4;
+    bool fits = true;
+    for (const Problem &P : s->P) fits = fits && (int64_t)edge * (P.n[0] + 1) * P.Kpad * elem < (int64_t(1) << 32);
+    if (!fits) {
+      if (P0.schedule != PDVM_SCHEDULE_AUTO) {
+        set_thread_error("the row pipeline needs a tile's span of h below 4 GiB (use the diagonal schedule)");
+        pdvm_destroy(s);
+        return PDVM_E_UNSUPPORTED;
+      }
+      s->rows = false;
+    }
+  }
   if (s->rows && P0.schedule != PDVM_SCHEDULE_ROWS_AGENT) {
     const int rc2 = probe_xcd_locality(s);
     if (rc2 != PDVM_OK) {

@@ -98,7 +98,7 @@ constexpr int kTileEdge[2] = {4, 8};
 // block offsets; a single problem is a batch of one.
 template <typename T>
 struct Batch {
-  int nprob = 0, dim = 2, Ko = 0, tile_edge = 8, y2wall = 0, ndiag_max = 0;
+  int nprob = 0, dim = 2, Ko = 0, tile_edge = 8, y2wall = 0, tau_fb = 0, ndiag_max = 0;
   const Geo<T> *d_geo = nullptr;
   const int *d_item_off = nullptr;   // [ndiag_max][nprob + 1] sweep blocks per diagonal
   const int *d_blk_off = nullptr;    // [nprob + 1] moment-kernel blocks

@@ -52,6 +52,18 @@ __device__ __forceinline__ gptr<T> as_global(T *p) {
   return (gptr<T>)p;
 }
 
+// Raw buffer stores (the 2D row pipeline): one resource per tile, the
+// voxel's byte offset as a scalar and the lane's slot as a vector offset.
+// Range checking is off in effect (the record count is the maximum).
+constexpr int kBufferFlags = 0x00020000;  // 32-bit data format, as untyped buffer accesses need
+typedef unsigned int u32x2_t __attribute__((ext_vector_type(2)));
+__device__ __forceinline__ void buffer_store(double v, __amdgpu_buffer_rsrc_t r, uint32_t voff, uint32_t soff) {
+  __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u32x2_t, v), r, (int)voff, (int)soff, 0);
+}
+__device__ __forceinline__ void buffer_store(float v, __amdgpu_buffer_rsrc_t r, uint32_t voff, uint32_t soff) {
+  __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(uint32_t, v), r, (int)voff, (int)soff, 0);
+}
+
 // The few per-problem values the image and indexing helpers need, held in
 // registers by the kernels that use them.
 template <typename T>
@@ -429,12 +441,14 @@ __global__ void __launch_bounds__(kWave)
 // from slot 0, so they compute bit-exact copies of lane 0 and store them to
 // lane 0's slot: every store is then decided by the voxel alone (uniform),
 // without a per-lane mask.
-template <typename T, int TT, bool Y2WALL, bool LOCAL, int NW>
+template <typename T, int TT, bool Y2WALL, bool LOCAL, int NW, bool TAU>
 __global__ void __launch_bounds__(kWave * NW)
     sweep_rows_kernel(const Geo<T> *__restrict__ G, const int *__restrict__ row_off, int nprob, int stride) {
   constexpr int DIM = 2;
   constexpr int NC = TT * TT;
-  constexpr int RW = 5 + 3 * DIM;
+  // record: src (3), then per axis (c1, c2, w), then the feedback source;
+  // 10 values, so a record is five aligned 16-byte LDS reads
+  constexpr int RW = 10;
   constexpr int RING = 2;
   __shared__ T rd_lds[4 * kWave];
   __shared__ T rec_lds[NW][NC * RW];
@@ -524,6 +538,18 @@ __global__ void __launch_bounds__(kWave * NW)
   const gptr<int32_t> wait_on = progress + (band > 0 ? (band - 1) * nchains + c : 0);
   const gptr<int32_t> publish = progress + band * nchains + c;
   const gptr<T> hz = hc;  // plane 0 of the current sweep
+  // store offsets of a whole tile (buffer stores, in bytes): row r and column
+  // i in sweep order, from the tile's lowest-addressed voxel
+  // (the column offset is folded into the lane's vector offset)
+  const int ylo = s[1] > 0 ? ys : ys - (TT - 1);
+  uint32_t rowb[TT], vcol[TT];
+#pragma unroll
+  for (int k = 0; k < TT; ++k) {
+    rowb[k] = (uint32_t)((s[1] > 0 ? k : TT - 1 - k) * (int64_t)n0 * Kp * (int64_t)sizeof(T));
+    vcol[k] = kst + (uint32_t)((s[0] > 0 ? k : TT - 1 - k) * Kp * (int64_t)sizeof(T));
+  }
+  // this lane's reciprocal denominators, offset by the voxel code's byte offset
+  const T *const rd_lane = rd_lds + lane;
   const int64_t wait_ticks = G_.wait_ticks;
   // Bounded wait: polls `ready` until it holds; after wait_ticks of the
   // wall clock (checked every 64 polls) it flags ctl->fault and gives up.
@@ -622,7 +648,7 @@ __global__ void __launch_bounds__(kWave * NW)
         rp[0] = cur.sv0;
         rp[1] = cur.sv1;
         rp[2] = cur.sv2;
-        rp[4] = cur.svt;
+        rp[9] = cur.svt;
         code = 0;
 #pragma unroll
         for (int k = 0; k < DIM; ++k) {
@@ -635,13 +661,14 @@ __global__ void __launch_bounds__(kWave * NW)
             c2 = T(0);
             wl = T(-0.5) * wall_at_y1(dm, wall, k, s[k], pin[k], x, y, 0);
           }
-          rp[5 + 3 * k] = c1;
-          rp[6 + 3 * k] = c2;
-          rp[7 + 3 * k] = wl;
+          rp[3 + 3 * k] = c1;
+          rp[4 + 3 * k] = c2;
+          rp[5 + 3 * k] = wl;
           code |= (first ? 1u : 0u) << k;
         }
       }
-      rcode[lane] = code;
+      // the byte offset of the voxel's reciprocal denominators in rd_lds
+      rcode[lane] = (code & R_SKIP) | ((code & 3u) * (uint32_t)(kWave * sizeof(T)));
     }
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
     __builtin_amdgcn_wave_barrier();
@@ -683,6 +710,10 @@ __global__ void __launch_bounds__(kWave * NW)
 #pragma unroll
     for (int k = 0; k < TT; ++k) hrow[k] = (gptr<char>)(hz + (int64_t)((ys + k * s[1]) * n0 + xs) * Kp);
     const int64_t colb = (int64_t)s[0] * Kp * (int64_t)sizeof(T);  // bytes from one column to the next
+    // a whole tile is stored through one buffer resource based at its
+    // lowest-addressed voxel, with wavefront-constant row and column offsets
+    const __amdgpu_buffer_rsrc_t tile_rsrc = __builtin_amdgcn_make_buffer_rsrc(
+        (void *)(T *)(hz + (int64_t)(ylo * n0 + (s[0] > 0 ? xs : xs - (TT - 1))) * Kp), (short)0, -1, kBufferFlags);
 
     // --- the tile's anti-diagonals (as in sweep_kernel) ---------------------
     // FULL: a whole TT x TT tile, so the columns and rows handed on are
@@ -713,14 +744,14 @@ __global__ void __launch_bounds__(kWave * NW)
           const T *rp = rec + (i + TT * r) * RW;
           T num = fma(rp[1], vv[0], rp[0]);
           num = fma(rp[2], vv[1], num);
-          num = fma(rp[4], vsqm, num);
+          if (TAU) num = fma(rp[9], vsqm, num);
           const T x1a = i >= 1 ? D1[r] : L1[r];
           const T x1b = i >= 2 ? D2[r] : (i == 1 ? L1[r] : L2[r]);
           const T x2a = r >= 1 ? D1[r >= 1 ? r - 1 : 0] : B1[i];
           const T x2b = r >= 2 ? D2[r >= 2 ? r - 2 : 0] : (r == 1 ? B1[i] : B2[i]);
-          num = fma(aa[0], fma(rp[5], x1a, fma(rp[6], x1b, rp[7])), num);
-          num = fma(aa[1], fma(rp[8], x2a, fma(rp[9], x2b, rp[10])), num);
-          Nw[r] = num * rd_lds[(code & 7u) * kWave + lane];
+          num = fma(aa[0], fma(rp[3], x1a, fma(rp[4], x1b, rp[5])), num);
+          num = fma(aa[1], fma(rp[6], x2a, fma(rp[7], x2b, rp[8])), num);
+          Nw[r] = num * *(const T *)((const char *)rd_lane + (code & ~R_SKIP));
           Nc[r] = code;
           if (FULL) {
             if (i == TT - 1) out.LN1[r] = Nw[r];
@@ -738,7 +769,9 @@ __global__ void __launch_bounds__(kWave * NW)
         for (int r = 0; r < TT; ++r) {
           const int i = d - r;
           if (i < 0 || i >= TT) continue;
-          if (!(Nc[r] & R_SKIP)) *(gptr<T>)(hrow[r] + i * colb + kst) = Nw[r];
+          if (Nc[r] & R_SKIP) continue;
+          if (FULL) buffer_store(Nw[r], tile_rsrc, vcol[i], rowb[r]);
+          else *(gptr<T>)(hrow[r] + i * colb + kst) = Nw[r];
         }
 #pragma unroll
         for (int r = 0; r < TT; ++r) {
@@ -1147,16 +1180,20 @@ hipError_t launch_sweep(const Batch<T> &B, int diag, hipStream_t st) {
 
 template <typename T, bool LOCAL>
 void launch_rows_local(const Batch<T> &B, dim3 grid, hipStream_t st) {
-#define PDVM_ROWS(TTV, Y2)                                                                        \
-  hipLaunchKernelGGL((sweep_rows_kernel<T, TTV, Y2, LOCAL, band_waves(TTV)>), grid,              \
+#define PDVM_ROWS(TTV, Y2, TAU)                                                                   \
+  hipLaunchKernelGGL((sweep_rows_kernel<T, TTV, Y2, LOCAL, band_waves(TTV), TAU>), grid,         \
                      dim3(kWave * band_waves(TTV)), 0, st, B.d_geo, B.d_row_off, B.nprob, B.row_stride)
+#define PDVM_ROWS_TAU(TTV, Y2)         \
+  if (B.tau_fb) PDVM_ROWS(TTV, Y2, true); \
+  else PDVM_ROWS(TTV, Y2, false)
   if (B.tile_edge == 4) {
-    if (B.y2wall) PDVM_ROWS(4, true);
-    else PDVM_ROWS(4, false);
+    if (B.y2wall) PDVM_ROWS_TAU(4, true);
+    else PDVM_ROWS_TAU(4, false);
   } else {
-    if (B.y2wall) PDVM_ROWS(8, true);
-    else PDVM_ROWS(8, false);
+    if (B.y2wall) PDVM_ROWS_TAU(8, true);
+    else PDVM_ROWS_TAU(8, false);
   }
+#undef PDVM_ROWS_TAU
 #undef PDVM_ROWS
 }
 
