@@ -172,7 +172,7 @@ size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
 
 template <typename T>
 struct Layout {
-  size_t ctl, flags, absv, av, vsqm, rden, wq, h[2], src[2], srct[2], wall[2], rho[2], u[2], part, tiles, offs, scratch,
+  size_t ctl, flags, absv, av, vsqm, rden, wq, h[2], src[2], srct[2], wall[2], rho[2], u[2], part, tiles, offs, fidx, scratch,
       progress, total;
 };
 
@@ -191,6 +191,7 @@ struct Problem {
   std::vector<uint32_t> flags;
   std::vector<double> absv, wq, vsqm, rden;   // host FP64 tables, [rows][Ko_pad]
   std::vector<int32_t> diag_tiles, diag_off;
+  std::vector<int32_t> fluid_idx;  // fluid voxels in index order
   uint64_t fingerprint = 0;  // hash of everything that defines the problem
 };
 
@@ -336,6 +337,10 @@ int validate_and_build(const pdvm_config *cfg, Problem &P, std::string &err) {
         P.flags[c] = f;
       }
   P.fluid = fluid;
+  P.fluid_idx.clear();
+  P.fluid_idx.reserve((size_t)fluid);
+  for (int64_t c = 0; c < P.N; ++c)
+    if (!(P.flags[c] & F_SOLID)) P.fluid_idx.push_back((int32_t)c);
   if (fluid == 0) { err = "the geometry has no fluid voxel"; return PDVM_E_INVAL; }
   {
     PeriodicUF uf(P.N);
@@ -393,7 +398,8 @@ int validate_and_build(const pdvm_config *cfg, Problem &P, std::string &err) {
     P.diag_tiles.insert(P.diag_tiles.end(), v.begin(), v.end());
     P.diag_off.push_back((int32_t)(P.diag_tiles.size() / 4));
   }
-  P.mom_blocks = (int)std::min<int64_t>((P.N + 3) / 4, 4096);
+  // moment kernel: about 16 fluid voxels per wavefront, at most one round of 4096 wavefronts
+  P.mom_blocks = (int)std::max<int64_t>(1, std::min<int64_t>((P.fluid + 63) / 64, 1024));
   uint64_t fp = 1469598103934665603ull;
   const double scal[5] = {P.kn, P.jump, (double)P.lateral_periodic, (double)P.tau_fb, (double)P.stencil_rule};
   fp = fnv1a(fp, scal, sizeof(scal));
@@ -431,6 +437,7 @@ Layout<T> make_layout(const Problem &P) {
   L.part = take((size_t)P.mom_blocks * 4 * 8);
   L.tiles = take(P.diag_tiles.size() * 4);
   L.offs = take(P.diag_off.size() * 4);
+  L.fidx = take((size_t)P.fluid * 4);
   L.scratch = take(8 * N * 8);  // tau, q (3), rho, u (3) staging
   L.progress = take((size_t)(P.ngroups << P.dim) * P.ntile[1] * 4);  // row-pipeline counters
   L.total = o;
@@ -599,6 +606,8 @@ int setup_problem(pdvm_solver *s, int i) {
   g.mom_blocks = P.mom_blocks;
   g.diag_tiles = (const int32_t *)(b + L.tiles);
   g.diag_off = (const int32_t *)(b + L.offs);
+  g.fluid_idx = (const int32_t *)(b + L.fidx);
+  g.nfluid = P.fluid;
   g.ndiag = P.ndiag;
   g.progress = (int32_t *)(b + L.progress);
   {
@@ -625,6 +634,7 @@ int setup_problem(pdvm_solver *s, int i) {
   HIPCHK(s, hipMemcpyAsync((void *)g.rden, rden.data(), rden.size() * sizeof(T), hipMemcpyHostToDevice, st));
   HIPCHK(s, hipMemcpyAsync((void *)g.wq, P.wq.data(), P.wq.size() * 8, hipMemcpyHostToDevice, st));
   HIPCHK(s, hipMemcpyAsync((void *)g.diag_tiles, P.diag_tiles.data(), P.diag_tiles.size() * 4, hipMemcpyHostToDevice, st));
+  HIPCHK(s, hipMemcpyAsync((void *)g.fluid_idx, P.fluid_idx.data(), P.fluid_idx.size() * 4, hipMemcpyHostToDevice, st));
   HIPCHK(s, hipMemcpyAsync((void *)g.diag_off, P.diag_off.data(), P.diag_off.size() * 4, hipMemcpyHostToDevice, st));
   Ctl c{};
   c.kn_coef = 2.0 / std::sqrt(M_PI) * (std::isinf(P.kn) ? 0.0 : P.kn);

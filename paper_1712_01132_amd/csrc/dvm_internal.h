@@ -70,6 +70,8 @@ struct Geo {
   Ctl *ctl;
   double *part;            // [mom_blocks][4] per-block residual / flux partials
   int32_t mom_blocks;
+  const int32_t *fluid_idx;  // [nfluid] the fluid voxels in index order (moment kernel's work list)
+  int64_t nfluid;
   int32_t tile[3], ntile[3];
   const int32_t *diag_tiles;  // [count][4] oriented tile coordinates (x1, x2, x3, pad)
   const int32_t *diag_off;    // [ndiag + 1]

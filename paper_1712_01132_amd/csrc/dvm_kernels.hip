@@ -830,11 +830,39 @@ __device__ __forceinline__ double wave_sum(double v) {
   return v;
 }
 
-// Steps (ii)-(iii). One wavefront per fluid voxel at a time: lane l owns the
-// octant slots q = l + 64 m (m < NS) of every octant, keeps their quadrature
-// weights in registers, and accumulates rho and the half-fluxes; the loads of
-// a voxel's whole distribution are independent, so they are all in flight
-// together. Slots past the octant size load nothing and weigh 0.
+// Sum over the 64 lanes of eight values at once: at each of the first three
+// exchange steps a lane keeps one half of its values and sends the other
+// half, so ten exchanges (not 8 x 6) leave in lane l the total of value
+// ((l >> 5) & 1) * 4 + ((l >> 4) & 1) * 2 + ((l >> 3) & 1).
+__device__ __forceinline__ double wave_sum8(const double (&v)[8], int lane) {
+  double a[4], b[2];
+  const bool u32 = lane & 32, u16 = lane & 16, u8 = lane & 8;
+#pragma unroll
+  for (int k = 0; k < 4; ++k) a[k] = (u32 ? v[4 + k] : v[k]) + __shfl_xor(u32 ? v[k] : v[4 + k], 32, kWave);
+#pragma unroll
+  for (int k = 0; k < 2; ++k) b[k] = (u16 ? a[2 + k] : a[k]) + __shfl_xor(u16 ? a[k] : a[2 + k], 16, kWave);
+  double c = (u8 ? b[1] : b[0]) + __shfl_xor(u8 ? b[0] : b[1], 8, kWave);
+  c += __shfl_xor(c, 4, kWave);
+  c += __shfl_xor(c, 2, kWave);
+  c += __shfl_xor(c, 1, kWave);
+  return c;
+}
+
+__device__ __forceinline__ double readlane_d(double v, int l) {
+  const uint64_t b = __builtin_bit_cast(uint64_t, v);
+  const uint32_t lo = __builtin_amdgcn_readlane((uint32_t)b, l), hi = __builtin_amdgcn_readlane((uint32_t)(b >> 32), l);
+  return __builtin_bit_cast(double, ((uint64_t)hi << 32) | lo);
+}
+
+// Steps (ii)-(iii). A wavefront takes fluid voxels i = w, w + nw, ... of the
+// fluid list (nw wavefronts in all), one at a time: lane l owns the octant
+// slots q = l + 64 m (m < NS) of every octant, keeps their quadrature weights
+// in registers and accumulates rho, the half-fluxes and the energy; the eight
+// sums are then reduced over the lanes together. The voxel indices of the
+// next 64 voxels come in one load (a lane each), and the next voxel's
+// distribution is loaded before the current one is reduced, so a wavefront
+// always has a voxel's loads in flight. Slots past the octant size read a
+// valid neighbour (same cache lines) and weigh 0.
 template <typename T, int DIM, int NS>
 __global__ void __launch_bounds__(kMomBlock)
     moments_kernel(const Geo<T> *__restrict__ G, const int *__restrict__ blk_off, int nprob) {
@@ -850,18 +878,15 @@ __global__ void __launch_bounds__(kMomBlock)
   const gptr<T> src_n = as_global(np ? g.src[1] : g.src[0]);
   const gptr<T> srct_n = as_global(np ? g.srct[1] : g.srct[0]);
   const gptr<T> wall_n = as_global(np ? g.wall[1] : g.wall[0]);
-  const gptr<const uint32_t> flags = as_global(g.flags);
+  const gptr<const int32_t> fidx = as_global(g.fluid_idx);
   const gptr<const double> wq = as_global(g.wq);
   const gptr<double> part = as_global(g.part);
-  const int64_t N = g.N, Kpad = g.Kpad;
+  const int64_t N = g.N, Kpad = g.Kpad, nf = g.nfluid;
   const int Ko = g.Ko, Ko_pad = g.Ko_pad, tau_fb = g.tau_fb, mom_blocks = g.mom_blocks;
   const double nu = g.nu, Dj[3] = {g.D[0], g.D[1], g.D[2]};
   const int lane = threadIdx.x & (kWave - 1), wid = threadIdx.x / kWave;
   constexpr int WPB = kMomBlock / kWave;
   const int64_t nw = (int64_t)mom_blocks * WPB;
-  // slots past the octant size read a valid neighbour (same cache lines) and
-  // weigh 0, so every load is unconditional and all of a voxel's loads are
-  // in flight together
   double wr[NS][2 + DIM];
   int qc[NS];
 #pragma unroll
@@ -872,54 +897,75 @@ __global__ void __launch_bounds__(kMomBlock)
 #pragma unroll
     for (int r = 0; r < 2 + DIM; ++r) wr[m][r] = ok ? wq[r * Ko_pad + q] : 0.0;
   }
-  double mdu = 0, mu = 0, su = 0;
-  for (int64_t c = (int64_t)blk * WPB + wid; c < N; c += nw) {
-    if (flags[c] & F_SOLID) continue;
+  auto load = [&](int64_t c, T (&hv)[1 << DIM][NS]) __attribute__((always_inline)) {
     const gptr<const T> hc = h + c * Kpad;
-    T hv[1 << DIM][NS];
 #pragma unroll
     for (int o = 0; o < (1 << DIM); ++o)
 #pragma unroll
       for (int m = 0; m < NS; ++m) hv[o][m] = hc[o * Ko_pad + qc[m]];
-    double r = 0, e = 0;
-    double ph[3][2] = {{0, 0}, {0, 0}, {0, 0}};
+  };
+  // the next voxel's distribution is held in registers only when it is small
+  constexpr bool kAhead = (1 << DIM) * NS * sizeof(T) <= 256;
+  double mdu = 0, mu = 0, su = 0;
+  const int64_t first = (int64_t)blk * WPB + wid;
+  for (int64_t base = first; base < nf; base += nw * kWave) {
+    // this wavefront's next (up to) 64 voxels: lane t holds the index of voxel base + t nw
+    const int64_t il = base + (int64_t)lane * nw;
+    const int32_t cl = fidx[il < nf ? il : base];
+    const int cnt = (int)min<int64_t>(kWave, (nf - base + nw - 1) / nw);
+    T hv[1 << DIM][NS];
+    int64_t c = __builtin_amdgcn_readlane(cl, 0);
+    load(c, hv);
+    for (int t = 0; t < cnt; ++t) {
+      const int64_t cn = __builtin_amdgcn_readlane(cl, min(t + 1, cnt - 1));
+      T hn[1 << DIM][NS];
+      if (kAhead) load(cn, hn);  // in flight while this voxel is reduced
+      double v[8] = {0, 0, 0, 0, 0, 0, 0, 0};  // rho, half-fluxes (j, +/-), energy
 #pragma unroll
-    for (int o = 0; o < (1 << DIM); ++o) {
-      double pj[3] = {0, 0, 0};
+      for (int o = 0; o < (1 << DIM); ++o) {
 #pragma unroll
-      for (int m = 0; m < NS; ++m) {
-        const double x = (double)hv[o][m];
-        r = fma(wr[m][0], x, r);
+        for (int m = 0; m < NS; ++m) {
+          const double x = (double)hv[o][m];
+          v[0] = fma(wr[m][0], x, v[0]);
 #pragma unroll
-        for (int j = 0; j < DIM; ++j) pj[j] = fma(wr[m][1 + j], x, pj[j]);
-        if (tau_fb) e = fma(wr[m][1 + DIM], x, e);
+          for (int j = 0; j < DIM; ++j) v[1 + 2 * j + ((o >> j) & 1)] = fma(wr[m][1 + j], x, v[1 + 2 * j + ((o >> j) & 1)]);
+          v[7] = fma(wr[m][1 + DIM], x, v[7]);
+        }
       }
-#pragma unroll
-      for (int j = 0; j < DIM; ++j) ph[j][(o >> j) & 1] += pj[j];
-    }
-    r = wave_sum(r);
-#pragma unroll
-    for (int j = 0; j < DIM; ++j) {
-      ph[j][0] = wave_sum(ph[j][0]);
-      ph[j][1] = wave_sum(ph[j][1]);
-    }
-    if (tau_fb) e = wave_sum(e);
-    if (lane == 0) {
-      rho_n[c] = r;
-      const gptr<T> sp = src_n + c * kSrcStride;
-      sp[0] = T(nu * r);
+      const double tot = wave_sum8(v, lane);
+      const double r = readlane_d(tot, 0);
+      double ph[3][2];
 #pragma unroll
       for (int j = 0; j < DIM; ++j) {
-        const double uj = ph[j][0] - ph[j][1];
-        mdu = fmax(mdu, fabs(uj - uold[j * N + c]));
-        mu = fmax(mu, fabs(uj));
-        u_n[j * N + c] = uj;
-        sp[1 + j] = T(2.0 * nu * uj);
-        wall_n[c * 6 + 2 * j] = T(ph[j][0] / Dj[j]);
-        wall_n[c * 6 + 2 * j + 1] = T(ph[j][1] / Dj[j]);
+        ph[j][0] = readlane_d(tot, 8 * (1 + 2 * j));
+        ph[j][1] = readlane_d(tot, 8 * (2 + 2 * j));
       }
-      if (tau_fb) srct_n[c] = T(nu * ((2.0 / 3.0) * e - r));
-      su += ph[0][0] - ph[0][1];
+      if (lane == 0) {
+        rho_n[c] = r;
+        const gptr<T> sp = src_n + c * kSrcStride;
+        sp[0] = T(nu * r);
+#pragma unroll
+        for (int j = 0; j < DIM; ++j) {
+          const double uj = ph[j][0] - ph[j][1];
+          mdu = fmax(mdu, fabs(uj - uold[j * N + c]));
+          mu = fmax(mu, fabs(uj));
+          u_n[j * N + c] = uj;
+          sp[1 + j] = T(2.0 * nu * uj);
+          wall_n[c * 6 + 2 * j] = T(ph[j][0] / Dj[j]);
+          wall_n[c * 6 + 2 * j + 1] = T(ph[j][1] / Dj[j]);
+        }
+        if (tau_fb) srct_n[c] = T(nu * ((2.0 / 3.0) * readlane_d(tot, 56) - r));
+        su += ph[0][0] - ph[0][1];
+      }
+      if (kAhead) {
+#pragma unroll
+        for (int o = 0; o < (1 << DIM); ++o)
+#pragma unroll
+          for (int m = 0; m < NS; ++m) hv[o][m] = hn[o][m];
+      } else {
+        load(cn, hv);
+      }
+      c = cn;
     }
   }
   __shared__ double sh[WPB][3];

@@ -111,14 +111,18 @@ def test_ragged_tiles_3d_fp32_match_oracle(tile, rule):
     ((40, 33), [16, 32], (8, 5), "fp32", "periodic", 0),
     ((70, 24), [8, 8], (4, 4), "fp64", "specular", 1),
     ((45, 30), [6, 6], (4, 4), "fp32", "periodic", 1),
+    ((37, 29), [24, 24], (4, 4), "fp64", "specular", 1),
+    ((50, 44), [16, 32], (4, 4), "fp32", "periodic", 0),
 ])
 def test_row_pipeline_equals_tile_diagonals_bitwise(shape, nv, tile, precision, lateral, rule):
     """The one-launch row pipeline and the per-diagonal launches run the same
     arithmetic on the same values: every iterate is bitwise identical. Wide
     velocity grids give several chains per octant; narrow and ragged tiles
     exercise the register-carried left halo; more tile rows than one band
-    holds (8 rows of 4x4 tiles, 4 of 8x8), partial last bands and one- or
-    two-voxel top rows exercise the LDS ring and the hand-over between bands."""
+    holds, partial last bands and one- or two-voxel top rows exercise the LDS
+    ring and the hand-over between bands; 4x4 tiles with several 64-velocity
+    groups per octant, one of them partly empty, give several chains per
+    band."""
     m = random_mask(shape, 0.3, sum(shape) + 7)
     out = []
     for sched in ("rows", "diagonals"):
