@@ -125,10 +125,11 @@ def _ttr_fp64(mask, nv, kn, tile, tol=1e-6):
     return {"seconds": dt, "iterations": r["total_iters"], "k": r["k"], "converged": r["converged"]}
 
 
-def _ttr_fp32_then_fp64(mask, nv, kn, tile, tile32, net=None, trial=50, tol=1e-6):
+def _ttr_fp32_then_fp64(mask, nv, kn, tile, tile32, net=None, trial=50, tol=1e-6, ramp=False):
     """FP32 iterations until r <= SWITCH_TOL, then the FP64 iteration from the
-    exact FP32 state. With a network: its prediction and rest are each run
-    `trial` iterations in FP32 and the start with the smaller residual goes on."""
+    exact FP32 state. From rest, from the pressure ramp (ramp=True), or with a
+    network: its prediction and the ramp are each run `trial` iterations in
+    FP32 and the start with the smaller residual goes on."""
     from paper_1712_01132_amd import poredvm, warmstart
     b = poredvm.Solver(mask, nv, kn, precision="fp64", tile=tile)
     t0 = time.perf_counter()
@@ -138,6 +139,8 @@ def _ttr_fp32_then_fp64(mask, nv, kn, tile, tile32, net=None, trial=50, tol=1e-6
         a, used, _, _ = warmstart.judged_start(mask, nv, kn, start, trial=trial, precision="fp32", tile=tile32)
     else:
         a = poredvm.Solver(mask, nv, kn, precision="fp32", tile=tile32)
+        if ramp:
+            a.set_initial(*warmstart.ramp_start(mask))
     r32 = a.iterate(FP32_MAX_ITERS, SWITCH_TOL)
     b.set_state(a.get_state())
     r64 = b.iterate(TTR_MAX_ITERS, tol)
@@ -185,6 +188,9 @@ def time_to_residual(mask, nv, kn, tile, tile32):
     log("time to r<=1e-6, FP32 from rest, finished in FP64")
     out["fp32_then_fp64"] = _ttr_fp32_then_fp64(mask, nv, kn, tile, tile32)
     log("  %s" % json.dumps(out["fp32_then_fp64"]))
+    log("time to r<=1e-6, FP32 from the pressure ramp rho = 1/2 - x1, finished in FP64")
+    out["fp32_ramp_then_fp64"] = _ttr_fp32_then_fp64(mask, nv, kn, tile, tile32, ramp=True)
+    log("  %s" % json.dumps(out["fp32_ramp_then_fp64"]))
     try:
         from paper_1712_01132_amd import warmstart
         params, _ = warmstart.load_weights()
@@ -194,14 +200,14 @@ def time_to_residual(mask, nv, kn, tile, tile32):
     if params is not None:
         net = warmstart.Net(mask.shape[1], mask.shape[0], batch_max=1, dataset_max=0)
         net.set_params(params)
-        log("time to r<=1e-6, FP32 from the network's prediction (50-iteration trial against rest), "
+        log("time to r<=1e-6, FP32 from the network's prediction (50-iteration trial against the ramp), "
             "finished in FP64")
         res = _ttr_fp32_then_fp64(mask, nv, kn, tile, tile32, net=net, trial=50)
         net.close()
         out["fp32_warm_then_fp64"] = res
         log("  %s" % json.dumps(res))
     k64 = out["fp64"]["k"]
-    for key in ("fp32_then_fp64", "fp32_warm_then_fp64"):
+    for key in ("fp32_then_fp64", "fp32_ramp_then_fp64", "fp32_warm_then_fp64"):
         if "k" in out[key]:
             out[key]["k_rel_diff_vs_fp64"] = abs(out[key]["k"] - k64) / abs(k64)
             out[key]["speedup_vs_fp64"] = out["fp64"]["seconds"] / out[key]["seconds"]

@@ -188,14 +188,19 @@ def main():
         starts = [net.predict(m, kn) for m, kn in evp]
         sc, _ = solve_chunk(evp, nv, args.eval_tol, args.eval_max_iters)
         sw, _ = solve_chunk(evp, nv, args.eval_tol, args.eval_max_iters, starts=starts)
+        sr, _ = solve_chunk(evp, nv, args.eval_tol, args.eval_max_iters,
+                            starts=[warmstart.ramp_start(m) for m, _ in evp])
         ic = np.array([s["total_iters"] for s in sc])
         iw = np.array([s["total_iters"] for s in sw])
+        ir = np.array([s["total_iters"] for s in sr])
         kc = np.array([s["k"] for s in sc])
         kw = np.array([s["k"] for s in sw])
         meta["eval"] = {"problems": ne, "tol": args.eval_tol, "cold_iters": ic.tolist(), "warm_iters": iw.tolist(),
                         "cold_converged": int(sum(s["converged"] for s in sc)),
                         "warm_converged": int(sum(s["converged"] for s in sw)),
-                        "median_ratio": float(np.median(iw / ic)), "k_rel_diff_max": float(np.max(np.abs(kw - kc) / np.abs(kc)))}
+                        "median_ratio": float(np.median(iw / ic)), "k_rel_diff_max": float(np.max(np.abs(kw - kc) / np.abs(kc))),
+                        "ramp_iters": ir.tolist(), "median_ratio_ramp": float(np.median(ir / ic)),
+                        "median_ratio_warm_vs_ramp": float(np.median(iw / ir))}
         log("held-out warm/cold iterations to r <= %g: median ratio %.3f, cold median %d, warm median %d, "
             "warm better in %d/%d" % (args.eval_tol, meta["eval"]["median_ratio"], int(np.median(ic)),
                                       int(np.median(iw)), int(np.sum(iw < ic)), ne))

@@ -225,13 +225,28 @@ def load_weights(path=WEIGHTS_PATH):
         return z["params"].astype(np.float32), {k: z[k] for k in z.files if k != "params"}
 
 
-def judged_start(mask, nv, kn, start, trial=50, precision="fp32", jump=1.0, tile=None, grid=None):
+def ramp_start(mask, jump=1.0):
+    """The pressure ramp that the jump condition imposes on average (Eq.
+    periodic_BC): rho = jump (1/2 - x1) at the fluid nodes (x1 at the node,
+    L = 1), u = 0. It needs no training and already removes the slowest part
+    of the start-up from rest, so it is the baseline a learned start has to
+    beat."""
+    mask = np.asarray(mask)
+    n1 = mask.shape[-1]
+    x1 = (np.arange(n1) + 0.5) / n1
+    rho = np.broadcast_to(jump * (0.5 - x1), mask.shape).copy()
+    rho[mask != 0] = 0.0
+    return rho, np.zeros((mask.ndim,) + mask.shape)
+
+
+def judged_start(mask, nv, kn, start, trial=50, precision="fp32", jump=1.0, tile=None, grid=None, fallback="ramp"):
     """The iteration judges a guessed start: `trial` iterations from the start
-    fields (rho, u) and `trial` iterations from rest, each in its own solver.
+    fields (rho, u) and `trial` iterations from the fallback (the pressure
+    ramp of `ramp_start`, or rest with fallback=None), each in its own solver.
     The one whose velocity field still changes less per iteration
     (r * max|u|, the absolute change at the last trial iteration) goes on and
     is returned; the other is closed. Returns (solver, used_start, change_start,
-    change_rest)."""
+    change_fallback)."""
     kw = dict(precision=precision, jump=jump, tile=tile)
     if grid is not None:
         kw["grid"] = grid
@@ -245,7 +260,7 @@ def judged_start(mask, nv, kn, start, trial=50, precision="fp32", jump=1.0, tile
         return s, r * float(np.abs(u).max())
 
     a, da = run(start)
-    b, db = run(None)
+    b, db = run(ramp_start(mask, jump) if fallback == "ramp" else None)
     if da < db:
         b.close()
         return a, True, da, db

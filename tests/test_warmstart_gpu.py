@@ -163,17 +163,37 @@ def test_trained_network_saves_iterations_on_held_out_geometries():
     assert iw.sum() <= 0.95 * ic.sum() and np.sum(iw < ic) >= 6
 
 
-def test_iteration_judges_the_guess_and_falls_back_to_rest():
+def test_iteration_judges_the_guess_and_falls_back():
     from paper_1712_01132_amd import geometry, warmstart
     m, kn = geometry.workload_warmstart(20001)
     net = _trained_net()
     rho, u = net.predict(m, kn)
     net.close()
-    s, used, rw, rc = warmstart.judged_start(m, [24, 24], kn, (rho, u), trial=50)
+    s, used, rw, rc = warmstart.judged_start(m, [24, 24], kn, (rho, u), trial=50, fallback=None)
     s.close()
-    assert used and rw < rc
-    # a wrong guess (reversed and amplified flow) loses the trial: the solve goes on from rest
+    assert used and rw < rc  # the prediction beats rest
+    # a wrong guess (reversed and amplified flow) loses the trial against the
+    # pressure ramp: the solve goes on from the ramp
     s, used, rw, rc = warmstart.judged_start(m, [24, 24], kn, (-3.0 * rho, -3.0 * u), trial=50)
     st = s.iterate(10)
     s.close()
     assert not used and rw >= rc and st["total_iters"] == 60
+
+
+def test_pressure_ramp_start_saves_iterations():
+    """The ramp that the jump condition imposes (no training) starts closer to
+    the solution than rest on held-out problems."""
+    from paper_1712_01132_amd import geometry, warmstart
+    probs = [geometry.workload_warmstart(20000 + i) for i in range(4)]
+    out = []
+    for ramp in (False, True):
+        b = poredvm.Batch(probs, [24, 24], precision="fp32", tile=[8, 8])
+        if ramp:
+            for i, (m, _) in enumerate(probs):
+                b.set_initial(i, *warmstart.ramp_start(m))
+        st = b.iterate(8000, 1e-5)
+        b.close()
+        assert all(x["converged"] for x in st)
+        out.append(np.array([x["total_iters"] for x in st]))
+    print("rest", out[0].tolist(), "ramp", out[1].tolist())
+    assert out[1].sum() <= 0.95 * out[0].sum()
