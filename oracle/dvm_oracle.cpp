@@ -34,7 +34,12 @@
 //   wall density of the solid met by a stencil along axis j with upwind sign s
 //   is taken from the fluid node next to it in the +s direction, with the
 //   quadrature sum D_j = sum_{v_j>0} W v_j as denominator;
-//   isothermal source (the tau term is dropped unless tau_feedback, 3D only);
+//   isothermal source (the tau term is dropped unless tau_feedback);
+//   in 2D with tau_feedback the v3-integrated equation needs a second reduced
+//   function psi = int (v3^2 - 1/2) h exp(-v3^2)/sqrt(pi) dv3, with source
+//   tau/2, wall value 0 (a diffuse wall emits a v3-Maxwellian) and no jump
+//   at the x1 wrap (the jump is v3-independent); phi (the reduced h) then
+//   has the source tau (v1^2 + v2^2 - 1), and tau takes int W psi;
 //   residual r = max|u^l - u^(l-1)| / max|u^l| over fluid cells and components.
 //
 // Velocity order inside this file: k = a + n1 (b + n2 c) over the tensor grid
@@ -78,6 +83,8 @@ struct Oracle {
   // boundary store: per axis, 4 layers {0, 1, N-2, N-1} of the previous
   // iteration's h, all velocities: hbc[a][slot][facecell * K + k]
   std::vector<double> hbc[3][4];
+  std::vector<double> psibc[3][4];  // the same layers of psi (2D with tau_fb)
+  bool has_psi() const { return dim == 2 && tau_fb; }
 
   long iters_done = 0;
   double last_r = 0.0, last_err = -1.0, last_k = 0.0, last_gp = 0.0;
@@ -118,7 +125,7 @@ Image image_of(const Oracle &o, int a, int c) {
 // Value of upstream node m (1 or 2) of fluid node x along axis j for velocity k.
 // Returns via *is_solid whether the image is solid. hk holds the current sweep.
 double upstream_value(const Oracle &o, const int x[3], int j, int m, int k,
-                      const double *hk, int *is_solid) {
+                      const double *hk, int *is_solid, bool psi = false) {
   const int s = o.v[j][k] > 0 ? 1 : -1;
   int y[3] = {x[0], x[1], x[2]};
   y[j] -= m * s;
@@ -129,6 +136,7 @@ double upstream_value(const Oracle &o, const int x[3], int j, int m, int k,
   const long cy = o.idx(yr[0], yr[1], yr[2]);
   if (o.solid[cy]) {
     *is_solid = 1;
+    if (psi) return 0.0;  // the wall emits a Maxwellian in v3: psi = 0
     // wall value: wall density of the solid seen along s e_j, from the fluid
     // node x_f = y + s e_j next to it. [Eq. wall_density, alpha = 1]
     int f[3] = {y[0], y[1], y[2]};
@@ -148,24 +156,26 @@ double upstream_value(const Oracle &o, const int x[3], int j, int m, int k,
   // lagged boundary data from the previous iteration [Sec. 3.1 step (ii)]
   const int kk = im.mirrored ? o.mirror[j][k] : k;
   const int sl = Oracle::slot_of(im.r, o.n[j]);
+  if (psi) return o.psibc[j][sl][o.face_index(j, yr) * o.K + kk];  // no jump for psi
   return o.hbc[j][sl][o.face_index(j, yr) * o.K + kk] + im.jump * o.J;
 }
 
 // Source term S_k(x) = rho + 2 u.v_k (+ tau(|v_k|^2 - 3/2)). [Eq. linearised_Boltzmann_equation]
+// In 2D |v|^2 - 3/2 integrates over v3 to v1^2 + v2^2 - 1.
 double source(const Oracle &o, long c, int k) {
   double S = o.rho[c];
   for (int j = 0; j < o.dim; ++j) S += 2.0 * o.u[j][c] * o.v[j][k];
   if (o.tau_fb) {
     double v2 = 0;
     for (int j = 0; j < o.dim; ++j) v2 += o.v[j][k] * o.v[j][k];
-    S += o.tau[c] * (v2 - 1.5);
+    S += o.tau[c] * (o.dim == 2 ? v2 - 1.0 : v2 - 1.5);
   }
   return S;
 }
 
 // Step (i) for one velocity: forward substitution over all fluid nodes in the
 // raster order of the velocity's sign octant. [Sec. 3.1 step (i), Eq. Discretised_...]
-void sweep_velocity(const Oracle &o, int k, double *hk) {
+void sweep_velocity(const Oracle &o, int k, double *hk, bool psi = false) {
   const double inv_dx = (double)o.n[0];
   int sgn[3] = {1, 1, 1};
   for (int j = 0; j < o.dim; ++j) sgn[j] = o.v[j][k] > 0 ? 1 : -1;
@@ -178,14 +188,14 @@ void sweep_velocity(const Oracle &o, int k, double *hk) {
         const long c = o.idx(i, jj, l);
         if (o.solid[c]) continue;
         const int x[3] = {i, jj, l};
-        double num = o.nu * source(o, c, k);
+        double num = o.nu * (psi ? 0.5 * o.tau[c] : source(o, c, k));
         double den = o.nu;
         for (int j = 0; j < o.dim; ++j) {
           const double a = std::fabs(o.v[j][k]) * inv_dx;
           int s1 = 0, s2 = 0;
-          const double y1 = upstream_value(o, x, j, 1, k, hk, &s1);
+          const double y1 = upstream_value(o, x, j, 1, k, hk, &s1, psi);
           double y2 = 0.0;
-          if (!s1) y2 = upstream_value(o, x, j, 2, k, hk, &s2);
+          if (!s1) y2 = upstream_value(o, x, j, 2, k, hk, &s2, psi);
           if (s1 || (o.stencil_rule == 1 && s2)) {  // first order: C = (1, -1, 0)/dx
             den += a;
             num += a * y1;
@@ -269,7 +279,10 @@ void *orc_create(int dim, const int *n, const uint8_t *solid, const int *nv,
     o->phi[j][1].assign(o->N, 0.0);
   }
   for (int a = 0; a < dim; ++a)
-    for (int s = 0; s < 4; ++s) o->hbc[a][s].assign(o->face_count(a) * o->K, 0.0);
+    for (int s = 0; s < 4; ++s) {
+      o->hbc[a][s].assign(o->face_count(a) * o->K, 0.0);
+      if (o->has_psi()) o->psibc[a][s].assign(o->face_count(a) * o->K, 0.0);
+    }
   return o;
 }
 
@@ -307,8 +320,11 @@ void orc_set_initial(void *hh, const double *rho, const double *u, const double 
       if (r < 0 || r >= o.n[a]) continue;
       for (long f = 0; f < o.face_count(a); ++f) {
         const long c = face_cell(o, a, r, f);
-        for (int k = 0; k < o.K; ++k)
+        for (int k = 0; k < o.K; ++k) {
           o.hbc[a][s][f * o.K + k] = o.solid[c] ? 0.0 : source(o, c, k);
+          // the local equilibrium's psi: tau int (v3^2 - 1/2) v3^2 = tau / 2
+          if (o.has_psi()) o.psibc[a][s][f * o.K + k] = o.solid[c] ? 0.0 : 0.5 * o.tau[c];
+        }
       }
     }
   o.iters_done = 0;
@@ -323,12 +339,18 @@ int orc_iterate(void *hh, long iters, double tol, int stop_mode, double *stats) 
   Oracle &o = *static_cast<Oracle *>(hh);
   const int T = o.nthreads;
   const long N = o.N;
-  const int nm = 1 + 2 * o.dim + 1 + o.dim;  // rho, phi(+-), sum W|v|^2 h, q
+  // rho, phi(+-), sum W|v|^2 h, q, then (2D with tau_fb) sum W psi
+  const int nm = 1 + 2 * o.dim + 1 + o.dim + (o.has_psi() ? 1 : 0);
+  const int PSI = 2 + 3 * o.dim;  // index of the psi sum
   std::vector<std::vector<double>> acc(T, std::vector<double>((size_t)nm * N));
   std::vector<std::vector<double>> hk(T, std::vector<double>(N));
-  std::vector<double> hbc_new[3][4];
+  std::vector<std::vector<double>> pk(T, std::vector<double>(o.has_psi() ? N : 0));
+  std::vector<double> hbc_new[3][4], psibc_new[3][4];
   for (int a = 0; a < o.dim; ++a)
-    for (int s = 0; s < 4; ++s) hbc_new[a][s].assign(o.hbc[a][s].size(), 0.0);
+    for (int s = 0; s < 4; ++s) {
+      hbc_new[a][s].assign(o.hbc[a][s].size(), 0.0);
+      if (o.has_psi()) psibc_new[a][s].assign(o.psibc[a][s].size(), 0.0);
+    }
   long done = 0;
   int converged = 0;
   for (long it = 0; it < iters; ++it) {
@@ -344,6 +366,8 @@ int orc_iterate(void *hh, long iters, double tol, int stop_mode, double *stats) 
 #endif
       double *h = hk[t].data();
       sweep_velocity(o, k, h);
+      double *ps = o.has_psi() ? pk[t].data() : nullptr;
+      if (ps) sweep_velocity(o, k, ps, true);
       // step (iii): quadrature moments and half-fluxes [Eq. perturbed_quantities]
       double *A = acc[t].data();
       double v2 = 0;
@@ -361,6 +385,12 @@ int orc_iterate(void *hh, long iters, double tol, int stop_mode, double *stats) 
           A[(2 + 2 * o.dim + j) * N + c] += wh * vj * (vsq - 2.5);
         }
         A[(1 + 2 * o.dim) * N + c] += wh * vsq;
+        if (ps) {
+          const double wp = o.W[k] * ps[c];
+          A[PSI * N + c] += wp;
+          // q_j gains int v_j v3^2 h = v_j (psi + phi/2); the phi/2 is in vsq
+          for (int j = 0; j < o.dim; ++j) A[(2 + 2 * o.dim + j) * N + c] += wp * o.v[j][k];
+        }
       }
       // step (ii): keep the boundary layers of h for the next iteration
       for (int a = 0; a < o.dim; ++a)
@@ -370,6 +400,7 @@ int orc_iterate(void *hh, long iters, double tol, int stop_mode, double *stats) 
           for (long f = 0; f < o.face_count(a); ++f) {
             const long c = face_cell(o, a, r, f);
             hbc_new[a][s][f * o.K + k] = o.solid[c] ? 0.0 : h[c];
+            if (ps) psibc_new[a][s][f * o.K + k] = o.solid[c] ? 0.0 : ps[c];
           }
         }
     }
@@ -392,10 +423,14 @@ int orc_iterate(void *hh, long iters, double tol, int stop_mode, double *stats) 
         o.q[j][c] = M[(2 + 2 * o.dim + j) * N + c];
       }
       o.tau[c] = (2.0 / 3.0) * M[(1 + 2 * o.dim) * N + c] - (2.0 / 3.0) * 1.5 * M[c];
+      if (o.has_psi()) o.tau[c] += (2.0 / 3.0) * M[PSI * N + c];
       sum_u1 += o.u[0][c];
     }
     for (int a = 0; a < o.dim; ++a)
-      for (int s = 0; s < 4; ++s) o.hbc[a][s].swap(hbc_new[a][s]);
+      for (int s = 0; s < 4; ++s) {
+        o.hbc[a][s].swap(hbc_new[a][s]);
+        if (o.has_psi()) o.psibc[a][s].swap(psibc_new[a][s]);
+      }
     ++o.iters_done;
     ++done;
     // steps (iv)-(v): G_p as the mean of u1 over all cells (solid = 0), k, r, Err
