@@ -83,7 +83,10 @@ typedef struct {
   int32_t precision;         /* PDVM_FP64 or PDVM_FP32 (moments and reductions stay FP64) */
   int32_t lateral_bc;        /* PDVM_LATERAL_SPECULAR (paper) or PDVM_LATERAL_PERIODIC */
   int32_t tau_feedback;      /* 0 = isothermal source as in the paper's runs; 1 = feed the
-                                temperature term back (3D only, else PDVM_E_UNSUPPORTED) */
+                                temperature term back. In 2D this also carries the second
+                                v3-reduced function psi = int (v3^2 - 1/2) h dv3 in a second
+                                slot per velocity (twice the work and memory; at most 512
+                                velocities per sign octant, else PDVM_E_INVAL) */
   int32_t check_every;       /* host polls convergence every this many iterations (0 = 16) */
   int32_t tile[3];           /* sweep tile extent per axis in voxels (0 = default: 8 along
                                 x1, x1's value along x2, 8 along x3); x1 and x2 are capped

@@ -189,6 +189,7 @@ struct Problem {
   int lateral_periodic = 0, tau_fb = 0, precision = 0, check_every = 16, stencil_rule = 1;
   int schedule = 0;  // sweep schedule requested (PDVM_SCHEDULE_*)
   std::vector<uint32_t> flags;
+  int psi = 0;       // 2D with tau feedback: octant slots [Ko/2, Ko) hold psi
   std::vector<double> absv, wq, vsqm, rden;   // host FP64 tables, [rows][Ko_pad]
   std::vector<int32_t> diag_tiles, diag_off;
   std::vector<int32_t> fluid_idx;  // fluid voxels in index order
@@ -219,13 +220,13 @@ int validate_and_build(const pdvm_config *cfg, Problem &P, std::string &err) {
   if (!std::isfinite(cfg->jump)) { err = "jump must be finite"; return PDVM_E_INVAL; }
   if (cfg->precision != PDVM_FP64 && cfg->precision != PDVM_FP32) { err = "precision must be FP64 or FP32"; return PDVM_E_INVAL; }
   if (cfg->lateral_bc != PDVM_LATERAL_SPECULAR && cfg->lateral_bc != PDVM_LATERAL_PERIODIC) { err = "bad lateral_bc"; return PDVM_E_INVAL; }
-  if (cfg->tau_feedback && P.dim != 3) { err = "tau feedback needs the second reduced distribution in 2D"; return PDVM_E_UNSUPPORTED; }
   P.kn = cfg->kn;
   P.nu = std::isinf(cfg->kn) ? 0.0 : std::sqrt(M_PI) / (2.0 * cfg->kn);
   P.jump = cfg->jump;
   P.precision = cfg->precision;
   P.lateral_periodic = cfg->lateral_bc == PDVM_LATERAL_PERIODIC;
   P.tau_fb = cfg->tau_feedback ? 1 : 0;
+  P.psi = P.dim == 2 && P.tau_fb;
   P.check_every = cfg->check_every > 0 ? cfg->check_every : 16;
   if (cfg->sweep_schedule < 0 || cfg->sweep_schedule > 3) { err = "sweep_schedule must be 0..3"; return PDVM_E_INVAL; }
   P.schedule = cfg->sweep_schedule;
@@ -263,8 +264,15 @@ int validate_and_build(const pdvm_config *cfg, Problem &P, std::string &err) {
     P.hv[a] = m / 2;
     for (int i = 0; i < m / 2; ++i) { xp[a].push_back(x[m / 2 + i]); wp[a].push_back(w[m / 2 + i]); }
   }
-  P.Ko = P.hv[0] * P.hv[1] * P.hv[2];
-  if (P.Ko > 16 * kWave) { err = "at most 1024 velocities per sign octant"; return PDVM_E_INVAL; }
+  // velocities per sign octant; in 2D with the temperature fed back, each
+  // velocity also carries the second reduced function psi, in slot Kv + q
+  const int Kv = P.hv[0] * P.hv[1] * P.hv[2];
+  P.Ko = P.psi ? 2 * Kv : Kv;
+  if (P.Ko > 16 * kWave) {
+    err = P.psi ? "at most 512 velocities per sign octant in 2D with tau feedback (psi doubles them)"
+                : "at most 1024 velocities per sign octant";
+    return PDVM_E_INVAL;
+  }
   const int elem = P.precision == PDVM_FP64 ? 8 : 4;
   const int line = 128 / elem;
   P.Ko_pad = (P.Ko + line - 1) / line * line;
@@ -275,20 +283,26 @@ int validate_and_build(const pdvm_config *cfg, Problem &P, std::string &err) {
   const double dx_inv = (double)P.n[0];
   P.absv.assign(3 * (size_t)P.Ko_pad, 0.0);
   P.wq.assign(5 * (size_t)P.Ko_pad, 0.0);
-  P.vsqm.assign(P.Ko_pad, 0.0);
+  P.vsqm.assign(2 * (size_t)P.Ko_pad, 0.0);  // row 0: temperature-source factor, row 1: 1 = h, 0 = psi
   P.rden.assign(8 * (size_t)P.Ko_pad, 0.0);
   for (int q = 0; q < P.Ko; ++q) {
-    const int p[3] = {q % P.hv[0], (q / P.hv[0]) % P.hv[1], q / (P.hv[0] * P.hv[1])};
+    const int qv = q % Kv;
+    const bool ps = q >= Kv;  // a psi slot
+    const int p[3] = {qv % P.hv[0], (qv / P.hv[0]) % P.hv[1], qv / (P.hv[0] * P.hv[1])};
     double W = 1, vsq = 0;
     for (int j = 0; j < 3; ++j) {
       W *= wp[j][p[j]];
       if (j < P.dim) { P.absv[j * P.Ko_pad + q] = xp[j][p[j]]; vsq += xp[j][p[j]] * xp[j][p[j]]; }
     }
-    P.wq[q] = W;
-    for (int j = 0; j < P.dim; ++j) P.wq[(1 + j) * P.Ko_pad + q] = W * xp[j][p[j]];
+    // moment weights: psi enters only the energy, as int (v3^2 - 1/2) h = psi
+    P.wq[q] = ps ? 0.0 : W;
+    for (int j = 0; j < P.dim; ++j) P.wq[(1 + j) * P.Ko_pad + q] = ps ? 0.0 : W * xp[j][p[j]];
     // |v|^2 weight row (2D: the reduced distribution adds <v3^2> = 1/2)
-    P.wq[(1 + P.dim) * P.Ko_pad + q] = W * (vsq + (P.dim == 2 ? 0.5 : 0.0));
-    P.vsqm[q] = vsq - 1.5;
+    P.wq[(1 + P.dim) * P.Ko_pad + q] = ps ? W : W * (vsq + (P.dim == 2 ? 0.5 : 0.0));
+    // temperature source factor: |v|^2 - 3/2, integrated over v3 in 2D
+    // (v1^2 + v2^2 - 1); psi's source is tau / 2
+    P.vsqm[q] = ps ? 0.5 : vsq - (P.dim == 2 ? 1.0 : 1.5);
+    P.vsqm[P.Ko_pad + q] = ps ? 0.0 : 1.0;
     for (int combo = 0; combo < (1 << P.dim); ++combo) {
       double den = P.nu;
       for (int j = 0; j < P.dim; ++j) den += xp[j][p[j]] * dx_inv * (((combo >> j) & 1) ? 1.0 : 1.5);
@@ -423,7 +437,7 @@ Layout<T> make_layout(const Problem &P) {
   L.flags = take(N * 4);
   L.absv = take(3 * (size_t)P.Ko_pad * sizeof(T));
   L.av = take(3 * (size_t)P.Ko_pad * sizeof(T));
-  L.vsqm = take((size_t)P.Ko_pad * sizeof(T));
+  L.vsqm = take(2 * (size_t)P.Ko_pad * sizeof(T));
   L.rden = take(8 * (size_t)P.Ko_pad * sizeof(T));
   L.wq = take(5 * (size_t)P.Ko_pad * 8);
   for (int b = 0; b < 2; ++b) {
@@ -592,6 +606,8 @@ int setup_problem(pdvm_solver *s, int i) {
   g.absv = (const T *)(b + L.absv);
   g.av = (const T *)(b + L.av);
   g.vsqm = (const T *)(b + L.vsqm);
+  g.phm = g.vsqm + P.Ko_pad;
+  g.psi = P.psi;
   g.rden = (const T *)(b + L.rden);
   g.wq = (const double *)(b + L.wq);
   for (int k = 0; k < 2; ++k) {
@@ -695,6 +711,7 @@ int finalize_batch(pdvm_solver *s) {
   B.tile_edge = tile_edge;
   B.y2wall = P0.stencil_rule == 0;
   B.tau_fb = P0.tau_fb;
+  B.psi = P0.psi;
   B.ndiag_max = ndmax;
   B.d_geo = (const Geo<T> *)geo;
   B.d_item_off = (const int *)item;

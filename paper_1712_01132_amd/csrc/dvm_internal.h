@@ -52,15 +52,19 @@ struct Geo {
   int64_t N;
   int32_t Ko, Ko_pad, Kpad, ngroups;  // velocities per sign octant, padded, per voxel, 64-groups per octant
   int32_t lateral_periodic, tau_fb;
+  int32_t psi;             // 2D with tau_fb: octant slots [Ko/2, Ko) hold psi of velocity q - Ko/2
   int32_t y2wall;          // stencil rule 0: a solid second image enters the second-order stencil
   T jump;
   double nu, D[3];
   const uint32_t *flags;   // [N]
   const T *absv;           // [3][Ko_pad]   |v_j| of octant slot q
   const T *av;             // [3][Ko_pad]   |v_j| / dx
-  const T *vsqm;           // [Ko_pad]      |v|^2 - 3/2
+  const T *vsqm;           // [Ko_pad]      temperature-source factor: |v|^2 - 3/2 (3D),
+                           //               v1^2 + v2^2 - 1 (2D), 1/2 (psi slots)
+  const T *phm;            // [Ko_pad]      1 for a slot of h, 0 for a psi slot (no rho, u, wall or jump terms)
   const T *rden;           // [8][Ko_pad]   1 / (nu + sum_j a_j (1 or 3/2)), bit j = first order on axis j
-  const double *wq;        // [5][Ko_pad]   W, W|v1|, W|v2|, W|v3|, W |v|^2 (2D: + W/2)
+  const double *wq;        // [5][Ko_pad]   W, W|v1|, W|v2|, W|v3|, W |v|^2 (2D: + W/2);
+                           //               psi slots: 0 except W in the energy row
   T *h[2];                 // [N][Kpad]     distribution, voxel-major, velocity fastest
   T *src[2];               // [N][kSrcStride]
   T *srct[2];              // [N] nu tau (only with the temperature term fed back)
@@ -100,7 +104,7 @@ constexpr int kTileEdge[2] = {4, 8};
 // block offsets; a single problem is a batch of one.
 template <typename T>
 struct Batch {
-  int nprob = 0, dim = 2, Ko = 0, tile_edge = 8, y2wall = 0, tau_fb = 0, ndiag_max = 0;
+  int nprob = 0, dim = 2, Ko = 0, tile_edge = 8, y2wall = 0, tau_fb = 0, psi = 0, ndiag_max = 0;
   const Geo<T> *d_geo = nullptr;
   const int *d_item_off = nullptr;   // [ndiag_max][nprob + 1] sweep blocks per diagonal
   const int *d_blk_off = nullptr;    // [nprob + 1] moment-kernel blocks

@@ -159,7 +159,7 @@ __device__ __forceinline__ int owner_of(const int *off, int nprob, int b) {
   return lo;
 }
 
-template <typename T, int DIM, int TT, bool Y2WALL>
+template <typename T, int DIM, int TT, bool Y2WALL, bool PSI>
 __global__ void __launch_bounds__(kWave)
     sweep_kernel(const Geo<T> *__restrict__ G, const int *__restrict__ item_off, int nprob, int diag) {
   constexpr int NC = TT * TT;
@@ -211,10 +211,15 @@ __global__ void __launch_bounds__(kWave)
     s[j] = sidx[j] ? -1 : 1;
     pin[j] = 1 - sidx[j];  // incoming half at a wall emitting along s e_j has sign -s
   }
+  // PSI: the lane's slot holds h (ph = 1) or psi (ph = 0), which has no
+  // rho, u or wall term and no jump at the x1 wrap
+  const T ph = PSI ? as_global(G_.phm)[qq] : T(1);
+  Dom<T> dv = dm;  // as dm, with the jump this lane's values take
+  if (PSI) dv.jump = dm.jump * ph;
   T vv[3] = {T(0), T(0), T(0)}, aa[3] = {T(0), T(0), T(0)};
 #pragma unroll
   for (int j = 0; j < DIM; ++j) {
-    const T av = absv[j * Ko_pad + qq];
+    const T av = absv[j * Ko_pad + qq] * ph;
     vv[j] = s[j] > 0 ? av : -av;
     aa[j] = avv[j * Ko_pad + qq];
   }
@@ -265,8 +270,8 @@ __global__ void __launch_bounds__(kWave)
           L1[k] = hz[(int64_t)(y * n0 + xs - s[0]) * Kp];
           L2[k] = hz[(int64_t)(y * n0 + xs - 2 * s[0]) * Kp];
         } else {
-          L1[k] = upstream_fluid(dm, hc, hp, 0, xs - s[0], y, z, kofs, kmir[0]);
-          L2[k] = upstream_fluid(dm, hc, hp, 0, xs - 2 * s[0], y, z, kofs, kmir[0]);
+          L1[k] = upstream_fluid(dv, hc, hp, 0, xs - s[0], y, z, kofs, kmir[0]);
+          L2[k] = upstream_fluid(dv, hc, hp, 0, xs - 2 * s[0], y, z, kofs, kmir[0]);
         }
       }
       if (k < cnt[0]) {
@@ -275,8 +280,8 @@ __global__ void __launch_bounds__(kWave)
           B1[k] = hz[(int64_t)((ys - s[1]) * n0 + x) * Kp];
           B2[k] = hz[(int64_t)((ys - 2 * s[1]) * n0 + x) * Kp];
         } else {
-          B1[k] = upstream_fluid(dm, hc, hp, 1, x, ys - s[1], z, kofs, kmir[1]);
-          B2[k] = upstream_fluid(dm, hc, hp, 1, x, ys - 2 * s[1], z, kofs, kmir[1]);
+          B1[k] = upstream_fluid(dv, hc, hp, 1, x, ys - s[1], z, kofs, kmir[1]);
+          B2[k] = upstream_fluid(dv, hc, hp, 1, x, ys - 2 * s[1], z, kofs, kmir[1]);
         }
       }
     }
@@ -359,8 +364,8 @@ __global__ void __launch_bounds__(kWave)
             Z1[r] = hv0[-zstep];
             Z2[r] = hv0[-2 * zstep];
           } else {
-            Z1[r] = upstream_fluid(dm, hc, hp, 2, x, y, z - s[2], kofs, kmir[2]);
-            Z2[r] = upstream_fluid(dm, hc, hp, 2, x, y, z - 2 * s[2], kofs, kmir[2]);
+            Z1[r] = upstream_fluid(dv, hc, hp, 2, x, y, z - s[2], kofs, kmir[2]);
+            Z2[r] = upstream_fluid(dv, hc, hp, 2, x, y, z - 2 * s[2], kofs, kmir[2]);
           }
         }
       }
@@ -372,7 +377,7 @@ __global__ void __launch_bounds__(kWave)
         // anti-diagonal can be issued together (a skipped voxel's record is 0)
         const uint32_t code = __builtin_amdgcn_readfirstlane(rcode[i + TT * r]);
         const T *rp = rec + (i + TT * r) * RW;
-        T num = fma(rp[1], vv[0], rp[0]);
+        T num = fma(rp[1], vv[0], PSI ? rp[0] * ph : rp[0]);
         num = fma(rp[2], vv[1], num);
         if (DIM == 3) num = fma(rp[3], vv[2], num);
         num = fma(rp[4], vsqm, num);  // rp[4] = vsqm = 0 without the feedback
@@ -380,8 +385,8 @@ __global__ void __launch_bounds__(kWave)
         const T x1b = i >= 2 ? D2[r] : (i == 1 ? L1[r] : L2[r]);
         const T x2a = r >= 1 ? D1[r >= 1 ? r - 1 : 0] : B1[i];
         const T x2b = r >= 2 ? D2[r >= 2 ? r - 2 : 0] : (r == 1 ? B1[i] : B2[i]);
-        num = fma(aa[0], fma(rp[5], x1a, fma(rp[6], x1b, rp[7])), num);
-        num = fma(aa[1], fma(rp[8], x2a, fma(rp[9], x2b, rp[10])), num);
+        num = fma(aa[0], fma(rp[5], x1a, fma(rp[6], x1b, PSI ? rp[7] * ph : rp[7])), num);
+        num = fma(aa[1], fma(rp[8], x2a, fma(rp[9], x2b, PSI ? rp[10] * ph : rp[10])), num);
         if (DIM == 3) num = fma(aa[2], fma(rp[11], Z1[r], fma(rp[12], Z2[r], rp[13])), num);
         Nw[r] = num * rd_lds[(code & 7u) * kWave + lane];
         Nc[r] = code;
@@ -437,10 +442,13 @@ __global__ void __launch_bounds__(kWave)
 // counter polled after an L1 invalidation was never observed on gfx950.)
 // Otherwise: agent-scope release and acquire, correct for any placement.
 //
-// Lanes past the octant size read every per-velocity value and every halo
-// from slot 0, so they compute bit-exact copies of lane 0 and store them to
-// lane 0's slot: every store is then decided by the voxel alone (uniform),
-// without a per-lane mask.
+// Lanes past the octant size (in the last 64-velocity group of a chain) read
+// every per-velocity value and every halo from the octant's last slot, which
+// a lane of the same wavefront owns, so they compute bit-exact copies of that
+// lane's values and store them to its slot in the same instructions: every
+// store is then decided by the voxel alone (uniform), without a per-lane mask.
+// With TAU (the temperature fed back, which in 2D needs psi) a lane's slot
+// holds h or psi, as in sweep_kernel with PSI.
 template <typename T, int TT, bool Y2WALL, bool LOCAL, int NW, bool TAU>
 __global__ void __launch_bounds__(kWave * NW)
     sweep_rows_kernel(const Geo<T> *__restrict__ G, const int *__restrict__ row_off, int nprob, int stride) {
@@ -491,7 +499,7 @@ __global__ void __launch_bounds__(kWave * NW)
   const int o = c / ngroups;
   const int q = grp * kWave + lane;
   const bool active = q < Ko;
-  const int qq = active ? q : 0;
+  const int qq = active ? q : Ko - 1;
   int s[3], sidx[3], pin[3];
 #pragma unroll
   for (int k = 0; k < 3; ++k) {
@@ -499,10 +507,13 @@ __global__ void __launch_bounds__(kWave * NW)
     s[k] = sidx[k] ? -1 : 1;
     pin[k] = 1 - sidx[k];
   }
+  const T ph = TAU ? as_global(G_.phm)[qq] : T(1);
+  Dom<T> dv = dm;  // as dm, with the jump this lane's values take
+  if (TAU) dv.jump = dm.jump * ph;
   T vv[2], aa[2];
 #pragma unroll
   for (int k = 0; k < DIM; ++k) {
-    const T av = absv[k * Ko_pad + qq];
+    const T av = absv[k * Ko_pad + qq] * ph;
     vv[k] = s[k] > 0 ? av : -av;
     aa[k] = avv[k * Ko_pad + qq];
   }
@@ -623,8 +634,8 @@ __global__ void __launch_bounds__(kWave * NW)
     for (int k = 0; k < TT; ++k)
       if (k < cnt1) {
         const int y = ys + k * s[1];
-        L1[k] = upstream_fluid(dm, hc, hp, 0, xs - s[0], y, 0, kofs, kmir[0]);
-        L2[k] = upstream_fluid(dm, hc, hp, 0, xs - 2 * s[0], y, 0, kofs, kmir[0]);
+        L1[k] = upstream_fluid(dv, hc, hp, 0, xs - s[0], y, 0, kofs, kmir[0]);
+        L2[k] = upstream_fluid(dv, hc, hp, 0, xs - 2 * s[0], y, 0, kofs, kmir[0]);
       }
   }
   // uniform byte address of row r's first voxel in the current tile
@@ -742,15 +753,15 @@ __global__ void __launch_bounds__(kWave * NW)
           if (i < 0 || i >= TT) continue;
           const uint32_t code = __builtin_amdgcn_readfirstlane(rcode[i + TT * r]);
           const T *rp = rec + (i + TT * r) * RW;
-          T num = fma(rp[1], vv[0], rp[0]);
+          T num = fma(rp[1], vv[0], TAU ? rp[0] * ph : rp[0]);
           num = fma(rp[2], vv[1], num);
           if (TAU) num = fma(rp[9], vsqm, num);
           const T x1a = i >= 1 ? D1[r] : L1[r];
           const T x1b = i >= 2 ? D2[r] : (i == 1 ? L1[r] : L2[r]);
           const T x2a = r >= 1 ? D1[r >= 1 ? r - 1 : 0] : B1[i];
           const T x2b = r >= 2 ? D2[r >= 2 ? r - 2 : 0] : (r == 1 ? B1[i] : B2[i]);
-          num = fma(aa[0], fma(rp[3], x1a, fma(rp[4], x1b, rp[5])), num);
-          num = fma(aa[1], fma(rp[6], x2a, fma(rp[7], x2b, rp[8])), num);
+          num = fma(aa[0], fma(rp[3], x1a, fma(rp[4], x1b, TAU ? rp[5] * ph : rp[5])), num);
+          num = fma(aa[1], fma(rp[6], x2a, fma(rp[7], x2b, TAU ? rp[8] * ph : rp[8])), num);
           Nw[r] = num * *(const T *)((const char *)rd_lane + (code & ~R_SKIP));
           Nc[r] = code;
           if (FULL) {
@@ -1133,8 +1144,8 @@ __global__ void init_h_kernel(Geo<T> g, const double *rho, const double *u) {
     const int64_t c = e / g.Kpad;
     const int k = (int)(e - c * g.Kpad);
     const int o = k / g.Ko_pad, q = k - o * g.Ko_pad;
-    double v = 0.0;
-    if (q < g.Ko && !(g.flags[c] & F_SOLID)) {
+    double v = 0.0;  // psi of the local equilibrium is tau / 2 = 0
+    if (q < g.Ko && g.phm[q] != T(0) && !(g.flags[c] & F_SOLID)) {
       v = rho ? rho[c] : 0.0;
       if (u)
         for (int j = 0; j < DIM; ++j) {
@@ -1165,7 +1176,6 @@ __global__ void __launch_bounds__(kMomBlock) diagnostics_kernel(Geo<T> g, double
     for (int o = 0; o < (1 << DIM); ++o)
       for (int q = lane; q < g.Ko; q += kWave) {
         const double hv = (double)h[c * g.Kpad + o * g.Ko_pad + q];
-        const double w = g.wq[q];
         double vsq = DIM == 2 ? 0.5 : 0.0;
         double vj[3];
         for (int j = 0; j < DIM; ++j) {
@@ -1173,6 +1183,14 @@ __global__ void __launch_bounds__(kMomBlock) diagnostics_kernel(Geo<T> g, double
           vj[j] = ((o >> j) & 1) ? -a : a;
           vsq += a * a;
         }
+        if (g.psi && g.phm[q] == T(0)) {
+          // psi = int (v3^2 - 1/2) h: the energy takes W psi, q_j takes W v_j psi
+          const double w = g.wq[(1 + DIM) * g.Ko_pad + q];
+          e += w * hv;
+          for (int j = 0; j < DIM; ++j) qq[j] += w * vj[j] * hv;
+          continue;
+        }
+        const double w = g.wq[q];
         r += w * hv;
         e += w * vsq * hv;
         for (int j = 0; j < DIM; ++j) qq[j] += w * vj[j] * (vsq - 2.5) * hv;
@@ -1221,17 +1239,22 @@ void launch_sweep_rule(const Batch<T> &B, int diag, hipStream_t st) {
   const int items = B.h_item_off[(size_t)diag * (B.nprob + 1) + B.nprob];
   if (items == 0) return;
   const int *off = B.d_item_off + (size_t)diag * (B.nprob + 1);
-#define PDVM_SWEEP(D, X)                                                                             \
-  hipLaunchKernelGGL((sweep_kernel<T, D, X, Y2WALL>), dim3(items), dim3(kWave), 0, st, B.d_geo, off, \
+#define PDVM_SWEEP_P(D, X, P)                                                                           \
+  hipLaunchKernelGGL((sweep_kernel<T, D, X, Y2WALL, P>), dim3(items), dim3(kWave), 0, st, B.d_geo, off, \
                      B.nprob, diag)
+#define PDVM_SWEEP(D, X) PDVM_SWEEP_P(D, X, false)
   if (B.dim == 2) {
-    if (B.tile_edge <= 4) PDVM_SWEEP(2, 4);
+    if (B.psi) {
+      if (B.tile_edge <= 4) PDVM_SWEEP_P(2, 4, true);
+      else PDVM_SWEEP_P(2, 8, true);
+    } else if (B.tile_edge <= 4) PDVM_SWEEP(2, 4);
     else PDVM_SWEEP(2, 8);
   } else {
     if (B.tile_edge <= 4) PDVM_SWEEP(3, 4);
     else PDVM_SWEEP(3, 8);
   }
 #undef PDVM_SWEEP
+#undef PDVM_SWEEP_P
 }
 
 template <typename T>

@@ -83,7 +83,7 @@ def test_workspace_bytes_for_valid_config():
     ("asym", "symmetric"),
     ("kn0", "kn"),
     ("wsum", "sum"),
-    ("tau2d", "tau"),
+    ("tau2d_wide", "psi"),
     ("zero_node", "ascending"),
 ])
 def test_invalid_configs_rejected(case, needle):
@@ -109,8 +109,9 @@ def test_invalid_configs_rejected(case, needle):
     elif case == "wsum":
         x, w = quadrature.full_line_grid(4)
         grid = [(x, w * 1.001)] * 2
-    elif case == "tau2d":
-        kw["tau_feedback"] = True
+    elif case == "tau2d_wide":
+        kw["tau_feedback"] = True  # psi doubles the 576 velocities of an octant: over 1024
+        nv = [48, 48]
     elif case == "zero_node":
         grid = [(np.array([-1.0, -0.0, 0.0, 1.0]), np.array([0.25, 0.25, 0.25, 0.25]))] * 2
     kn = kw.pop("kn", 1.0)

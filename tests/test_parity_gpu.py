@@ -25,11 +25,11 @@ def rel(a, b):
 
 
 def pair(mask, nv, kn, precision="fp64", lateral="specular", tile=None, jump=1.0, tau=False, threads=16,
-         rule=1):
+         rule=1, schedule="auto"):
     o = OracleSolver(mask, nv, kn, jump=jump, lateral_periodic=(lateral == "periodic"),
                      tau_feedback=tau, threads=threads, stencil_rule=rule)
     s = poredvm.Solver(mask, nv, kn, jump=jump, precision=precision, lateral=lateral,
-                       tau_feedback=tau, tile=tile, grid=o.grid, stencil_rule=rule)
+                       tau_feedback=tau, tile=tile, grid=o.grid, stencil_rule=rule, schedule=schedule)
     return o, s
 
 
@@ -262,6 +262,41 @@ def test_tau_feedback_3d_matches_oracle():
     o.iterate(8)
     s.iterate(8)
     compare(o, s, RTOL64)
+
+
+@pytest.mark.parametrize("shape,nv,kn,tile,schedule,precision,lateral,rule", [
+    ((37, 29), [8, 8], 0.7, (4, 4), "rows", "fp64", "specular", 1),
+    ((37, 29), [8, 8], 0.7, (8, 8), "diagonals", "fp64", "specular", 1),
+    ((33, 26), [24, 24], 0.3, (8, 8), "rows", "fp64", "periodic", 1),
+    ((33, 26), [24, 24], 0.3, (4, 4), "diagonals", "fp64", "specular", 0),
+    ((29, 40), [6, 10], 2.0, (4, 4), "rows", "fp64", "specular", 0),
+    ((45, 40), [16, 16], 1.5, (4, 4), "rows", "fp32", "specular", 1),
+])
+def test_tau_feedback_2d_matches_oracle(shape, nv, kn, tile, schedule, precision, lateral, rule):
+    """2D with the temperature fed back: each velocity slot of an octant has a
+    psi slot after the octant's last velocity (Ko = 288 with the 24 x 24 grid:
+    psi starts inside a 64-velocity group and the last group is partial).
+    Random geometries: the GPU runs the oracle's iteration, lag included."""
+    m = random_mask(shape, 0.3, sum(shape) + 11)
+    o, s = pair(m, nv, kn, precision=precision, lateral=lateral, tile=tile, tau=True, rule=rule,
+                schedule=schedule)
+    assert s.schedule.startswith(schedule)
+    o.iterate(12)
+    s.iterate(12)
+    compare(o, s, RTOL64 if precision == "fp64" else RTOL32)
+
+
+@pytest.mark.parametrize("nv,tile", [([24, 24], (4, 4)), ([8, 8], (8, 8))])
+def test_tau_feedback_2d_row_pipeline_equals_tile_diagonals_bitwise(nv, tile):
+    m = random_mask((41, 35), 0.3, 21)
+    out = []
+    for sched in ("rows", "diagonals"):
+        s = poredvm.Solver(m, nv, 0.4, tau_feedback=True, tile=tile, schedule=sched)
+        s.iterate(9)
+        out.append(s.moments())
+        s.close()
+    for a, b in zip(*out):
+        assert np.array_equal(a, b)
 
 
 def test_paper_stop_mode_matches_oracle():
