@@ -40,6 +40,12 @@
 //   tau/2, wall value 0 (a diffuse wall emits a v3-Maxwellian) and no jump
 //   at the x1 wrap (the jump is v3-independent); phi (the reduced h) then
 //   has the source tau (v1^2 + v2^2 - 1), and tau takes int W psi;
+//   optional Shakhov model (a kinetic model the method extends to, Sec. 1
+//   and Sec. 2.1): the source gains (4/5)(1 - Pr) q.v (|v|^2 - 5/2), with
+//   the heat flux q = int v (|v|^2 - 5/2) h lagged like rho, u and tau, so
+//   that the collision relaxes q at the rate Pr nu instead of nu; reduced
+//   over v3 in 2D this is (4/5)(1 - Pr) q.v (v1^2 + v2^2 - 2) for phi and
+//   (2/5)(1 - Pr) q.v for psi;
 //   residual r = max|u^l - u^(l-1)| / max|u^l| over fluid cells and components.
 //
 // Velocity order inside this file: k = a + n1 (b + n2 c) over the tensor grid
@@ -71,6 +77,8 @@ struct Oracle {
   double D[3] = {0, 0, 0};   // D_j = sum_{v_j > 0} W v_j
   double kn = 1.0, nu = 0.0, J = 1.0;
   int lateral_periodic = 0, tau_fb = 0, nthreads = 1;
+  double prandtl = 0.0;  // > 0: Shakhov model with this Prandtl number (needs tau_fb)
+  double shakhov_coef() const { return prandtl > 0 ? 0.8 * (1.0 - prandtl) : 0.0; }
   // 0: first order iff the first upstream image is solid (a solid second
   //    upstream image enters the second-order stencil with its wall value);
   // 1: first order iff either upstream image is solid.
@@ -162,6 +170,7 @@ double upstream_value(const Oracle &o, const int x[3], int j, int m, int k,
 
 // Source term S_k(x) = rho + 2 u.v_k (+ tau(|v_k|^2 - 3/2)). [Eq. linearised_Boltzmann_equation]
 // In 2D |v|^2 - 3/2 integrates over v3 to v1^2 + v2^2 - 1.
+// Shakhov: + (4/5)(1 - Pr) q.v_k (|v_k|^2 - 5/2), in 2D (v1^2 + v2^2 - 2).
 double source(const Oracle &o, long c, int k) {
   double S = o.rho[c];
   for (int j = 0; j < o.dim; ++j) S += 2.0 * o.u[j][c] * o.v[j][k];
@@ -169,6 +178,23 @@ double source(const Oracle &o, long c, int k) {
     double v2 = 0;
     for (int j = 0; j < o.dim; ++j) v2 += o.v[j][k] * o.v[j][k];
     S += o.tau[c] * (o.dim == 2 ? v2 - 1.0 : v2 - 1.5);
+    if (o.prandtl > 0) {
+      double qv = 0;
+      for (int j = 0; j < o.dim; ++j) qv += o.q[j][c] * o.v[j][k];
+      S += o.shakhov_coef() * qv * (o.dim == 2 ? v2 - 2.0 : v2 - 2.5);
+    }
+  }
+  return S;
+}
+
+// Source of psi (2D with tau_fb): int (v3^2 - 1/2) S exp(-v3^2)/sqrt(pi) dv3
+// = tau / 2 (+ (1/2)(4/5)(1 - Pr) q.v_k for Shakhov).
+double psi_source(const Oracle &o, long c, int k) {
+  double S = 0.5 * o.tau[c];
+  if (o.prandtl > 0) {
+    double qv = 0;
+    for (int j = 0; j < o.dim; ++j) qv += o.q[j][c] * o.v[j][k];
+    S += 0.5 * o.shakhov_coef() * qv;
   }
   return S;
 }
@@ -188,7 +214,7 @@ void sweep_velocity(const Oracle &o, int k, double *hk, bool psi = false) {
         const long c = o.idx(i, jj, l);
         if (o.solid[c]) continue;
         const int x[3] = {i, jj, l};
-        double num = o.nu * (psi ? 0.5 * o.tau[c] : source(o, c, k));
+        double num = o.nu * (psi ? psi_source(o, c, k) : source(o, c, k));
         double den = o.nu;
         for (int j = 0; j < o.dim; ++j) {
           const double a = std::fabs(o.v[j][k]) * inv_dx;
@@ -288,6 +314,15 @@ void *orc_create(int dim, const int *n, const uint8_t *solid, const int *nv,
 
 void orc_destroy(void *h) { delete static_cast<Oracle *>(h); }
 
+// Switch to the Shakhov model with Prandtl number pr (0 < pr; pr = 1 is
+// BGK); needs tau_feedback. Call before orc_set_initial. Returns 0, or -1.
+int orc_set_shakhov(void *hh, double pr) {
+  Oracle &o = *static_cast<Oracle *>(hh);
+  if (!o.tau_fb || !(pr > 0)) return -1;
+  o.prandtl = pr;
+  return 0;
+}
+
 int orc_num_velocities(void *h) { return static_cast<Oracle *>(h)->K; }
 
 // Initial state as a local linearised equilibrium of the given fields:
@@ -300,6 +335,7 @@ void orc_set_initial(void *hh, const double *rho, const double *u, const double 
     o.rho[c] = (f && rho) ? rho[c] : 0.0;
     o.tau[c] = (f && tau && o.tau_fb) ? tau[c] : 0.0;
     for (int j = 0; j < o.dim; ++j) o.u[j][c] = (f && u) ? u[j * o.N + c] : 0.0;
+    for (int j = 0; j < o.dim; ++j) o.q[j][c] = 0.0;  // the equilibrium carries no heat flux
   }
   // half-fluxes of h = S_k: sum_{+-v_j>0} W |v_j| S_k
   for (long c = 0; c < o.N; ++c)
@@ -323,7 +359,7 @@ void orc_set_initial(void *hh, const double *rho, const double *u, const double 
         for (int k = 0; k < o.K; ++k) {
           o.hbc[a][s][f * o.K + k] = o.solid[c] ? 0.0 : source(o, c, k);
           // the local equilibrium's psi: tau int (v3^2 - 1/2) v3^2 = tau / 2
-          if (o.has_psi()) o.psibc[a][s][f * o.K + k] = o.solid[c] ? 0.0 : 0.5 * o.tau[c];
+          if (o.has_psi()) o.psibc[a][s][f * o.K + k] = o.solid[c] ? 0.0 : psi_source(o, c, k);
         }
       }
     }
@@ -532,7 +568,8 @@ void orc_apply_advection(void *hh, int k, const double *f, double *out) {
 
 // Collision term nu (S_k - h_k) of a distribution h (K values) at one node:
 // the moments of h by quadrature, then the isothermal (or full, with
-// tau_feedback) source. [Eqs. linearised_Boltzmann_equation, perturbed_quantities]
+// tau_feedback, or Shakhov) source, in the full velocity space (3D; in 2D the
+// tau and q terms would need psi). [Eqs. linearised_Boltzmann_equation, perturbed_quantities]
 void orc_collision(void *hh, const double *h, double *out) {
   Oracle &o = *static_cast<Oracle *>(hh);
   double rho = 0, u[3] = {0, 0, 0}, e = 0;
@@ -543,11 +580,18 @@ void orc_collision(void *hh, const double *h, double *out) {
     e += o.W[k] * v2 * h[k];
   }
   const double tau = (2.0 / 3.0) * e - rho;
+  double q[3] = {0, 0, 0};  // heat flux int v (|v|^2 - 5/2) h
+  for (int k = 0; k < o.K; ++k) {
+    double v2 = 0;
+    for (int j = 0; j < o.dim; ++j) v2 += o.v[j][k] * o.v[j][k];
+    for (int j = 0; j < o.dim; ++j) q[j] += o.W[k] * o.v[j][k] * (v2 - 2.5) * h[k];
+  }
   for (int k = 0; k < o.K; ++k) {
     double S = rho;
-    double v2 = 0;
-    for (int j = 0; j < o.dim; ++j) { S += 2.0 * u[j] * o.v[j][k]; v2 += o.v[j][k] * o.v[j][k]; }
+    double v2 = 0, qv = 0;
+    for (int j = 0; j < o.dim; ++j) { S += 2.0 * u[j] * o.v[j][k]; v2 += o.v[j][k] * o.v[j][k]; qv += q[j] * o.v[j][k]; }
     if (o.tau_fb) S += tau * (v2 - 1.5);
+    if (o.tau_fb && o.prandtl > 0) S += o.shakhov_coef() * qv * (v2 - 2.5);
     out[k] = o.nu * (S - h[k]);
   }
 }

@@ -42,6 +42,8 @@ def _load():
         lib.orc_destroy.argtypes = [vp]
         lib.orc_num_velocities.argtypes = [vp]
         lib.orc_set_initial.argtypes = [vp, dp, dp, dp]
+        lib.orc_set_shakhov.restype = ctypes.c_int
+        lib.orc_set_shakhov.argtypes = [vp, ctypes.c_double]
         lib.orc_iterate.argtypes = [vp, ctypes.c_long, ctypes.c_double, ctypes.c_int, dp]
         lib.orc_get_moments.argtypes = [vp, dp, dp, dp, dp]
         lib.orc_get_phi.argtypes = [vp, dp]
@@ -69,10 +71,11 @@ class OracleSolver:
     quadrature module is used; otherwise grid = [(nodes, weights), ...] per axis.
     stencil_rule 1 (default): first-order upwind stencil along an axis when
     either upstream image is solid; 0: only when the first one is.
+    prandtl (with tau_feedback): Shakhov model with this Prandtl number.
     """
 
     def __init__(self, solid, nv, kn, jump=1.0, lateral_periodic=False,
-                 tau_feedback=False, threads=None, grid=None, stencil_rule=1):
+                 tau_feedback=False, threads=None, grid=None, stencil_rule=1, prandtl=None):
         lib = _load()
         solid = np.ascontiguousarray(solid, dtype=np.uint8)
         self.dim = solid.ndim
@@ -101,6 +104,8 @@ class OracleSolver:
                                  self.threads, int(stencil_rule))
         self._keep = (nodes, weights)
         self.K = lib.orc_num_velocities(self._h)
+        if prandtl is not None and lib.orc_set_shakhov(self._h, float(prandtl)) != 0:
+            raise ValueError("the Shakhov model needs tau_feedback and prandtl > 0")
 
     def close(self):
         if getattr(self, "_h", None):

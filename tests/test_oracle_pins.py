@@ -74,6 +74,35 @@ def test_collision_conserves_mass_momentum(dim, tau_fb):
             assert abs(energy - expect) <= 1e-13 * scale
 
 
+@pytest.mark.parametrize("pr", [None, 2.0 / 3.0, 0.3, 1.0])
+def test_shakhov_collision_relaxes_heat_flux_at_prandtl_rate(pr):
+    """Shakhov model: the collision conserves mass, momentum and energy and
+    relaxes the heat flux q = int v (|v|^2 - 5/2) h at the rate Pr nu (BGK:
+    nu). Exact on the eight-node grid, which integrates the degree-6
+    polynomials involved."""
+    kn = 0.37
+    o = OracleSolver(np.zeros((4, 4, 4), np.uint8), [8] * 3, kn, tau_feedback=True, threads=1, prandtl=pr)
+    v, W = o.velocities()
+    v2 = np.sum(v ** 2, axis=0)
+    rng = np.random.default_rng(11)
+    rate = 1.0 if pr is None else pr
+    for _ in range(3):
+        h = rng.normal(size=o.K)
+        c = o.collision(h) / (math.sqrt(math.pi) / (2 * kn))
+        scale = np.sum(W * np.abs(h))
+        assert abs(np.sum(W * c)) <= 1e-14 * scale
+        assert abs(np.sum(W * v2 * c)) <= 1e-13 * scale
+        for j in range(3):
+            assert abs(np.sum(W * v[j] * c)) <= 1e-14 * scale
+            q = np.sum(W * v[j] * (v2 - 2.5) * h)
+            assert abs(np.sum(W * v[j] * (v2 - 2.5) * c) + rate * q) <= 1e-13 * scale
+
+
+def test_shakhov_needs_tau_feedback():
+    with pytest.raises(ValueError):
+        OracleSolver(np.zeros((4, 4), np.uint8), [4, 4], 1.0, prandtl=2.0 / 3.0)
+
+
 # --- upwind operator (Eq. numerical stencil) -----------------------------------
 
 def _linear_field(o, a, b=0.3):

@@ -36,12 +36,14 @@ CASES = [
 
 
 @pytest.mark.parametrize("case", [0, 1])
-@pytest.mark.parametrize("tau", [False, True])
-def test_2d_psi_equals_two_layer_extrusion(case, tau):
+@pytest.mark.parametrize("tau,pr", [(False, None), (True, None), (True, 2.0 / 3.0)])
+def test_2d_psi_equals_two_layer_extrusion(case, tau, pr):
+    """pr: the Shakhov model, whose heat-flux source reduces to
+    (4/5)(1 - Pr) q.v (v1^2 + v2^2 - 2) for phi and (2/5)(1 - Pr) q.v for psi."""
     m, kn = CASES[case]
     nv = [8, 8]
-    a = OracleSolver(m, nv, kn, tau_feedback=tau, threads=4)
-    b = OracleSolver(np.stack([m, m]), nv + [6], kn, tau_feedback=tau, threads=8)
+    a = OracleSolver(m, nv, kn, tau_feedback=tau, threads=4, prandtl=pr)
+    b = OracleSolver(np.stack([m, m]), nv + [6], kn, tau_feedback=tau, threads=8, prandtl=pr)
     ra = a.iterate(40000, 1e-13)
     rb = b.iterate(40000, 1e-13)
     assert ra["converged"] and rb["converged"]
@@ -57,9 +59,9 @@ def test_2d_psi_equals_two_layer_extrusion(case, tau):
     assert np.abs(t - t3[0]).max() <= tol
     assert np.abs(q - q3[:2, 0]).max() <= tol
     if tau:
-        # the feedback matters at this tolerance: it changes tau and q
-        iso = OracleSolver(m, nv, kn, threads=4)
-        iso.iterate(40000, 1e-13)
-        _, _, ti, qi = iso.moments()
+        # the feedback (and the Shakhov term) matters at this tolerance
+        ref = OracleSolver(m, nv, kn, tau_feedback=pr is not None, threads=4)
+        ref.iterate(40000, 1e-13)
+        _, _, ti, qi = ref.moments()
         assert np.abs(t - ti).max() > 1e3 * tol
         assert np.abs(q - qi).max() > 1e3 * tol
