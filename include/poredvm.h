@@ -99,6 +99,13 @@ typedef struct {
                                     this iteration can diverge on some geometries) */
   int32_t sweep_schedule;    /* PDVM_SCHEDULE_*; ROWS(_AGENT) with dim 3 is PDVM_E_UNSUPPORTED;
                                 a batch takes the first config's schedule */
+  double prandtl;            /* 0 = BGK. > 0 (needs tau_feedback = 1): Shakhov model, whose
+                                source adds (4/5)(1 - Pr) q.v (|v|^2 - 5/2) with the heat
+                                flux q of the previous iteration (2D: reduced over v3, as
+                                for tau), so that collisions relax q at Pr nu (a kinetic
+                                model the method extends to, Sec. 1 and Sec. 2.1; Pr = 2/3
+                                for a monatomic gas). Swept by the tile-diagonal schedule
+                                (AUTO picks it; ROWS(_AGENT) is PDVM_E_UNSUPPORTED) */
 } pdvm_config;
 
 typedef struct {

@@ -172,7 +172,8 @@ size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
 
 template <typename T>
 struct Layout {
-  size_t ctl, flags, absv, av, vsqm, rden, wq, h[2], src[2], srct[2], wall[2], rho[2], u[2], part, tiles, offs, fidx, scratch,
+  size_t ctl, flags, absv, av, vsqm, rden, wq, h[2], src[2], srct[2], srcq[2], wall[2], rho[2], u[2], part, tiles, offs, fidx,
+      scratch,
       progress, total;
 };
 
@@ -190,6 +191,7 @@ struct Problem {
   int schedule = 0;  // sweep schedule requested (PDVM_SCHEDULE_*)
   std::vector<uint32_t> flags;
   int psi = 0;       // 2D with tau feedback: octant slots [Ko/2, Ko) hold psi
+  double prandtl = 0;  // > 0: Shakhov model
   std::vector<double> absv, wq, vsqm, rden;   // host FP64 tables, [rows][Ko_pad]
   std::vector<int32_t> diag_tiles, diag_off;
   std::vector<int32_t> fluid_idx;  // fluid voxels in index order
@@ -227,11 +229,18 @@ int validate_and_build(const pdvm_config *cfg, Problem &P, std::string &err) {
   P.lateral_periodic = cfg->lateral_bc == PDVM_LATERAL_PERIODIC;
   P.tau_fb = cfg->tau_feedback ? 1 : 0;
   P.psi = P.dim == 2 && P.tau_fb;
+  if (!(cfg->prandtl >= 0) || !std::isfinite(cfg->prandtl)) { err = "prandtl must be >= 0 and finite"; return PDVM_E_INVAL; }
+  if (cfg->prandtl > 0 && !P.tau_fb) { err = "the Shakhov model (prandtl > 0) needs tau_feedback"; return PDVM_E_INVAL; }
+  P.prandtl = cfg->prandtl;
   P.check_every = cfg->check_every > 0 ? cfg->check_every : 16;
   if (cfg->sweep_schedule < 0 || cfg->sweep_schedule > 3) { err = "sweep_schedule must be 0..3"; return PDVM_E_INVAL; }
   P.schedule = cfg->sweep_schedule;
   if ((P.schedule == PDVM_SCHEDULE_ROWS || P.schedule == PDVM_SCHEDULE_ROWS_AGENT) && cfg->dim != 2) {
     err = "the row-pipeline sweep is 2D only";
+    return PDVM_E_UNSUPPORTED;
+  }
+  if ((P.schedule == PDVM_SCHEDULE_ROWS || P.schedule == PDVM_SCHEDULE_ROWS_AGENT) && P.prandtl > 0) {
+    err = "the Shakhov model is swept by the tile-diagonal schedule only";
     return PDVM_E_UNSUPPORTED;
   }
   if (cfg->stencil_rule != 0 && cfg->stencil_rule != 1) { err = "stencil_rule must be 0 or 1"; return PDVM_E_INVAL; }
@@ -282,8 +291,9 @@ int validate_and_build(const pdvm_config *cfg, Problem &P, std::string &err) {
   // per-slot tables of one octant (slot q <-> positive node indices p_j)
   const double dx_inv = (double)P.n[0];
   P.absv.assign(3 * (size_t)P.Ko_pad, 0.0);
-  P.wq.assign(5 * (size_t)P.Ko_pad, 0.0);
-  P.vsqm.assign(2 * (size_t)P.Ko_pad, 0.0);  // row 0: temperature-source factor, row 1: 1 = h, 0 = psi
+  P.wq.assign(8 * (size_t)P.Ko_pad, 0.0);
+  // row 0: temperature-source factor, row 1: 1 = h, 0 = psi, row 2: heat-flux source factor
+  P.vsqm.assign(3 * (size_t)P.Ko_pad, 0.0);
   P.rden.assign(8 * (size_t)P.Ko_pad, 0.0);
   for (int q = 0; q < P.Ko; ++q) {
     const int qv = q % Kv;
@@ -303,6 +313,13 @@ int validate_and_build(const pdvm_config *cfg, Problem &P, std::string &err) {
     // (v1^2 + v2^2 - 1); psi's source is tau / 2
     P.vsqm[q] = ps ? 0.5 : vsq - (P.dim == 2 ? 1.0 : 1.5);
     P.vsqm[P.Ko_pad + q] = ps ? 0.0 : 1.0;
+    // Shakhov: the source's q.v factor |v|^2 - 5/2, integrated over v3 in 2D
+    // (v1^2 + v2^2 - 2 for h, 1/2 for psi); q's weights W |v_j| (|v|^2 - 5/2)
+    // (2D: v1^2 + v2^2 - 2 for h, 1 for psi)
+    const double qs = ps ? 0.5 : vsq - (P.dim == 2 ? 2.0 : 2.5);
+    const double qw = ps ? 1.0 : vsq - (P.dim == 2 ? 2.0 : 2.5);
+    P.vsqm[2 * P.Ko_pad + q] = qs;
+    for (int j = 0; j < P.dim; ++j) P.wq[(5 + j) * P.Ko_pad + q] = W * xp[j][p[j]] * qw;
     for (int combo = 0; combo < (1 << P.dim); ++combo) {
       double den = P.nu;
       for (int j = 0; j < P.dim; ++j) den += xp[j][p[j]] * dx_inv * (((combo >> j) & 1) ? 1.0 : 1.5);
@@ -415,7 +432,7 @@ int validate_and_build(const pdvm_config *cfg, Problem &P, std::string &err) {
   // moment kernel: about 16 fluid voxels per wavefront, at most one round of 4096 wavefronts
   P.mom_blocks = (int)std::max<int64_t>(1, std::min<int64_t>((P.fluid + 63) / 64, 1024));
   uint64_t fp = 1469598103934665603ull;
-  const double scal[5] = {P.kn, P.jump, (double)P.lateral_periodic, (double)P.tau_fb, (double)P.stencil_rule};
+  const double scal[6] = {P.kn, P.jump, (double)P.lateral_periodic, (double)P.tau_fb, (double)P.stencil_rule, P.prandtl};
   fp = fnv1a(fp, scal, sizeof(scal));
   fp = fnv1a(fp, P.n, sizeof(P.n));
   fp = fnv1a(fp, P.hv, sizeof(P.hv));
@@ -437,13 +454,14 @@ Layout<T> make_layout(const Problem &P) {
   L.flags = take(N * 4);
   L.absv = take(3 * (size_t)P.Ko_pad * sizeof(T));
   L.av = take(3 * (size_t)P.Ko_pad * sizeof(T));
-  L.vsqm = take(2 * (size_t)P.Ko_pad * sizeof(T));
+  L.vsqm = take(3 * (size_t)P.Ko_pad * sizeof(T));
   L.rden = take(8 * (size_t)P.Ko_pad * sizeof(T));
-  L.wq = take(5 * (size_t)P.Ko_pad * 8);
+  L.wq = take(8 * (size_t)P.Ko_pad * 8);
   for (int b = 0; b < 2; ++b) {
     L.h[b] = take(N * (size_t)P.Kpad * sizeof(T));
     L.src[b] = take(N * kSrcStride * sizeof(T));
     L.srct[b] = take(N * sizeof(T));
+    L.srcq[b] = take(P.prandtl > 0 ? N * 4 * sizeof(T) : 0);
     L.wall[b] = take(N * 6 * sizeof(T));
     L.rho[b] = take(N * 8);
     L.u[b] = take(3 * N * 8);
@@ -607,13 +625,17 @@ int setup_problem(pdvm_solver *s, int i) {
   g.av = (const T *)(b + L.av);
   g.vsqm = (const T *)(b + L.vsqm);
   g.phm = g.vsqm + P.Ko_pad;
+  g.qsf = g.vsqm + 2 * P.Ko_pad;
   g.psi = P.psi;
+  g.shakhov = P.prandtl > 0;
+  g.sh_coef = P.prandtl > 0 ? 0.8 * (1.0 - P.prandtl) : 0.0;
   g.rden = (const T *)(b + L.rden);
   g.wq = (const double *)(b + L.wq);
   for (int k = 0; k < 2; ++k) {
     g.h[k] = (T *)(b + L.h[k]);
     g.src[k] = (T *)(b + L.src[k]);
     g.srct[k] = (T *)(b + L.srct[k]);
+    g.srcq[k] = P.prandtl > 0 ? (T *)(b + L.srcq[k]) : nullptr;
     g.wall[k] = (T *)(b + L.wall[k]);
     g.rho[k] = (double *)(b + L.rho[k]);
     g.u[k] = (double *)(b + L.u[k]);
@@ -712,6 +734,7 @@ int finalize_batch(pdvm_solver *s) {
   B.y2wall = P0.stencil_rule == 0;
   B.tau_fb = P0.tau_fb;
   B.psi = P0.psi;
+  B.shakhov = P0.prandtl > 0;
   B.ndiag_max = ndmax;
   B.d_geo = (const Geo<T> *)geo;
   B.d_item_off = (const int *)item;
@@ -844,8 +867,9 @@ int create_common(const pdvm_config *cfgs, int n, void *dev_workspace, size_t ws
     }
     const Problem &A = s->P[0], &B = s->P[i];
     if (B.precision != A.precision || !same_velocity_grid(A, B) || B.stencil_rule != A.stencil_rule ||
-        B.tau_fb != A.tau_fb) {
-      set_thread_error("config %d: a batch shares dimension, precision, velocity grid, stencil rule and tau feedback", i);
+        B.tau_fb != A.tau_fb || (B.prandtl > 0) != (A.prandtl > 0)) {
+      set_thread_error("config %d: a batch shares dimension, precision, velocity grid, stencil rule, tau feedback "
+                       "and collision model", i);
       delete s;
       return PDVM_E_INVAL;
     }
@@ -900,7 +924,7 @@ int create_common(const pdvm_config *cfgs, int n, void *dev_workspace, size_t ws
   // automatic: the row pipeline for a single 2D problem; a batch fills the
   // machine better with per-diagonal launches (measured)
   s->rows = P0.dim == 2 && (P0.schedule == PDVM_SCHEDULE_ROWS || P0.schedule == PDVM_SCHEDULE_ROWS_AGENT ||
-                            (P0.schedule == PDVM_SCHEDULE_AUTO && n == 1));
+                            (P0.schedule == PDVM_SCHEDULE_AUTO && n == 1 && !(P0.prandtl > 0)));
   if (s->rows) {
     // the row pipeline stores a tile through 32-bit byte offsets from its
     // lowest-addressed voxel
@@ -1061,7 +1085,7 @@ int get_flux_one(pdvm_solver *s, int i, double *gp, double *k, double *gp_sectio
 }
 
 // checkpoint layout: header, Ctl, then the parity-current rho, u, src, srct,
-// wall, then the boundary layers of h.
+// (Shakhov: srcq,) wall, then the boundary layers of h.
 struct StateHeader {
   uint64_t magic;
   int32_t dim, n0, n1, n2, Kpad, precision;
@@ -1088,7 +1112,8 @@ size_t state_bytes(const Problem &P, int precision) {
   const size_t es = precision == PDVM_FP64 ? 8 : 4;
   const size_t N = (size_t)P.N;
   const size_t kp = (size_t)kpad_of(P, precision);
-  size_t b = sizeof(StateHeader) + sizeof(Ctl) + N * 8 + 3 * N * 8 + N * kSrcStride * es + N * es + N * 6 * es;
+  const size_t nq = P.prandtl > 0 ? 4 * N : 0;  // srcq
+  size_t b = sizeof(StateHeader) + sizeof(Ctl) + N * 8 + 3 * N * 8 + N * kSrcStride * es + N * es + nq * es + N * 6 * es;
   for (int a = 0; a < P.dim; ++a) b += face_layers(P, a).size() * (N / P.n[a]) * kp * es;
   return b;
 }
@@ -1102,7 +1127,7 @@ void convert_sections(const Problem &P, const char *in, char *out, int64_t kin, 
   const size_t N = (size_t)P.N;
   const S *a = reinterpret_cast<const S *>(in);
   D *b = reinterpret_cast<D *>(out);
-  const size_t flat = N * kSrcStride + N + N * 6;  // src, srct, wall
+  const size_t flat = N * kSrcStride + N + (P.prandtl > 0 ? 4 * N : 0) + N * 6;  // src, srct, srcq, wall
   for (size_t i = 0; i < flat; ++i) b[i] = (D)a[i];
   a += flat;
   b += flat;
@@ -1152,6 +1177,7 @@ int state_io(pdvm_solver *s, int i, char *buf, bool save) {
   if ((rc = xfer(g.u[par], 3 * N * 8))) return rc;
   if ((rc = xfer(g.src[par], N * kSrcStride * sizeof(T)))) return rc;
   if ((rc = xfer(g.srct[par], N * sizeof(T)))) return rc;
+  if (P.prandtl > 0 && (rc = xfer(g.srcq[par], 4 * N * sizeof(T)))) return rc;
   if ((rc = xfer(g.wall[par], N * 6 * sizeof(T)))) return rc;
   T *stage = g.h[par ^ 1];  // free between iterations
   for (int a = 0; a < P.dim; ++a)

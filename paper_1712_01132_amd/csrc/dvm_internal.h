@@ -53,6 +53,8 @@ struct Geo {
   int32_t Ko, Ko_pad, Kpad, ngroups;  // velocities per sign octant, padded, per voxel, 64-groups per octant
   int32_t lateral_periodic, tau_fb;
   int32_t psi;             // 2D with tau_fb: octant slots [Ko/2, Ko) hold psi of velocity q - Ko/2
+  int32_t shakhov;         // the heat flux is fed back (Shakhov model)
+  double sh_coef;          // (4/5)(1 - Pr)
   int32_t y2wall;          // stencil rule 0: a solid second image enters the second-order stencil
   T jump;
   double nu, D[3];
@@ -62,12 +64,15 @@ struct Geo {
   const T *vsqm;           // [Ko_pad]      temperature-source factor: |v|^2 - 3/2 (3D),
                            //               v1^2 + v2^2 - 1 (2D), 1/2 (psi slots)
   const T *phm;            // [Ko_pad]      1 for a slot of h, 0 for a psi slot (no rho, u, wall or jump terms)
+  const T *qsf;            // [Ko_pad]      Shakhov source factor of q.v: |v|^2 - 5/2 (2D: v1^2 + v2^2 - 2; psi 1/2)
   const T *rden;           // [8][Ko_pad]   1 / (nu + sum_j a_j (1 or 3/2)), bit j = first order on axis j
-  const double *wq;        // [5][Ko_pad]   W, W|v1|, W|v2|, W|v3|, W |v|^2 (2D: + W/2);
-                           //               psi slots: 0 except W in the energy row
+  const double *wq;        // [8][Ko_pad]   W, W|v1|, W|v2|, W|v3|, W |v|^2 (2D: + W/2), then the heat
+                           //               flux's W |v_j| (|v|^2 - 5/2) (2D: v1^2 + v2^2 - 2);
+                           //               psi slots: 0 except W in the energy row and W |v_j| for q
   T *h[2];                 // [N][Kpad]     distribution, voxel-major, velocity fastest
   T *src[2];               // [N][kSrcStride]
   T *srct[2];              // [N] nu tau (only with the temperature term fed back)
+  T *srcq[2];              // [N][4] nu sh_coef q_j (Shakhov only, else null)
   T *wall[2];              // [N][6]        Phi_j^p / D_j  (p = 0: v_j > 0 half, 1: v_j < 0)
   double *rho[2];          // [N]
   double *u[2];            // [3][N]
@@ -89,6 +94,7 @@ struct Geo {
   T *hcur = nullptr;          // h being swept this iteration: h[par ^ 1]
   const T *hprev = nullptr;   // h of the previous iteration: h[par]
   const T *srccur = nullptr, *srctcur = nullptr, *wallcur = nullptr;  // src, srct, wall [par]
+  const T *srcqcur = nullptr;  // srcq [par]
   int32_t seq = 0;            // advanced by every arm and reduction: stamps of the row pipeline
   int32_t *progress = nullptr;  // [bands][chains] tiles completed per band (row-pipeline sweep)
   int64_t wait_ticks = 0;       // a row-pipeline wait gives up after this many wall-clock ticks (2 s)
@@ -104,7 +110,7 @@ constexpr int kTileEdge[2] = {4, 8};
 // block offsets; a single problem is a batch of one.
 template <typename T>
 struct Batch {
-  int nprob = 0, dim = 2, Ko = 0, tile_edge = 8, y2wall = 0, tau_fb = 0, psi = 0, ndiag_max = 0;
+  int nprob = 0, dim = 2, Ko = 0, tile_edge = 8, y2wall = 0, tau_fb = 0, psi = 0, shakhov = 0, ndiag_max = 0;
   const Geo<T> *d_geo = nullptr;
   const int *d_item_off = nullptr;   // [ndiag_max][nprob + 1] sweep blocks per diagonal
   const int *d_blk_off = nullptr;    // [nprob + 1] moment-kernel blocks

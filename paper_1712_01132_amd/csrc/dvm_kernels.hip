@@ -159,11 +159,14 @@ __device__ __forceinline__ int owner_of(const int *off, int nprob, int b) {
   return lo;
 }
 
-template <typename T, int DIM, int TT, bool Y2WALL, bool PSI>
+// EXT bit 0 (PSI, 2D): slots of h and of psi; bit 1 (SH): the Shakhov
+// heat-flux source, whose per-voxel values nu (4/5)(1 - Pr) q_j end the record.
+template <typename T, int DIM, int TT, bool Y2WALL, int EXT>
 __global__ void __launch_bounds__(kWave)
     sweep_kernel(const Geo<T> *__restrict__ G, const int *__restrict__ item_off, int nprob, int diag) {
+  constexpr bool PSI = (EXT & 1) != 0, SH = (EXT & 2) != 0;
   constexpr int NC = TT * TT;
-  constexpr int RW = 5 + 3 * DIM;  // record: src (4), nu tau, then per axis (c1, c2, w)
+  constexpr int RW = 5 + 3 * DIM + (SH ? DIM : 0);  // record: src (4), nu tau, per axis (c1, c2, w), [q]
   __shared__ T rd_lds[8 * kWave];
   __shared__ T rec[NC * RW];
   __shared__ uint32_t rcode[NC];
@@ -181,6 +184,7 @@ __global__ void __launch_bounds__(kWave)
   const gptr<const T> hp = as_global(G_.hprev);
   const gptr<const T> src = as_global(G_.srccur);
   const gptr<const T> srct = as_global(G_.srctcur);
+  const gptr<const T> srcq = as_global(G_.srcqcur);
   const gptr<const T> wall = as_global(G_.wallcur);
   const gptr<const uint32_t> flags = as_global(G_.flags);
   const int n0 = dm.n[0], n1 = dm.n[1];
@@ -216,12 +220,15 @@ __global__ void __launch_bounds__(kWave)
   const T ph = PSI ? as_global(G_.phm)[qq] : T(1);
   Dom<T> dv = dm;  // as dm, with the jump this lane's values take
   if (PSI) dv.jump = dm.jump * ph;
-  T vv[3] = {T(0), T(0), T(0)}, aa[3] = {T(0), T(0), T(0)};
+  T vv[3] = {T(0), T(0), T(0)}, aa[3] = {T(0), T(0), T(0)}, cq[3] = {T(0), T(0), T(0)};
+  const T qs = SH ? as_global(G_.qsf)[qq] : T(0);  // the Shakhov source's q.v factor
 #pragma unroll
   for (int j = 0; j < DIM; ++j) {
-    const T av = absv[j * Ko_pad + qq] * ph;
+    const T a = absv[j * Ko_pad + qq];
+    const T av = a * ph;
     vv[j] = s[j] > 0 ? av : -av;
     aa[j] = avv[j * Ko_pad + qq];
+    if (SH) cq[j] = (s[j] > 0 ? a : -a) * qs;
   }
 #pragma unroll
   for (int c = 0; c < (1 << DIM); ++c) rd_lds[c * kWave + lane] = rden[c * Ko_pad + qq];
@@ -310,6 +317,10 @@ __global__ void __launch_bounds__(kWave)
           rp[2] = sv2;
           rp[3] = sv3;
           rp[4] = svt;
+          if (SH) {
+#pragma unroll
+            for (int j = 0; j < DIM; ++j) rp[5 + 3 * DIM + j] = srcq[c * 4 + j];
+          }
           code = 0;
 #pragma unroll
           for (int j = 0; j < DIM; ++j) {
@@ -381,6 +392,10 @@ __global__ void __launch_bounds__(kWave)
         num = fma(rp[2], vv[1], num);
         if (DIM == 3) num = fma(rp[3], vv[2], num);
         num = fma(rp[4], vsqm, num);  // rp[4] = vsqm = 0 without the feedback
+        if (SH) {
+#pragma unroll
+          for (int j = 0; j < DIM; ++j) num = fma(rp[5 + 3 * DIM + j], cq[j], num);
+        }
         const T x1a = i >= 1 ? D1[r] : L1[r];
         const T x1b = i >= 2 ? D2[r] : (i == 1 ? L1[r] : L2[r]);
         const T x2a = r >= 1 ? D1[r >= 1 ? r - 1 : 0] : B1[i];
@@ -881,7 +896,9 @@ using vec2_t = T __attribute__((ext_vector_type(2)));
 // 128 p + 2 l + 1 (m = 2 p, 2 p + 1), so a voxel's distribution is loaded with
 // half as many, twice as wide loads. A pair at or past Ko (both slots, as Ko
 // and the pair start are even) reads the last valid pair and weighs 0.
-template <typename T, int DIM, int NS, bool PAIR>
+// SH: also the heat flux q_j (signed per octant from the weights
+// W |v_j| (|v|^2 - 5/2)), stored as the Shakhov source nu (4/5)(1 - Pr) q_j.
+template <typename T, int DIM, int NS, bool PAIR, bool SH>
 __global__ void __launch_bounds__(kMomBlock)
     moments_kernel(const Geo<T> *__restrict__ G, const int *__restrict__ blk_off, int nprob) {
   const int pb = nprob > 1 ? owner_of(blk_off, nprob, blockIdx.x) : 0;
@@ -895,6 +912,7 @@ __global__ void __launch_bounds__(kMomBlock)
   const gptr<double> u_n = as_global(np ? g.u[1] : g.u[0]);
   const gptr<T> src_n = as_global(np ? g.src[1] : g.src[0]);
   const gptr<T> srct_n = as_global(np ? g.srct[1] : g.srct[0]);
+  const gptr<T> srcq_n = as_global(np ? g.srcq[1] : g.srcq[0]);
   const gptr<T> wall_n = as_global(np ? g.wall[1] : g.wall[0]);
   const gptr<const int32_t> fidx = as_global(g.fluid_idx);
   const gptr<const double> wq = as_global(g.wq);
@@ -905,7 +923,8 @@ __global__ void __launch_bounds__(kMomBlock)
   const int lane = threadIdx.x & (kWave - 1), wid = threadIdx.x / kWave;
   constexpr int WPB = kMomBlock / kWave;
   const int64_t nw = (int64_t)mom_blocks * WPB;
-  double wr[NS][2 + DIM];
+  constexpr int NR = 2 + DIM + (SH ? DIM : 0);
+  double wr[NS][NR];
   int qc[NS];
 #pragma unroll
   for (int m = 0; m < NS; ++m) {
@@ -914,7 +933,12 @@ __global__ void __launch_bounds__(kMomBlock)
     qc[m] = ok ? q : (PAIR ? Ko - 2 + (m & 1) : Ko - 1);
 #pragma unroll
     for (int r = 0; r < 2 + DIM; ++r) wr[m][r] = ok ? wq[r * Ko_pad + q] : 0.0;
+    if (SH) {
+#pragma unroll
+      for (int j = 0; j < DIM; ++j) wr[m][2 + DIM + j] = ok ? wq[(5 + j) * Ko_pad + q] : 0.0;
+    }
   }
+  const double shc = nu * g.sh_coef;
   auto load = [&](int64_t c, T (&hv)[1 << DIM][NS]) __attribute__((always_inline)) {
     const gptr<const T> hc = h + c * Kpad;
 #pragma unroll
@@ -949,6 +973,7 @@ __global__ void __launch_bounds__(kMomBlock)
       T hn[1 << DIM][NS];
       if (kAhead) load(cn, hn);  // in flight while this voxel is reduced
       double v[8] = {0, 0, 0, 0, 0, 0, 0, 0};  // rho, half-fluxes (j, +/-), energy
+      double qa[3] = {0, 0, 0};                 // SH: heat flux
 #pragma unroll
       for (int o = 0; o < (1 << DIM); ++o) {
 #pragma unroll
@@ -958,16 +983,35 @@ __global__ void __launch_bounds__(kMomBlock)
 #pragma unroll
           for (int j = 0; j < DIM; ++j) v[1 + 2 * j + ((o >> j) & 1)] = fma(wr[m][1 + j], x, v[1 + 2 * j + ((o >> j) & 1)]);
           v[7] = fma(wr[m][1 + DIM], x, v[7]);
+          if (SH) {
+#pragma unroll
+            for (int j = 0; j < DIM; ++j) qa[j] = fma(((o >> j) & 1) ? -wr[m][2 + DIM + j] : wr[m][2 + DIM + j], x, qa[j]);
+          }
         }
       }
+      // in 2D the heat flux fits the two unused sums (5, 6); in 3D it takes a second reduction
+      if (SH && DIM == 2) {
+        v[5] = qa[0];
+        v[6] = qa[1];
+      }
       const double tot = wave_sum8(v, lane);
+      double qt = 0;
+      if (SH && DIM == 3) {
+        const double w2[8] = {qa[0], qa[1], qa[2], 0, 0, 0, 0, 0};
+        qt = wave_sum8(w2, lane);
+      }
       const double r = readlane_d(tot, 0);
-      double ph[3][2];
+      // every lane reads the totals here, outside the lane-0 branch below: a
+      // read of another lane inside it could see a value whose last step the
+      // compiler moved into the branch, where only lane 0 computes it
+      double ph[3][2], qf[3] = {0, 0, 0};
 #pragma unroll
       for (int j = 0; j < DIM; ++j) {
         ph[j][0] = readlane_d(tot, 8 * (1 + 2 * j));
         ph[j][1] = readlane_d(tot, 8 * (2 + 2 * j));
+        if (SH) qf[j] = DIM == 2 ? readlane_d(tot, 8 * (5 + j)) : readlane_d(qt, 8 * j);
       }
+      const double en = readlane_d(tot, 56);
       if (lane == 0) {
         rho_n[c] = r;
         const gptr<T> sp = src_n + c * kSrcStride;
@@ -982,7 +1026,11 @@ __global__ void __launch_bounds__(kMomBlock)
           wall_n[c * 6 + 2 * j] = T(ph[j][0] / Dj[j]);
           wall_n[c * 6 + 2 * j + 1] = T(ph[j][1] / Dj[j]);
         }
-        if (tau_fb) srct_n[c] = T(nu * ((2.0 / 3.0) * readlane_d(tot, 56) - r));
+        if (tau_fb) srct_n[c] = T(nu * ((2.0 / 3.0) * en - r));
+        if (SH) {
+#pragma unroll
+          for (int j = 0; j < DIM; ++j) srcq_n[c * 4 + j] = T(shc * qf[j]);
+        }
         su += ph[0][0] - ph[0][1];
       }
       if (kAhead) {
@@ -1026,6 +1074,7 @@ __device__ void resolve(Geo<T> &g, int par, int run) {
   g.hprev = par ? g.h[1] : g.h[0];
   g.srccur = par ? g.src[1] : g.src[0];
   g.srctcur = par ? g.srct[1] : g.srct[0];
+  g.srcqcur = par ? g.srcq[1] : g.srcq[0];
   g.wallcur = par ? g.wall[1] : g.wall[0];
 }
 
@@ -1120,6 +1169,8 @@ __global__ void init_moments_kernel(Geo<T> g, const double *rho, const double *u
     for (int i = 0; i < kSrcStride; ++i) sp[i] = T(0);
     sp[0] = T(g.nu * r);
     g.srct[par][c] = T(0);
+    if (g.shakhov)
+      for (int j = 0; j < 4; ++j) g.srcq[par][c * 4 + j] = T(0);
     for (int j = 0; j < 3; ++j) {
       const double uj = (fl && u && j < DIM) ? u[j * g.N + c] : 0.0;
       if (j < DIM) {
@@ -1239,22 +1290,23 @@ void launch_sweep_rule(const Batch<T> &B, int diag, hipStream_t st) {
   const int items = B.h_item_off[(size_t)diag * (B.nprob + 1) + B.nprob];
   if (items == 0) return;
   const int *off = B.d_item_off + (size_t)diag * (B.nprob + 1);
-#define PDVM_SWEEP_P(D, X, P)                                                                           \
-  hipLaunchKernelGGL((sweep_kernel<T, D, X, Y2WALL, P>), dim3(items), dim3(kWave), 0, st, B.d_geo, off, \
+#define PDVM_SWEEP_E(D, X, E)                                                                           \
+  hipLaunchKernelGGL((sweep_kernel<T, D, X, Y2WALL, E>), dim3(items), dim3(kWave), 0, st, B.d_geo, off, \
                      B.nprob, diag)
-#define PDVM_SWEEP(D, X) PDVM_SWEEP_P(D, X, false)
+#define PDVM_SWEEP_T(D, E)              \
+  if (B.tile_edge <= 4) PDVM_SWEEP_E(D, 4, E); \
+  else PDVM_SWEEP_E(D, 8, E)
+  // EXT: bit 0 psi (2D with tau fed back), bit 1 Shakhov
   if (B.dim == 2) {
-    if (B.psi) {
-      if (B.tile_edge <= 4) PDVM_SWEEP_P(2, 4, true);
-      else PDVM_SWEEP_P(2, 8, true);
-    } else if (B.tile_edge <= 4) PDVM_SWEEP(2, 4);
-    else PDVM_SWEEP(2, 8);
+    if (B.shakhov) { PDVM_SWEEP_T(2, 3); }
+    else if (B.psi) { PDVM_SWEEP_T(2, 1); }
+    else { PDVM_SWEEP_T(2, 0); }
   } else {
-    if (B.tile_edge <= 4) PDVM_SWEEP(3, 4);
-    else PDVM_SWEEP(3, 8);
+    if (B.shakhov) { PDVM_SWEEP_T(3, 2); }
+    else { PDVM_SWEEP_T(3, 0); }
   }
-#undef PDVM_SWEEP
-#undef PDVM_SWEEP_P
+#undef PDVM_SWEEP_T
+#undef PDVM_SWEEP_E
 }
 
 template <typename T>
@@ -1303,12 +1355,20 @@ hipError_t launch_xcd_probe(uint32_t *out, int blocks, int threads, hipStream_t 
   return hipGetLastError();
 }
 
+template <typename T, int D, int S, bool P>
+void launch_moments_as(const Batch<T> &B, int blocks, hipStream_t st) {
+  if (B.shakhov)
+    hipLaunchKernelGGL((moments_kernel<T, D, S, P, true>), dim3(blocks), dim3(kMomBlock), 0, st, B.d_geo, B.d_blk_off,
+                       B.nprob);
+  else
+    hipLaunchKernelGGL((moments_kernel<T, D, S, P, false>), dim3(blocks), dim3(kMomBlock), 0, st, B.d_geo, B.d_blk_off,
+                       B.nprob);
+}
+
 template <typename T>
 hipError_t launch_moments(const Batch<T> &B, hipStream_t st) {
   const int blocks = B.h_blk_off[B.nprob];
-#define PDVM_MOM(D, S, P)                                                                        \
-  hipLaunchKernelGGL((moments_kernel<T, D, S, P>), dim3(blocks), dim3(kMomBlock), 0, st, B.d_geo, \
-                     B.d_blk_off, B.nprob)
+#define PDVM_MOM(D, S, P) launch_moments_as<T, D, S, P>(B, blocks, st)
   // paired slots (2 per lane and 128-slot block) in 2D: 9 % faster in FP32 on
   // the 512^2 rock, unchanged in FP64; slower on the 96^3 pack, so not in 3D
   if (B.dim == 2 && B.Ko % 2 == 0 && B.Ko >= 2) {

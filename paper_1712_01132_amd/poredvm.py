@@ -41,6 +41,7 @@ class PdvmConfig(ctypes.Structure):
         ("tile", ctypes.c_int32 * 3),
         ("stencil_rule", ctypes.c_int32),
         ("sweep_schedule", ctypes.c_int32),
+        ("prandtl", ctypes.c_double),
     ]
 
 
@@ -149,8 +150,10 @@ def velocity_grid(n_total):
 
 
 def make_config(solid, nv, kn, jump=1.0, precision="fp64", lateral="specular",
-                tau_feedback=False, tile=None, check_every=16, grid=None, stencil_rule=1, schedule="auto"):
-    """Build a PdvmConfig; returns (config, keepalive) -- keep both alive."""
+                tau_feedback=False, tile=None, check_every=16, grid=None, stencil_rule=1, schedule="auto",
+                prandtl=None):
+    """Build a PdvmConfig; returns (config, keepalive) -- keep both alive.
+    prandtl (with tau_feedback): Shakhov model with this Prandtl number."""
     solid = np.ascontiguousarray(solid, dtype=np.uint8)
     dim = solid.ndim
     if dim not in (2, 3):
@@ -177,6 +180,7 @@ def make_config(solid, nv, kn, jump=1.0, precision="fp64", lateral="specular",
     cfg.check_every = int(check_every)
     cfg.stencil_rule = int(stencil_rule)
     cfg.sweep_schedule = SCHEDULES[schedule]
+    cfg.prandtl = 0.0 if prandtl is None else float(prandtl)
     return cfg, (solid, grid)
 
 
@@ -189,7 +193,7 @@ class Solver:
 
     def __init__(self, solid, nv, kn, jump=1.0, precision="fp64", lateral="specular",
                  tau_feedback=False, tile=None, check_every=16, grid=None, device=None,
-                 stencil_rule=1, schedule="auto"):
+                 stencil_rule=1, schedule="auto", prandtl=None):
         import torch
 
         lib = load()
@@ -197,7 +201,8 @@ class Solver:
         self.dim = len(self.shape)
         self.N = int(np.prod(self.shape))
         self.cfg, self._keep = make_config(solid, nv, kn, jump, precision, lateral,
-                                           tau_feedback, tile, check_every, grid, stencil_rule, schedule)
+                                           tau_feedback, tile, check_every, grid, stencil_rule, schedule,
+                                           prandtl)
         nbytes = lib.pdvm_workspace_bytes(ctypes.byref(self.cfg))
         if nbytes == 0:
             raise PdvmError(PDVM_E_INVAL, _err())

@@ -84,6 +84,9 @@ def test_workspace_bytes_for_valid_config():
     ("kn0", "kn"),
     ("wsum", "sum"),
     ("tau2d_wide", "psi"),
+    ("shakhov_no_tau", "tau_feedback"),
+    ("shakhov_rows", "Shakhov"),
+    ("prandtl_neg", "prandtl"),
     ("zero_node", "ascending"),
 ])
 def test_invalid_configs_rejected(case, needle):
@@ -109,6 +112,12 @@ def test_invalid_configs_rejected(case, needle):
     elif case == "wsum":
         x, w = quadrature.full_line_grid(4)
         grid = [(x, w * 1.001)] * 2
+    elif case == "shakhov_no_tau":
+        kw["prandtl"] = 2.0 / 3.0
+    elif case == "shakhov_rows":
+        kw.update(prandtl=2.0 / 3.0, tau_feedback=True, schedule="rows")
+    elif case == "prandtl_neg":
+        kw.update(prandtl=-0.5, tau_feedback=True)
     elif case == "tau2d_wide":
         kw["tau_feedback"] = True  # psi doubles the 576 velocities of an octant: over 1024
         nv = [48, 48]

@@ -25,11 +25,12 @@ def rel(a, b):
 
 
 def pair(mask, nv, kn, precision="fp64", lateral="specular", tile=None, jump=1.0, tau=False, threads=16,
-         rule=1, schedule="auto"):
+         rule=1, schedule="auto", prandtl=None):
     o = OracleSolver(mask, nv, kn, jump=jump, lateral_periodic=(lateral == "periodic"),
-                     tau_feedback=tau, threads=threads, stencil_rule=rule)
+                     tau_feedback=tau, threads=threads, stencil_rule=rule, prandtl=prandtl)
     s = poredvm.Solver(mask, nv, kn, jump=jump, precision=precision, lateral=lateral,
-                       tau_feedback=tau, tile=tile, grid=o.grid, stencil_rule=rule, schedule=schedule)
+                       tau_feedback=tau, tile=tile, grid=o.grid, stencil_rule=rule, schedule=schedule,
+                       prandtl=prandtl)
     return o, s
 
 
@@ -297,6 +298,44 @@ def test_tau_feedback_2d_row_pipeline_equals_tile_diagonals_bitwise(nv, tile):
         s.close()
     for a, b in zip(*out):
         assert np.array_equal(a, b)
+
+
+@pytest.mark.parametrize("shape,nv,kn,tile,precision,pr", [
+    ((8, 9, 10), [4, 4, 4], 0.9, None, "fp64", 2.0 / 3.0),
+    ((7, 10, 12), [6, 6, 6], 0.3, (8, 8, 4), "fp64", 0.4),
+    ((9, 8, 11), [8, 8, 8], 1.7, (4, 4, 3), "fp32", 2.0 / 3.0),
+    ((37, 29), [8, 8], 0.7, (4, 4), "fp64", 2.0 / 3.0),
+    ((33, 26), [24, 24], 0.3, (8, 8), "fp64", 0.5),
+    ((45, 40), [16, 16], 1.5, (4, 4), "fp32", 2.0 / 3.0),
+])
+def test_shakhov_matches_oracle(shape, nv, kn, tile, precision, pr):
+    """Shakhov model (heat flux fed back) on random geometries, 3D and 2D
+    (with psi); the automatic schedule is the tile-diagonal one."""
+    m = random_mask(shape, 0.25, sum(shape) + 5)
+    o, s = pair(m, nv, kn, precision=precision, tile=tile, tau=True, prandtl=pr)
+    assert s.schedule == "diagonals"
+    o.iterate(10)
+    s.iterate(10)
+    compare(o, s, RTOL64 if precision == "fp64" else RTOL32)
+    # the heat-flux term changes the iterate (it is not a no-op)
+    b = poredvm.Solver(m, nv, kn, precision=precision, tile=tile, tau_feedback=True, grid=o.grid)
+    b.iterate(10)
+    assert np.abs(b.moments()[3] - s.moments()[3]).max() > 1e-6 * np.abs(s.moments()[3]).max()
+    b.close()
+
+
+def test_shakhov_checkpoint_resume_is_bitwise():
+    m = random_mask((30, 28), 0.3, 17)
+    s = poredvm.Solver(m, [8, 8], 0.5, tau_feedback=True, prandtl=2.0 / 3.0)
+    s.iterate(7)
+    st = s.get_state()
+    s.iterate(6)
+    a = s.moments()
+    t = poredvm.Solver(m, [8, 8], 0.5, tau_feedback=True, prandtl=2.0 / 3.0)
+    t.set_state(st)
+    t.iterate(6)
+    for x, y in zip(a, t.moments()):
+        assert np.array_equal(x, y)
 
 
 def test_paper_stop_mode_matches_oracle():
