@@ -46,6 +46,12 @@
 //   that the collision relaxes q at the rate Pr nu instead of nu; reduced
 //   over v3 in 2D this is (4/5)(1 - Pr) q.v (v1^2 + v2^2 - 2) for phi and
 //   (2/5)(1 - Pr) q.v for psi;
+//   optional Maxwell walls with accommodation alpha < 1 (Eq.
+//   diffusive-specular_BC): the wall value becomes alpha times the diffuse
+//   value plus (1 - alpha) times the previous iteration's value at the fluid
+//   node next to the wall (the node itself, as walls enter only through the
+//   first-order stencil of stencil_rule 1) for the velocity mirrored in the
+//   wall normal e_j; the wall density keeps its zero-mass-flux value;
 //   residual r = max|u^l - u^(l-1)| / max|u^l| over fluid cells and components.
 //
 // Velocity order inside this file: k = a + n1 (b + n2 c) over the tensor grid
@@ -78,6 +84,8 @@ struct Oracle {
   double kn = 1.0, nu = 0.0, J = 1.0;
   int lateral_periodic = 0, tau_fb = 0, nthreads = 1;
   double prandtl = 0.0;  // > 0: Shakhov model with this Prandtl number (needs tau_fb)
+  double alpha = 1.0;    // wall accommodation; < 1 keeps the previous iteration's h (and psi)
+  std::vector<double> hold, psiold;  // [k * N + c] when alpha < 1
   double shakhov_coef() const { return prandtl > 0 ? 0.8 * (1.0 - prandtl) : 0.0; }
   // 0: first order iff the first upstream image is solid (a solid second
   //    upstream image enters the second-order stencil with its wall value);
@@ -144,9 +152,17 @@ double upstream_value(const Oracle &o, const int x[3], int j, int m, int k,
   const long cy = o.idx(yr[0], yr[1], yr[2]);
   if (o.solid[cy]) {
     *is_solid = 1;
-    if (psi) return 0.0;  // the wall emits a Maxwellian in v3: psi = 0
+    // specular part (alpha < 1): the previous iteration's value at the fluid
+    // node x_f = y + s e_j (= x, m = 1) for the velocity mirrored in e_j
+    // [Eq. diffusive-specular_BC]
+    double spec = 0.0;
+    if (o.alpha < 1.0) {
+      const int km = o.mirror[j][k];
+      spec = (1.0 - o.alpha) * (psi ? o.psiold : o.hold)[(size_t)km * o.N + o.idx(x[0], x[1], x[2])];
+    }
+    if (psi) return spec;  // the diffuse wall emits a Maxwellian in v3: psi = 0
     // wall value: wall density of the solid seen along s e_j, from the fluid
-    // node x_f = y + s e_j next to it. [Eq. wall_density, alpha = 1]
+    // node x_f = y + s e_j next to it. [Eq. wall_density]
     int f[3] = {y[0], y[1], y[2]};
     f[j] += s;
     int fr[3] = {f[0], f[1], f[2]};
@@ -157,7 +173,7 @@ double upstream_value(const Oracle &o, const int x[3], int j, int m, int k,
     int incoming_pos = (s < 0);            // v_j > 0 is incoming when s = -1
     if (fi.mirrored) incoming_pos = !incoming_pos;
     const double flux = o.phi[j][incoming_pos ? 0 : 1][cf];
-    return flux / o.D[j] + fi.jump * o.J;
+    return o.alpha * (flux / o.D[j] + fi.jump * o.J) + spec;
   }
   *is_solid = 0;
   if (!ghost) return hk[cy];
@@ -314,6 +330,19 @@ void *orc_create(int dim, const int *n, const uint8_t *solid, const int *nv,
 
 void orc_destroy(void *h) { delete static_cast<Oracle *>(h); }
 
+// Maxwell walls with accommodation alpha in (0, 1] (1 = diffuse); needs
+// stencil_rule 1. Call before orc_set_initial. Returns 0, or -1.
+int orc_set_accommodation(void *hh, double alpha) {
+  Oracle &o = *static_cast<Oracle *>(hh);
+  if (!(alpha > 0 && alpha <= 1) || (alpha < 1 && o.stencil_rule != 1)) return -1;
+  o.alpha = alpha;
+  if (alpha < 1) {
+    o.hold.assign((size_t)o.N * o.K, 0.0);
+    if (o.has_psi()) o.psiold.assign((size_t)o.N * o.K, 0.0);
+  }
+  return 0;
+}
+
 // Switch to the Shakhov model with Prandtl number pr (0 < pr; pr = 1 is
 // BGK); needs tau_feedback. Call before orc_set_initial. Returns 0, or -1.
 int orc_set_shakhov(void *hh, double pr) {
@@ -363,6 +392,12 @@ void orc_set_initial(void *hh, const double *rho, const double *u, const double 
         }
       }
     }
+  if (o.alpha < 1.0)
+    for (int k = 0; k < o.K; ++k)
+      for (long c = 0; c < o.N; ++c) {
+        o.hold[(size_t)k * o.N + c] = o.solid[c] ? 0.0 : source(o, c, k);
+        if (o.has_psi()) o.psiold[(size_t)k * o.N + c] = o.solid[c] ? 0.0 : psi_source(o, c, k);
+      }
   o.iters_done = 0;
   o.kring.clear();
 }
@@ -382,6 +417,7 @@ int orc_iterate(void *hh, long iters, double tol, int stop_mode, double *stats) 
   std::vector<std::vector<double>> hk(T, std::vector<double>(N));
   std::vector<std::vector<double>> pk(T, std::vector<double>(o.has_psi() ? N : 0));
   std::vector<double> hbc_new[3][4], psibc_new[3][4];
+  std::vector<double> hold_new(o.hold.size()), psiold_new(o.psiold.size());
   for (int a = 0; a < o.dim; ++a)
     for (int s = 0; s < 4; ++s) {
       hbc_new[a][s].assign(o.hbc[a][s].size(), 0.0);
@@ -404,6 +440,10 @@ int orc_iterate(void *hh, long iters, double tol, int stop_mode, double *stats) 
       sweep_velocity(o, k, h);
       double *ps = o.has_psi() ? pk[t].data() : nullptr;
       if (ps) sweep_velocity(o, k, ps, true);
+      if (o.alpha < 1.0) {  // the whole iterate, for the next iteration's specular wall values
+        std::copy(h, h + N, hold_new.begin() + (size_t)k * N);
+        if (ps) std::copy(ps, ps + N, psiold_new.begin() + (size_t)k * N);
+      }
       // step (iii): quadrature moments and half-fluxes [Eq. perturbed_quantities]
       double *A = acc[t].data();
       double v2 = 0;
@@ -467,6 +507,8 @@ int orc_iterate(void *hh, long iters, double tol, int stop_mode, double *stats) 
         o.hbc[a][s].swap(hbc_new[a][s]);
         if (o.has_psi()) o.psibc[a][s].swap(psibc_new[a][s]);
       }
+    o.hold.swap(hold_new);
+    o.psiold.swap(psiold_new);
     ++o.iters_done;
     ++done;
     // steps (iv)-(v): G_p as the mean of u1 over all cells (solid = 0), k, r, Err

@@ -42,6 +42,8 @@ def _load():
         lib.orc_destroy.argtypes = [vp]
         lib.orc_num_velocities.argtypes = [vp]
         lib.orc_set_initial.argtypes = [vp, dp, dp, dp]
+        lib.orc_set_accommodation.restype = ctypes.c_int
+        lib.orc_set_accommodation.argtypes = [vp, ctypes.c_double]
         lib.orc_set_shakhov.restype = ctypes.c_int
         lib.orc_set_shakhov.argtypes = [vp, ctypes.c_double]
         lib.orc_iterate.argtypes = [vp, ctypes.c_long, ctypes.c_double, ctypes.c_int, dp]
@@ -72,10 +74,12 @@ class OracleSolver:
     stencil_rule 1 (default): first-order upwind stencil along an axis when
     either upstream image is solid; 0: only when the first one is.
     prandtl (with tau_feedback): Shakhov model with this Prandtl number.
+    accommodation: Maxwell walls, the diffuse fraction alpha in (0, 1].
     """
 
     def __init__(self, solid, nv, kn, jump=1.0, lateral_periodic=False,
-                 tau_feedback=False, threads=None, grid=None, stencil_rule=1, prandtl=None):
+                 tau_feedback=False, threads=None, grid=None, stencil_rule=1, prandtl=None,
+                 accommodation=1.0):
         lib = _load()
         solid = np.ascontiguousarray(solid, dtype=np.uint8)
         self.dim = solid.ndim
@@ -106,6 +110,10 @@ class OracleSolver:
         self.K = lib.orc_num_velocities(self._h)
         if prandtl is not None and lib.orc_set_shakhov(self._h, float(prandtl)) != 0:
             raise ValueError("the Shakhov model needs tau_feedback and prandtl > 0")
+        if accommodation != 1.0:
+            if lib.orc_set_accommodation(self._h, float(accommodation)) != 0:
+                raise ValueError("accommodation must be in (0, 1], and below 1 needs stencil_rule 1")
+            self.set_initial()
 
     def close(self):
         if getattr(self, "_h", None):

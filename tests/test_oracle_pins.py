@@ -179,6 +179,42 @@ def test_free_molecular_channel_closed_form(n1, n2, nv):
     assert np.max(np.abs(rr[1:-1] + J * (xx - xx.mean())[None, :])) <= 1e-12
 
 
+@pytest.mark.parametrize("n1,n2,nv,alpha", [(8, 10, 8, 0.8), (8, 10, 8, 0.3), (6, 12, 16, 0.5)])
+def test_free_molecular_channel_maxwell_walls_closed_form(n1, n2, nv, alpha):
+    """Kn = inf in a plane channel with Maxwell walls (Eq. diffusive-specular_BC):
+    a molecule leaving a wall carries alpha times the diffuse value plus
+    (1 - alpha) times the value of the mirrored velocity at the fluid node
+    next to the wall. With h = -J x1 + J (v1/v2)(x2 - x2_wall(v)) + B(v) the
+    two walls give B = rho_w + ((1 - alpha)/alpha) J (v1/v2) (N2 - 2) dx, so
+    u1 = J dx A [(N2 - 1) + 2 ((1 - alpha)/alpha)(N2 - 2)] with
+    A = sum_{v2>0} W v1^2 / v2, uniform over the fluid (alpha = 1: the diffuse
+    closed form above)."""
+    J = 1.0
+    m = geometry.plane_channel(n1, n2)
+    o = OracleSolver(m, [nv, nv], np.inf, jump=J, threads=4, accommodation=alpha)
+    assert o.iterate(400000, 1e-14)["converged"]
+    _, u, _, _ = o.moments()
+    x, w = quadrature.full_line_grid(nv)
+    A = 0.5 * np.sum(w[x > 0] / x[x > 0])
+    u1 = J / n1 * A * ((n2 - 1) + 2 * (1 - alpha) / alpha * (n2 - 2))
+    fl = m == 0
+    assert np.max(np.abs(u[0][fl] - u1)) <= 1e-10 * u1
+    assert np.max(np.abs(u[1][fl])) <= 1e-12 * u1
+
+
+def test_maxwell_walls_alpha_one_is_diffuse_and_rule_0_rejected():
+    m = _random_mask((10, 12), 0.3, 3)
+    a = OracleSolver(m, [6, 6], 0.5, threads=2)
+    b = OracleSolver(m, [6, 6], 0.5, threads=2, accommodation=1.0)
+    a.iterate(30)
+    b.iterate(30)
+    assert np.array_equal(a.moments()[1], b.moments()[1])
+    with pytest.raises(ValueError):
+        OracleSolver(m, [6, 6], 0.5, stencil_rule=0, accommodation=0.5)
+    with pytest.raises(ValueError):
+        OracleSolver(m, [6, 6], 0.5, accommodation=0.0)
+
+
 def test_finite_kn_channel_translation_invariant_and_direct():
     m = geometry.plane_channel(6, 9)
     o = OracleSolver(m, [6, 6], 0.3, threads=4)

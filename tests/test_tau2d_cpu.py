@@ -36,14 +36,18 @@ CASES = [
 
 
 @pytest.mark.parametrize("case", [0, 1])
-@pytest.mark.parametrize("tau,pr", [(False, None), (True, None), (True, 2.0 / 3.0)])
-def test_2d_psi_equals_two_layer_extrusion(case, tau, pr):
+@pytest.mark.parametrize("tau,pr,alpha", [(False, None, 1.0), (True, None, 1.0), (True, 2.0 / 3.0, 1.0),
+                                          (False, None, 0.6), (True, None, 0.6)])
+def test_2d_psi_equals_two_layer_extrusion(case, tau, pr, alpha):
     """pr: the Shakhov model, whose heat-flux source reduces to
-    (4/5)(1 - Pr) q.v (v1^2 + v2^2 - 2) for phi and (2/5)(1 - Pr) q.v for psi."""
+    (4/5)(1 - Pr) q.v (v1^2 + v2^2 - 2) for phi and (2/5)(1 - Pr) q.v for psi.
+    alpha < 1: Maxwell walls, whose specular part reflects psi as well (the
+    extruded solid has no walls normal to x3)."""
     m, kn = CASES[case]
     nv = [8, 8]
-    a = OracleSolver(m, nv, kn, tau_feedback=tau, threads=4, prandtl=pr)
-    b = OracleSolver(np.stack([m, m]), nv + [6], kn, tau_feedback=tau, threads=8, prandtl=pr)
+    a = OracleSolver(m, nv, kn, tau_feedback=tau, threads=4, prandtl=pr, accommodation=alpha)
+    b = OracleSolver(np.stack([m, m]), nv + [6], kn, tau_feedback=tau, threads=8, prandtl=pr,
+                     accommodation=alpha)
     ra = a.iterate(40000, 1e-13)
     rb = b.iterate(40000, 1e-13)
     assert ra["converged"] and rb["converged"]
@@ -60,7 +64,7 @@ def test_2d_psi_equals_two_layer_extrusion(case, tau, pr):
     assert np.abs(q - q3[:2, 0]).max() <= tol
     if tau:
         # the feedback (and the Shakhov term) matters at this tolerance
-        ref = OracleSolver(m, nv, kn, tau_feedback=pr is not None, threads=4)
+        ref = OracleSolver(m, nv, kn, tau_feedback=pr is not None, threads=4, accommodation=alpha)
         ref.iterate(40000, 1e-13)
         _, _, ti, qi = ref.moments()
         assert np.abs(t - ti).max() > 1e3 * tol
