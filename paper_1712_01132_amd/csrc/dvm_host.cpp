@@ -192,6 +192,7 @@ struct Problem {
   std::vector<uint32_t> flags;
   int psi = 0;       // 2D with tau feedback: octant slots [Ko/2, Ko) hold psi
   double prandtl = 0;  // > 0: Shakhov model
+  double spec = 0;     // > 0: Maxwell walls, 1 - alpha
   std::vector<double> absv, wq, vsqm, rden;   // host FP64 tables, [rows][Ko_pad]
   std::vector<int32_t> diag_tiles, diag_off;
   std::vector<int32_t> fluid_idx;  // fluid voxels in index order
@@ -232,6 +233,11 @@ int validate_and_build(const pdvm_config *cfg, Problem &P, std::string &err) {
   if (!(cfg->prandtl >= 0) || !std::isfinite(cfg->prandtl)) { err = "prandtl must be >= 0 and finite"; return PDVM_E_INVAL; }
   if (cfg->prandtl > 0 && !P.tau_fb) { err = "the Shakhov model (prandtl > 0) needs tau_feedback"; return PDVM_E_INVAL; }
   P.prandtl = cfg->prandtl;
+  if (!(cfg->specular_fraction >= 0 && cfg->specular_fraction < 1)) {
+    err = "specular_fraction (1 - alpha) must be in [0, 1)";
+    return PDVM_E_INVAL;
+  }
+  P.spec = cfg->specular_fraction;
   P.check_every = cfg->check_every > 0 ? cfg->check_every : 16;
   if (cfg->sweep_schedule < 0 || cfg->sweep_schedule > 3) { err = "sweep_schedule must be 0..3"; return PDVM_E_INVAL; }
   P.schedule = cfg->sweep_schedule;
@@ -243,7 +249,12 @@ int validate_and_build(const pdvm_config *cfg, Problem &P, std::string &err) {
     err = "the Shakhov model is swept by the tile-diagonal schedule only";
     return PDVM_E_UNSUPPORTED;
   }
+  if ((P.schedule == PDVM_SCHEDULE_ROWS || P.schedule == PDVM_SCHEDULE_ROWS_AGENT) && P.spec > 0) {
+    err = "Maxwell walls (specular_fraction > 0) are swept by the tile-diagonal schedule only";
+    return PDVM_E_UNSUPPORTED;
+  }
   if (cfg->stencil_rule != 0 && cfg->stencil_rule != 1) { err = "stencil_rule must be 0 or 1"; return PDVM_E_INVAL; }
+  if (P.spec > 0 && cfg->stencil_rule != 1) { err = "Maxwell walls (specular_fraction > 0) need stencil_rule 1"; return PDVM_E_UNSUPPORTED; }
   P.stencil_rule = cfg->stencil_rule;
 
   // velocity grid: per axis, symmetric, even, no zero node, weights > 0, sum 1
@@ -432,7 +443,8 @@ int validate_and_build(const pdvm_config *cfg, Problem &P, std::string &err) {
   // moment kernel: about 16 fluid voxels per wavefront, at most one round of 4096 wavefronts
   P.mom_blocks = (int)std::max<int64_t>(1, std::min<int64_t>((P.fluid + 63) / 64, 1024));
   uint64_t fp = 1469598103934665603ull;
-  const double scal[6] = {P.kn, P.jump, (double)P.lateral_periodic, (double)P.tau_fb, (double)P.stencil_rule, P.prandtl};
+  const double scal[7] = {P.kn, P.jump, (double)P.lateral_periodic, (double)P.tau_fb, (double)P.stencil_rule, P.prandtl,
+                          P.spec};
   fp = fnv1a(fp, scal, sizeof(scal));
   fp = fnv1a(fp, P.n, sizeof(P.n));
   fp = fnv1a(fp, P.hv, sizeof(P.hv));
@@ -629,6 +641,9 @@ int setup_problem(pdvm_solver *s, int i) {
   g.psi = P.psi;
   g.shakhov = P.prandtl > 0;
   g.sh_coef = P.prandtl > 0 ? 0.8 * (1.0 - P.prandtl) : 0.0;
+  g.maxwell = P.spec > 0;
+  g.spec = T(P.spec);
+  g.alpha = T(1.0 - P.spec);
   g.rden = (const T *)(b + L.rden);
   g.wq = (const double *)(b + L.wq);
   for (int k = 0; k < 2; ++k) {
@@ -735,6 +750,7 @@ int finalize_batch(pdvm_solver *s) {
   B.tau_fb = P0.tau_fb;
   B.psi = P0.psi;
   B.shakhov = P0.prandtl > 0;
+  B.maxwell = P0.spec > 0;
   B.ndiag_max = ndmax;
   B.d_geo = (const Geo<T> *)geo;
   B.d_item_off = (const int *)item;
@@ -867,7 +883,7 @@ int create_common(const pdvm_config *cfgs, int n, void *dev_workspace, size_t ws
     }
     const Problem &A = s->P[0], &B = s->P[i];
     if (B.precision != A.precision || !same_velocity_grid(A, B) || B.stencil_rule != A.stencil_rule ||
-        B.tau_fb != A.tau_fb || (B.prandtl > 0) != (A.prandtl > 0)) {
+        B.tau_fb != A.tau_fb || (B.prandtl > 0) != (A.prandtl > 0) || (B.spec > 0) != (A.spec > 0)) {
       set_thread_error("config %d: a batch shares dimension, precision, velocity grid, stencil rule, tau feedback "
                        "and collision model", i);
       delete s;
@@ -924,7 +940,7 @@ int create_common(const pdvm_config *cfgs, int n, void *dev_workspace, size_t ws
   // automatic: the row pipeline for a single 2D problem; a batch fills the
   // machine better with per-diagonal launches (measured)
   s->rows = P0.dim == 2 && (P0.schedule == PDVM_SCHEDULE_ROWS || P0.schedule == PDVM_SCHEDULE_ROWS_AGENT ||
-                            (P0.schedule == PDVM_SCHEDULE_AUTO && n == 1 && !(P0.prandtl > 0)));
+                            (P0.schedule == PDVM_SCHEDULE_AUTO && n == 1 && !(P0.prandtl > 0) && !(P0.spec > 0)));
   if (s->rows) {
     // the row pipeline stores a tile through 32-bit byte offsets from its
     // lowest-addressed voxel
@@ -1085,7 +1101,8 @@ int get_flux_one(pdvm_solver *s, int i, double *gp, double *k, double *gp_sectio
 }
 
 // checkpoint layout: header, Ctl, then the parity-current rho, u, src, srct,
-// (Shakhov: srcq,) wall, then the boundary layers of h.
+// (Shakhov: srcq,) wall, then the boundary layers of h (Maxwell walls: all of
+// h, as their specular part reads the previous iterate next to every wall).
 struct StateHeader {
   uint64_t magic;
   int32_t dim, n0, n1, n2, Kpad, precision;
@@ -1114,6 +1131,7 @@ size_t state_bytes(const Problem &P, int precision) {
   const size_t kp = (size_t)kpad_of(P, precision);
   const size_t nq = P.prandtl > 0 ? 4 * N : 0;  // srcq
   size_t b = sizeof(StateHeader) + sizeof(Ctl) + N * 8 + 3 * N * 8 + N * kSrcStride * es + N * es + nq * es + N * 6 * es;
+  if (P.spec > 0) return b + N * kp * es;
   for (int a = 0; a < P.dim; ++a) b += face_layers(P, a).size() * (N / P.n[a]) * kp * es;
   return b;
 }
@@ -1132,13 +1150,14 @@ void convert_sections(const Problem &P, const char *in, char *out, int64_t kin, 
   a += flat;
   b += flat;
   const int64_t kin_o = kin >> P.dim, kout_o = kout >> P.dim;
-  for (int ax = 0; ax < P.dim; ++ax) {
-    const size_t cells = face_layers(P, ax).size() * (N / P.n[ax]);
-    for (size_t c = 0; c < cells; ++c, a += kin, b += kout) {
-      for (int64_t k = 0; k < kout; ++k) b[k] = D(0);
-      for (int o = 0; o < (1 << P.dim); ++o)
-        for (int q = 0; q < P.Ko; ++q) b[o * kout_o + q] = (D)a[o * kin_o + q];
-    }
+  size_t cells = 0;
+  if (P.spec > 0) cells = N;
+  else
+    for (int ax = 0; ax < P.dim; ++ax) cells += face_layers(P, ax).size() * (N / P.n[ax]);
+  for (size_t c = 0; c < cells; ++c, a += kin, b += kout) {
+    for (int64_t k = 0; k < kout; ++k) b[k] = D(0);
+    for (int o = 0; o < (1 << P.dim); ++o)
+      for (int q = 0; q < P.Ko; ++q) b[o * kout_o + q] = (D)a[o * kin_o + q];
   }
 }
 
@@ -1179,6 +1198,11 @@ int state_io(pdvm_solver *s, int i, char *buf, bool save) {
   if ((rc = xfer(g.srct[par], N * sizeof(T)))) return rc;
   if (P.prandtl > 0 && (rc = xfer(g.srcq[par], 4 * N * sizeof(T)))) return rc;
   if ((rc = xfer(g.wall[par], N * 6 * sizeof(T)))) return rc;
+  if (P.spec > 0) {
+    if ((rc = xfer(g.h[par], N * (size_t)P.Kpad * sizeof(T)))) return rc;
+    HIPCHK(s, hipStreamSynchronize(s->stream));
+    return PDVM_OK;
+  }
   T *stage = g.h[par ^ 1];  // free between iterations
   for (int a = 0; a < P.dim; ++a)
     for (int r : face_layers(P, a)) {

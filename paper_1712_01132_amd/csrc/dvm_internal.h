@@ -55,6 +55,8 @@ struct Geo {
   int32_t psi;             // 2D with tau_fb: octant slots [Ko/2, Ko) hold psi of velocity q - Ko/2
   int32_t shakhov;         // the heat flux is fed back (Shakhov model)
   double sh_coef;          // (4/5)(1 - Pr)
+  int32_t maxwell;         // Maxwell walls: a wall value is alpha (diffuse) + spec (mirrored previous h)
+  T spec, alpha;           // 1 - alpha, alpha
   int32_t y2wall;          // stencil rule 0: a solid second image enters the second-order stencil
   T jump;
   double nu, D[3];
@@ -110,7 +112,7 @@ constexpr int kTileEdge[2] = {4, 8};
 // block offsets; a single problem is a batch of one.
 template <typename T>
 struct Batch {
-  int nprob = 0, dim = 2, Ko = 0, tile_edge = 8, y2wall = 0, tau_fb = 0, psi = 0, shakhov = 0, ndiag_max = 0;
+  int nprob = 0, dim = 2, Ko = 0, tile_edge = 8, y2wall = 0, tau_fb = 0, psi = 0, shakhov = 0, maxwell = 0, ndiag_max = 0;
   const Geo<T> *d_geo = nullptr;
   const int *d_item_off = nullptr;   // [ndiag_max][nprob + 1] sweep blocks per diagonal
   const int *d_blk_off = nullptr;    // [nprob + 1] moment-kernel blocks

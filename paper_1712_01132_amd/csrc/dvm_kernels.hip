@@ -160,11 +160,15 @@ __device__ __forceinline__ int owner_of(const int *off, int nprob, int b) {
 }
 
 // EXT bit 0 (PSI, 2D): slots of h and of psi; bit 1 (SH): the Shakhov
-// heat-flux source, whose per-voxel values nu (4/5)(1 - Pr) q_j end the record.
+// heat-flux source, whose per-voxel values nu (4/5)(1 - Pr) q_j end the record;
+// bit 2 (MW): Maxwell walls. A voxel whose axis-j stencil meets a wall (code
+// bit 4 + j) adds a_j (1 - alpha) times its own previous-iteration value of
+// the velocity mirrored in e_j; the record's wall term is alpha rho_w.
 template <typename T, int DIM, int TT, bool Y2WALL, int EXT>
 __global__ void __launch_bounds__(kWave)
     sweep_kernel(const Geo<T> *__restrict__ G, const int *__restrict__ item_off, int nprob, int diag) {
-  constexpr bool PSI = (EXT & 1) != 0, SH = (EXT & 2) != 0;
+  constexpr bool PSI = (EXT & 1) != 0, SH = (EXT & 2) != 0, MW = (EXT & 4) != 0;
+  static_assert(!(MW && Y2WALL), "Maxwell walls need stencil rule 1");
   constexpr int NC = TT * TT;
   constexpr int RW = 5 + 3 * DIM + (SH ? DIM : 0);  // record: src (4), nu tau, per axis (c1, c2, w), [q]
   __shared__ T rd_lds[8 * kWave];
@@ -220,8 +224,9 @@ __global__ void __launch_bounds__(kWave)
   const T ph = PSI ? as_global(G_.phm)[qq] : T(1);
   Dom<T> dv = dm;  // as dm, with the jump this lane's values take
   if (PSI) dv.jump = dm.jump * ph;
-  T vv[3] = {T(0), T(0), T(0)}, aa[3] = {T(0), T(0), T(0)}, cq[3] = {T(0), T(0), T(0)};
+  T vv[3] = {T(0), T(0), T(0)}, aa[3] = {T(0), T(0), T(0)}, cq[3] = {T(0), T(0), T(0)}, am[3] = {T(0), T(0), T(0)};
   const T qs = SH ? as_global(G_.qsf)[qq] : T(0);  // the Shakhov source's q.v factor
+  const T spec = G_.spec, alpha = G_.alpha;
 #pragma unroll
   for (int j = 0; j < DIM; ++j) {
     const T a = absv[j * Ko_pad + qq];
@@ -229,6 +234,7 @@ __global__ void __launch_bounds__(kWave)
     vv[j] = s[j] > 0 ? av : -av;
     aa[j] = avv[j * Ko_pad + qq];
     if (SH) cq[j] = (s[j] > 0 ? a : -a) * qs;
+    if (MW) am[j] = aa[j] * spec;
   }
 #pragma unroll
   for (int c = 0; c < (1 << DIM); ++c) rd_lds[c * kWave + lane] = rden[c * Ko_pad + qq];
@@ -328,7 +334,7 @@ __global__ void __launch_bounds__(kWave)
             const bool first = fj & 1u, y1s = fj & 2u, y2s = fj & 4u;
             T c1 = first ? (y1s ? T(0) : T(1)) : T(2);
             T c2 = first ? T(0) : T(-0.5);
-            T w = (first && y1s) ? wv[j] : T(0);
+            T w = (first && y1s) ? (MW ? alpha * wv[j] : wv[j]) : T(0);
             if (Y2WALL && !first && y2s) {
               c2 = T(0);
               w = T(-0.5) * wall_at_y1(dm, wall, j, s[j], pin[j], x, y, z);
@@ -337,6 +343,7 @@ __global__ void __launch_bounds__(kWave)
             rp[6 + 3 * j] = c2;
             rp[7 + 3 * j] = w;
             code |= (first ? 1u : 0u) << j;
+            if (MW && first && y1s) code |= 16u << j;
           }
         }
       }
@@ -395,6 +402,13 @@ __global__ void __launch_bounds__(kWave)
         if (SH) {
 #pragma unroll
           for (int j = 0; j < DIM; ++j) num = fma(rp[5 + 3 * DIM + j], cq[j], num);
+        }
+        if (MW) {
+          // the voxel's own previous iterate at the mirrored velocity (a uniform branch)
+          const gptr<const T> hv_prev = hp + ((hrow[r] + icol[i]) - hc) - kofs;
+#pragma unroll
+          for (int j = 0; j < DIM; ++j)
+            if (code & (16u << j)) num = fma(am[j], hv_prev[kmir[j]], num);
         }
         const T x1a = i >= 1 ? D1[r] : L1[r];
         const T x1b = i >= 2 ? D2[r] : (i == 1 ? L1[r] : L2[r]);
@@ -1296,7 +1310,21 @@ void launch_sweep_rule(const Batch<T> &B, int diag, hipStream_t st) {
 #define PDVM_SWEEP_T(D, E)              \
   if (B.tile_edge <= 4) PDVM_SWEEP_E(D, 4, E); \
   else PDVM_SWEEP_E(D, 8, E)
-  // EXT: bit 0 psi (2D with tau fed back), bit 1 Shakhov
+  // EXT: bit 0 psi (2D with tau fed back), bit 1 Shakhov, bit 2 Maxwell walls
+  // (stencil rule 1 only, so never with Y2WALL)
+  if constexpr (!Y2WALL) {
+    if (B.maxwell) {
+      if (B.dim == 2) {
+        if (B.shakhov) { PDVM_SWEEP_T(2, 7); }
+        else if (B.psi) { PDVM_SWEEP_T(2, 5); }
+        else { PDVM_SWEEP_T(2, 4); }
+      } else {
+        if (B.shakhov) { PDVM_SWEEP_T(3, 6); }
+        else { PDVM_SWEEP_T(3, 4); }
+      }
+      return;
+    }
+  }
   if (B.dim == 2) {
     if (B.shakhov) { PDVM_SWEEP_T(2, 3); }
     else if (B.psi) { PDVM_SWEEP_T(2, 1); }

@@ -42,6 +42,7 @@ class PdvmConfig(ctypes.Structure):
         ("stencil_rule", ctypes.c_int32),
         ("sweep_schedule", ctypes.c_int32),
         ("prandtl", ctypes.c_double),
+        ("specular_fraction", ctypes.c_double),
     ]
 
 
@@ -151,9 +152,10 @@ def velocity_grid(n_total):
 
 def make_config(solid, nv, kn, jump=1.0, precision="fp64", lateral="specular",
                 tau_feedback=False, tile=None, check_every=16, grid=None, stencil_rule=1, schedule="auto",
-                prandtl=None):
+                prandtl=None, accommodation=1.0):
     """Build a PdvmConfig; returns (config, keepalive) -- keep both alive.
-    prandtl (with tau_feedback): Shakhov model with this Prandtl number."""
+    prandtl (with tau_feedback): Shakhov model with this Prandtl number.
+    accommodation: Maxwell walls, the diffuse fraction alpha in (0, 1]."""
     solid = np.ascontiguousarray(solid, dtype=np.uint8)
     dim = solid.ndim
     if dim not in (2, 3):
@@ -181,6 +183,7 @@ def make_config(solid, nv, kn, jump=1.0, precision="fp64", lateral="specular",
     cfg.stencil_rule = int(stencil_rule)
     cfg.sweep_schedule = SCHEDULES[schedule]
     cfg.prandtl = 0.0 if prandtl is None else float(prandtl)
+    cfg.specular_fraction = 1.0 - float(accommodation)
     return cfg, (solid, grid)
 
 
@@ -193,7 +196,7 @@ class Solver:
 
     def __init__(self, solid, nv, kn, jump=1.0, precision="fp64", lateral="specular",
                  tau_feedback=False, tile=None, check_every=16, grid=None, device=None,
-                 stencil_rule=1, schedule="auto", prandtl=None):
+                 stencil_rule=1, schedule="auto", prandtl=None, accommodation=1.0):
         import torch
 
         lib = load()
@@ -202,7 +205,7 @@ class Solver:
         self.N = int(np.prod(self.shape))
         self.cfg, self._keep = make_config(solid, nv, kn, jump, precision, lateral,
                                            tau_feedback, tile, check_every, grid, stencil_rule, schedule,
-                                           prandtl)
+                                           prandtl, accommodation)
         nbytes = lib.pdvm_workspace_bytes(ctypes.byref(self.cfg))
         if nbytes == 0:
             raise PdvmError(PDVM_E_INVAL, _err())

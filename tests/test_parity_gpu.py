@@ -25,12 +25,12 @@ def rel(a, b):
 
 
 def pair(mask, nv, kn, precision="fp64", lateral="specular", tile=None, jump=1.0, tau=False, threads=16,
-         rule=1, schedule="auto", prandtl=None):
+         rule=1, schedule="auto", prandtl=None, alpha=1.0):
     o = OracleSolver(mask, nv, kn, jump=jump, lateral_periodic=(lateral == "periodic"),
-                     tau_feedback=tau, threads=threads, stencil_rule=rule, prandtl=prandtl)
+                     tau_feedback=tau, threads=threads, stencil_rule=rule, prandtl=prandtl, accommodation=alpha)
     s = poredvm.Solver(mask, nv, kn, jump=jump, precision=precision, lateral=lateral,
                        tau_feedback=tau, tile=tile, grid=o.grid, stencil_rule=rule, schedule=schedule,
-                       prandtl=prandtl)
+                       prandtl=prandtl, accommodation=alpha)
     return o, s
 
 
@@ -332,6 +332,55 @@ def test_shakhov_checkpoint_resume_is_bitwise():
     s.iterate(6)
     a = s.moments()
     t = poredvm.Solver(m, [8, 8], 0.5, tau_feedback=True, prandtl=2.0 / 3.0)
+    t.set_state(st)
+    t.iterate(6)
+    for x, y in zip(a, t.moments()):
+        assert np.array_equal(x, y)
+
+
+@pytest.mark.parametrize("shape,nv,kn,tile,precision,lateral,alpha,tau,pr", [
+    ((37, 29), [8, 8], 0.7, (4, 4), "fp64", "specular", 0.5, False, None),
+    ((33, 26), [24, 24], 0.3, (8, 8), "fp64", "periodic", 0.8, False, None),
+    ((37, 29), [8, 8], 0.7, (8, 8), "fp64", "specular", 0.6, True, None),
+    ((37, 29), [8, 8], 0.7, (4, 4), "fp64", "specular", 0.6, True, 2.0 / 3.0),
+    ((45, 40), [16, 16], 1.5, (4, 4), "fp32", "specular", 0.3, False, None),
+    ((8, 9, 10), [4, 4, 4], 0.9, None, "fp64", "specular", 0.5, False, None),
+    ((7, 10, 12), [6, 6, 6], 0.4, (4, 4, 3), "fp64", "periodic", 0.7, True, 0.5),
+])
+def test_maxwell_walls_match_oracle(shape, nv, kn, tile, precision, lateral, alpha, tau, pr):
+    """Maxwell walls (alpha < 1), alone and with tau fed back (psi) and the
+    Shakhov model, 2D and 3D, on random geometries."""
+    m = random_mask(shape, 0.25, sum(shape) + 3)
+    o, s = pair(m, nv, kn, precision=precision, lateral=lateral, tile=tile, tau=tau, prandtl=pr, alpha=alpha)
+    assert s.schedule == "diagonals"
+    o.iterate(10)
+    s.iterate(10)
+    compare(o, s, RTOL64 if precision == "fp64" else RTOL32)
+
+
+def test_maxwell_free_molecular_channel_closed_form_on_gpu():
+    """The closed form of the free-molecular channel with Maxwell walls:
+    u1 = J dx A [(N2 - 1) + 2 ((1 - alpha)/alpha)(N2 - 2)], A = sum_{v2>0} W v1^2/v2."""
+    n1, n2, nv, alpha = 8, 10, 8, 0.5
+    m = geometry.plane_channel(n1, n2)
+    s = poredvm.Solver(m, [nv, nv], math.inf, accommodation=alpha)
+    r = s.iterate(100000, 1e-14)
+    assert r["converged"]
+    x, w = poredvm.velocity_grid(nv)
+    A = 0.5 * np.sum(w[x > 0] / x[x > 0])
+    u1 = A / n1 * ((n2 - 1) + 2 * (1 - alpha) / alpha * (n2 - 2))
+    u = s.moments(diagnostics=False)[1]
+    assert np.max(np.abs(u[0][m == 0] - u1)) <= 1e-10 * u1
+
+
+def test_maxwell_checkpoint_resume_is_bitwise():
+    m = random_mask((30, 28), 0.3, 19)
+    s = poredvm.Solver(m, [8, 8], 0.5, accommodation=0.6)
+    s.iterate(7)
+    st = s.get_state()
+    s.iterate(6)
+    a = s.moments()
+    t = poredvm.Solver(m, [8, 8], 0.5, accommodation=0.6)
     t.set_state(st)
     t.iterate(6)
     for x, y in zip(a, t.moments()):
