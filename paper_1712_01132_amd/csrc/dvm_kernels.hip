@@ -489,7 +489,7 @@ __global__ void __launch_bounds__(kWave * NW)
   constexpr int RING = 2;
   __shared__ T rd_lds[4 * kWave];
   __shared__ T rec_lds[NW][NC * RW];
-  __shared__ uint32_t rcode_lds[NW][NC];
+  __shared__ __attribute__((aligned(16))) uint32_t rcode_lds[NW][NC];
   __shared__ T ring[NW > 1 ? NW - 1 : 1][RING][2 * TT][kWave];
   __shared__ int32_t made[NW], used[NW];
   const int p = nprob > 1 ? owner_of(row_off, nprob, blockIdx.x) : 0;
@@ -755,6 +755,19 @@ __global__ void __launch_bounds__(kWave * NW)
     const __amdgpu_buffer_rsrc_t tile_rsrc = __builtin_amdgcn_make_buffer_rsrc(
         (void *)(T *)(hz + (int64_t)(ylo * n0 + (s[0] > 0 ? xs : xs - (TT - 1))) * Kp), (short)0, -1, kBufferFlags);
 
+    // 4 x 4 tiles: the voxel codes and this lane's reciprocal denominators of
+    // the whole tile are read before the walk, so that no voxel waits on two
+    // chained LDS reads (code, then denominator)
+    constexpr bool PRE = TT == 4;
+    uint32_t cw[PRE ? NC : 1];
+    T rdv[PRE ? NC : 1];
+    if (PRE) {
+#pragma unroll
+      for (int k = 0; k < NC; ++k) cw[k] = __builtin_amdgcn_readfirstlane(rcode[k]);
+#pragma unroll
+      for (int k = 0; k < NC; ++k) rdv[k] = *(const T *)((const char *)rd_lane + (cw[k] & ~R_SKIP));
+    }
+
     // --- the tile's anti-diagonals (as in sweep_kernel) ---------------------
     // FULL: a whole TT x TT tile, so the columns and rows handed on are
     // compile-time ones; otherwise they are selected by the tile's extent.
@@ -780,7 +793,7 @@ __global__ void __launch_bounds__(kWave * NW)
         for (int r = 0; r < TT; ++r) {
           const int i = d - r;
           if (i < 0 || i >= TT) continue;
-          const uint32_t code = __builtin_amdgcn_readfirstlane(rcode[i + TT * r]);
+          const uint32_t code = PRE ? cw[PRE ? i + TT * r : 0] : __builtin_amdgcn_readfirstlane(rcode[i + TT * r]);
           const T *rp = rec + (i + TT * r) * RW;
           T num = fma(rp[1], vv[0], TAU ? rp[0] * ph : rp[0]);
           num = fma(rp[2], vv[1], num);
@@ -791,7 +804,7 @@ __global__ void __launch_bounds__(kWave * NW)
           const T x2b = r >= 2 ? D2[r >= 2 ? r - 2 : 0] : (r == 1 ? B1[i] : B2[i]);
           num = fma(aa[0], fma(rp[3], x1a, fma(rp[4], x1b, TAU ? rp[5] * ph : rp[5])), num);
           num = fma(aa[1], fma(rp[6], x2a, fma(rp[7], x2b, TAU ? rp[8] * ph : rp[8])), num);
-          Nw[r] = num * *(const T *)((const char *)rd_lane + (code & ~R_SKIP));
+          Nw[r] = num * (PRE ? rdv[PRE ? i + TT * r : 0] : *(const T *)((const char *)rd_lane + (code & ~R_SKIP)));
           Nc[r] = code;
           if (FULL) {
             if (i == TT - 1) out.LN1[r] = Nw[r];
@@ -960,13 +973,13 @@ __global__ void __launch_bounds__(kMomBlock)
       if (PAIR) {
 #pragma unroll
         for (int m = 0; m < NS; m += 2) {
-          const vec2_t<T> v = *(const gptr<const vec2_t<T>>)(hc + o * Ko_pad + qc[m]);
+          const vec2_t<T> v = __builtin_nontemporal_load((const gptr<const vec2_t<T>>)(hc + o * Ko_pad + qc[m]));
           hv[o][m] = v.x;
           hv[o][m + 1] = v.y;
         }
       } else {
 #pragma unroll
-        for (int m = 0; m < NS; ++m) hv[o][m] = hc[o * Ko_pad + qc[m]];
+        for (int m = 0; m < NS; ++m) hv[o][m] = __builtin_nontemporal_load(&hc[o * Ko_pad + qc[m]]);
       }
     }
   };
