@@ -70,7 +70,9 @@ def timed_updates(solver, fluid, K, steps, warmup):
 # HBM bytes per sweep launch from the rocprofv3 FETCH_SIZE / WRITE_SIZE passes
 # (scaled by a 1 GiB copy), valid only for the kernel source they were taken on
 # Key: (source hash, schedule, tile).
-TRAFFIC = {("f677f1ddb44a2dc6", "rows-xcd", (4, 4)): 525.4e6 + 841.9e6}
+TRAFFIC = {("1e582be9d473dc90", "rows-xcd", (4, 4)): 525.9e6 + 841.9e6}
+# the same for the moment kernel of that iteration (h read once, moments written)
+MOM_TRAFFIC = {("1e582be9d473dc90", "rows-xcd", (4, 4)): 879.8e6 + 12.8e6}
 
 
 def kernel_source_hash():
@@ -87,13 +89,15 @@ def roofline(tm, elem, traffic_key=None, schedule="diagonals"):
     per_launch = per_iter / tm["sweep_launches_per_iter"]
     achieved = per_launch / (tm["sweep_ms_per_launch"] * 1e-3) / 1e9
     traffic = TRAFFIC.get(traffic_key) if traffic_key else None
+    mom_traffic = MOM_TRAFFIC.get(traffic_key) if traffic_key else None
     return {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
             "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
             "kernel": "sweep_kernel" if schedule == "diagonals" else "sweep_rows_kernel",
             "bytes_per_launch": per_launch, "launch_ms": tm["sweep_ms_per_launch"],
             "launches_per_iter": tm["sweep_launches_per_iter"],
             "moments_kernel": {"bytes_per_launch": per_iter, "launch_ms": tm["moments_ms_per_launch"],
-                               "achieved_gbs": per_iter / (tm["moments_ms_per_launch"] * 1e-3) / 1e9}}
+                               "achieved_gbs": per_iter / (tm["moments_ms_per_launch"] * 1e-3) / 1e9,
+                               "traffic": mom_traffic}}
 
 
 def copy_calibration(mib):
