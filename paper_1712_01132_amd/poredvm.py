@@ -192,6 +192,9 @@ class Solver:
 
     solid: uint8 mask (1 = solid), shape (N2, N1) or (N3, N2, N1), x1 fastest.
     nv: 1D velocity counts per axis; kn: Knudsen number (L = N1 voxels).
+    tau_feedback: keep the temperature term of the source (2D: with the second
+    reduced function psi); prandtl (with tau_feedback): Shakhov model;
+    accommodation: Maxwell walls, the diffuse fraction alpha in (0, 1].
     """
 
     def __init__(self, solid, nv, kn, jump=1.0, precision="fp64", lateral="specular",
