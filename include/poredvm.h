@@ -50,7 +50,7 @@ enum {
   PDVM_E_HIP = -3,          /* a HIP runtime call failed */
   PDVM_E_NONFINITE = -4,    /* r or k became NaN/Inf; the last good state is kept */
   PDVM_E_STATE = -5,        /* checkpoint buffer of the wrong size or problem */
-  PDVM_E_UNSUPPORTED = -6   /* valid but not implemented (e.g. tau feedback in 2D) */
+  PDVM_E_UNSUPPORTED = -6   /* valid but not implemented (e.g. the row pipeline in 3D) */
 };
 
 enum { PDVM_FP64 = 0, PDVM_FP32 = 1 };                       /* sweep + h storage precision */
