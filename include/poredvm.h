@@ -104,15 +104,13 @@ typedef struct {
                                 flux q of the previous iteration (2D: reduced over v3, as
                                 for tau), so that collisions relax q at Pr nu (a kinetic
                                 model the method extends to, Sec. 1 and Sec. 2.1; Pr = 2/3
-                                for a monatomic gas). Swept by the tile-diagonal schedule
-                                (AUTO picks it; ROWS(_AGENT) is PDVM_E_UNSUPPORTED) */
+                                for a monatomic gas). Both sweep schedules carry it */
   double specular_fraction;  /* 1 - alpha of Maxwell walls (Eq. diffusive-specular_BC), in
                                 [0, 1); 0 = diffuse walls as in the paper's runs. A solid met
                                 by the first-order stencil of fluid node x along e_j emits
                                 alpha times the diffuse value plus (1 - alpha) times the
                                 previous iteration's h at x for the velocity mirrored in e_j.
-                                Needs stencil_rule 1; swept by the tile-diagonal schedule
-                                (AUTO picks it; ROWS(_AGENT) is PDVM_E_UNSUPPORTED); a
+                                Needs stencil_rule 1; both sweep schedules carry it; a
                                 checkpoint then holds all of h */
 } pdvm_config;
 

@@ -245,14 +245,6 @@ int validate_and_build(const pdvm_config *cfg, Problem &P, std::string &err) {
     err = "the row-pipeline sweep is 2D only";
     return PDVM_E_UNSUPPORTED;
   }
-  if ((P.schedule == PDVM_SCHEDULE_ROWS || P.schedule == PDVM_SCHEDULE_ROWS_AGENT) && P.prandtl > 0) {
-    err = "the Shakhov model is swept by the tile-diagonal schedule only";
-    return PDVM_E_UNSUPPORTED;
-  }
-  if ((P.schedule == PDVM_SCHEDULE_ROWS || P.schedule == PDVM_SCHEDULE_ROWS_AGENT) && P.spec > 0) {
-    err = "Maxwell walls (specular_fraction > 0) are swept by the tile-diagonal schedule only";
-    return PDVM_E_UNSUPPORTED;
-  }
   if (cfg->stencil_rule != 0 && cfg->stencil_rule != 1) { err = "stencil_rule must be 0 or 1"; return PDVM_E_INVAL; }
   if (P.spec > 0 && cfg->stencil_rule != 1) { err = "Maxwell walls (specular_fraction > 0) need stencil_rule 1"; return PDVM_E_UNSUPPORTED; }
   P.stencil_rule = cfg->stencil_rule;
@@ -940,7 +932,7 @@ int create_common(const pdvm_config *cfgs, int n, void *dev_workspace, size_t ws
   // automatic: the row pipeline for a single 2D problem; a batch fills the
   // machine better with per-diagonal launches (measured)
   s->rows = P0.dim == 2 && (P0.schedule == PDVM_SCHEDULE_ROWS || P0.schedule == PDVM_SCHEDULE_ROWS_AGENT ||
-                            (P0.schedule == PDVM_SCHEDULE_AUTO && n == 1 && !(P0.prandtl > 0) && !(P0.spec > 0)));
+                            (P0.schedule == PDVM_SCHEDULE_AUTO && n == 1));
   if (s->rows) {
     // the row pipeline stores a tile through 32-bit byte offsets from its
     // lowest-addressed voxel

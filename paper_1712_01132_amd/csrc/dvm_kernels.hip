@@ -147,6 +147,9 @@ __device__ __forceinline__ T wall_at_y1(const Dom<T> &g, PW wall, int j, int s, 
 // from the current sweep of upstream tiles (earlier launches) or from the
 // lagged images outside the domain.
 constexpr uint32_t R_SKIP = 0x80000000u;  // solid voxel or outside the tile
+// row pipeline codes: the reciprocal denominators' LDS byte offset below
+// kRdMask, Maxwell-wall bits (axis k: kWallBit << k) above it
+constexpr uint32_t kRdMask = 0xFFFFu, kWallBit = 0x10000u;
 
 // Index of the problem owning block b: off[p] <= b < off[p + 1].
 __device__ __forceinline__ int owner_of(const int *off, int nprob, int b) {
@@ -478,14 +481,20 @@ __global__ void __launch_bounds__(kWave)
 // store is then decided by the voxel alone (uniform), without a per-lane mask.
 // With TAU (the temperature fed back, which in 2D needs psi) a lane's slot
 // holds h or psi, as in sweep_kernel with PSI.
-template <typename T, int TT, bool Y2WALL, bool LOCAL, int NW, bool TAU>
+// EXT as in sweep_kernel: bit 0 the temperature fed back (in 2D with psi),
+// bit 1 the Shakhov heat-flux source (two more record values), bit 2 Maxwell
+// walls (never with Y2WALL).
+template <typename T, int TT, bool Y2WALL, bool LOCAL, int NW, int EXT>
 __global__ void __launch_bounds__(kWave * NW)
     sweep_rows_kernel(const Geo<T> *__restrict__ G, const int *__restrict__ row_off, int nprob, int stride) {
   constexpr int DIM = 2;
   constexpr int NC = TT * TT;
+  constexpr bool TAU = (EXT & 1) != 0, SH = (EXT & 2) != 0, MW = (EXT & 4) != 0;
+  static_assert(!(MW && Y2WALL), "Maxwell walls need stencil rule 1");
   // record: src (3), then per axis (c1, c2, w), then the feedback source;
-  // 10 values, so a record is five aligned 16-byte LDS reads
-  constexpr int RW = 10;
+  // 10 values, so a record is five aligned 16-byte LDS reads (Shakhov: the
+  // two heat-flux sources follow)
+  constexpr int RW = SH ? 12 : 10;
   constexpr int RING = 2;
   __shared__ T rd_lds[4 * kWave];
   __shared__ T rec_lds[NW][NC * RW];
@@ -539,12 +548,17 @@ __global__ void __launch_bounds__(kWave * NW)
   const T ph = TAU ? as_global(G_.phm)[qq] : T(1);
   Dom<T> dv = dm;  // as dm, with the jump this lane's values take
   if (TAU) dv.jump = dm.jump * ph;
-  T vv[2], aa[2];
+  T vv[2], aa[2], cq[2] = {T(0), T(0)}, am[2] = {T(0), T(0)};
+  const T qs = SH ? as_global(G_.qsf)[qq] : T(0);  // the Shakhov source's q.v factor
+  const T spec = G_.spec, alpha = G_.alpha;
 #pragma unroll
   for (int k = 0; k < DIM; ++k) {
-    const T av = absv[k * Ko_pad + qq] * ph;
+    const T a = absv[k * Ko_pad + qq];
+    const T av = a * ph;
     vv[k] = s[k] > 0 ? av : -av;
     aa[k] = avv[k * Ko_pad + qq];
+    if (SH) cq[k] = (s[k] > 0 ? a : -a) * qs;
+    if (MW) am[k] = aa[k] * spec;
   }
   if (w == 0) {
 #pragma unroll
@@ -632,7 +646,7 @@ __global__ void __launch_bounds__(kWave * NW)
   // a wait for the halo must not also wait for this prefetch.
   struct Raw {
     uint32_t f;
-    T sv0, sv1, sv2, svt, wv[2];
+    T sv0, sv1, sv2, svt, wv[2], sq[2];
   };
   auto fetch = [&](int a, Raw &R) {
     const int ta = s[0] > 0 ? a : ntile0 - 1 - a;
@@ -650,6 +664,11 @@ __global__ void __launch_bounds__(kWave * NW)
     R.svt = tau_fb ? st : T(0);
 #pragma unroll
     for (int k = 0; k < DIM; ++k) R.wv[k] = wall[cc * 6 + 2 * k + pin[k]];
+    if (SH) {
+      const gptr<const T> qp = as_global(G_.srcqcur) + cc * 4;
+      R.sq[0] = qp[0];
+      R.sq[1] = qp[1];
+    }
     R.f = in ? f : F_SOLID;
   };
   Raw nxt;
@@ -689,6 +708,10 @@ __global__ void __launch_bounds__(kWave * NW)
         rp[1] = cur.sv1;
         rp[2] = cur.sv2;
         rp[9] = cur.svt;
+        if (SH) {
+          rp[10] = cur.sq[0];
+          rp[11] = cur.sq[1];
+        }
         code = 0;
 #pragma unroll
         for (int k = 0; k < DIM; ++k) {
@@ -696,7 +719,8 @@ __global__ void __launch_bounds__(kWave * NW)
           const bool first = fj & 1u, y1s = fj & 2u, y2s = fj & 4u;
           T c1 = first ? (y1s ? T(0) : T(1)) : T(2);
           T c2 = first ? T(0) : T(-0.5);
-          T wl = (first && y1s) ? cur.wv[k] : T(0);
+          T wl = (first && y1s) ? (MW ? alpha * cur.wv[k] : cur.wv[k]) : T(0);
+          if (MW && first && y1s) code |= kWallBit << k;
           if (Y2WALL && !first && y2s) {
             c2 = T(0);
             wl = T(-0.5) * wall_at_y1(dm, wall, k, s[k], pin[k], x, y, 0);
@@ -708,7 +732,8 @@ __global__ void __launch_bounds__(kWave * NW)
         }
       }
       // the byte offset of the voxel's reciprocal denominators in rd_lds
-      rcode[lane] = (code & R_SKIP) | ((code & 3u) * (uint32_t)(kWave * sizeof(T)));
+      // (and, with Maxwell walls, the wall bits above it)
+      rcode[lane] = (code & (R_SKIP | kWallBit | (kWallBit << 1))) | ((code & 3u) * (uint32_t)(kWave * sizeof(T)));
     }
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
     __builtin_amdgcn_wave_barrier();
@@ -765,7 +790,7 @@ __global__ void __launch_bounds__(kWave * NW)
 #pragma unroll
       for (int k = 0; k < NC; ++k) cw[k] = __builtin_amdgcn_readfirstlane(rcode[k]);
 #pragma unroll
-      for (int k = 0; k < NC; ++k) rdv[k] = *(const T *)((const char *)rd_lane + (cw[k] & ~R_SKIP));
+      for (int k = 0; k < NC; ++k) rdv[k] = *(const T *)((const char *)rd_lane + (cw[k] & kRdMask));
     }
 
     // --- the tile's anti-diagonals (as in sweep_kernel) ---------------------
@@ -798,13 +823,21 @@ __global__ void __launch_bounds__(kWave * NW)
           T num = fma(rp[1], vv[0], TAU ? rp[0] * ph : rp[0]);
           num = fma(rp[2], vv[1], num);
           if (TAU) num = fma(rp[9], vsqm, num);
+          if (SH) num = fma(rp[11], cq[1], fma(rp[10], cq[0], num));
+          if (MW) {
+            // the voxel's own previous iterate at the mirrored velocity (a uniform branch)
+            const gptr<const T> hv_prev = hp + (int64_t)((ys + r * s[1]) * n0 + xs + i * s[0]) * Kp;
+#pragma unroll
+            for (int k = 0; k < DIM; ++k)
+              if (code & (kWallBit << k)) num = fma(am[k], hv_prev[kmir[k]], num);
+          }
           const T x1a = i >= 1 ? D1[r] : L1[r];
           const T x1b = i >= 2 ? D2[r] : (i == 1 ? L1[r] : L2[r]);
           const T x2a = r >= 1 ? D1[r >= 1 ? r - 1 : 0] : B1[i];
           const T x2b = r >= 2 ? D2[r >= 2 ? r - 2 : 0] : (r == 1 ? B1[i] : B2[i]);
           num = fma(aa[0], fma(rp[3], x1a, fma(rp[4], x1b, TAU ? rp[5] * ph : rp[5])), num);
           num = fma(aa[1], fma(rp[6], x2a, fma(rp[7], x2b, TAU ? rp[8] * ph : rp[8])), num);
-          Nw[r] = num * (PRE ? rdv[PRE ? i + TT * r : 0] : *(const T *)((const char *)rd_lane + (code & ~R_SKIP)));
+          Nw[r] = num * (PRE ? rdv[PRE ? i + TT * r : 0] : *(const T *)((const char *)rd_lane + (code & kRdMask)));
           Nc[r] = code;
           if (FULL) {
             if (i == TT - 1) out.LN1[r] = Nw[r];
@@ -1359,20 +1392,29 @@ hipError_t launch_sweep(const Batch<T> &B, int diag, hipStream_t st) {
 
 template <typename T, bool LOCAL>
 void launch_rows_local(const Batch<T> &B, dim3 grid, hipStream_t st) {
-#define PDVM_ROWS(TTV, Y2, TAU)                                                                   \
-  hipLaunchKernelGGL((sweep_rows_kernel<T, TTV, Y2, LOCAL, band_waves(TTV), TAU>), grid,         \
+#define PDVM_ROWS(TTV, Y2, E)                                                                   \
+  hipLaunchKernelGGL((sweep_rows_kernel<T, TTV, Y2, LOCAL, band_waves(TTV), E>), grid,         \
                      dim3(kWave * band_waves(TTV)), 0, st, B.d_geo, B.d_row_off, B.nprob, B.row_stride)
-#define PDVM_ROWS_TAU(TTV, Y2)         \
-  if (B.tau_fb) PDVM_ROWS(TTV, Y2, true); \
-  else PDVM_ROWS(TTV, Y2, false)
+  // EXT: bit 0 tau fed back (psi), bit 1 Shakhov, bit 2 Maxwell walls (rule 1 only)
+#define PDVM_ROWS_EXT(TTV, Y2)                                   \
+  if (B.shakhov) PDVM_ROWS(TTV, Y2, 3);                          \
+  else if (B.tau_fb) PDVM_ROWS(TTV, Y2, 1);                      \
+  else PDVM_ROWS(TTV, Y2, 0)
+#define PDVM_ROWS_MW(TTV)                                        \
+  if (B.shakhov) PDVM_ROWS(TTV, false, 7);                       \
+  else if (B.tau_fb) PDVM_ROWS(TTV, false, 5);                   \
+  else PDVM_ROWS(TTV, false, 4)
   if (B.tile_edge == 4) {
-    if (B.y2wall) PDVM_ROWS_TAU(4, true);
-    else PDVM_ROWS_TAU(4, false);
+    if (B.maxwell) { PDVM_ROWS_MW(4); }
+    else if (B.y2wall) { PDVM_ROWS_EXT(4, true); }
+    else { PDVM_ROWS_EXT(4, false); }
   } else {
-    if (B.y2wall) PDVM_ROWS_TAU(8, true);
-    else PDVM_ROWS_TAU(8, false);
+    if (B.maxwell) { PDVM_ROWS_MW(8); }
+    else if (B.y2wall) { PDVM_ROWS_EXT(8, true); }
+    else { PDVM_ROWS_EXT(8, false); }
   }
-#undef PDVM_ROWS_TAU
+#undef PDVM_ROWS_MW
+#undef PDVM_ROWS_EXT
 #undef PDVM_ROWS
 }
 

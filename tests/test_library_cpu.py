@@ -85,10 +85,8 @@ def test_workspace_bytes_for_valid_config():
     ("wsum", "sum"),
     ("tau2d_wide", "psi"),
     ("shakhov_no_tau", "tau_feedback"),
-    ("shakhov_rows", "Shakhov"),
     ("prandtl_neg", "prandtl"),
     ("maxwell_rule0", "stencil_rule 1"),
-    ("maxwell_rows", "Maxwell"),
     ("maxwell_alpha0", "specular_fraction"),
     ("zero_node", "ascending"),
 ])
@@ -117,14 +115,10 @@ def test_invalid_configs_rejected(case, needle):
         grid = [(x, w * 1.001)] * 2
     elif case == "shakhov_no_tau":
         kw["prandtl"] = 2.0 / 3.0
-    elif case == "shakhov_rows":
-        kw.update(prandtl=2.0 / 3.0, tau_feedback=True, schedule="rows")
     elif case == "prandtl_neg":
         kw.update(prandtl=-0.5, tau_feedback=True)
     elif case == "maxwell_rule0":
         kw.update(accommodation=0.5, stencil_rule=0)
-    elif case == "maxwell_rows":
-        kw.update(accommodation=0.5, schedule="rows")
     elif case == "maxwell_alpha0":
         kw.update(accommodation=0.0)
     elif case == "tau2d_wide":

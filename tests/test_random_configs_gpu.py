@@ -34,9 +34,7 @@ def draw(case):
     tau = bool(rng.random() < 0.4)
     prandtl = float(rng.choice([0.5, 2.0 / 3.0])) if (tau and rng.random() < 0.5) else None
     alpha = float(rng.choice([0.4, 0.75])) if (rule == 1 and rng.random() < 0.35) else 1.0
-    schedule = "auto"
-    if dim == 2 and prandtl is None and alpha == 1.0:
-        schedule = str(rng.choice(["auto", "rows", "diagonals"]))
+    schedule = str(rng.choice(["auto", "rows", "diagonals"])) if dim == 2 else "auto"
     return {
         "shape": shape, "nv": nv, "tile": tile, "rule": rule, "tau": tau, "prandtl": prandtl, "alpha": alpha,
         "schedule": schedule,
