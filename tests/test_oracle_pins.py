@@ -215,6 +215,29 @@ def test_maxwell_walls_alpha_one_is_diffuse_and_rule_0_rejected():
         OracleSolver(m, [6, 6], 0.5, accommodation=0.0)
 
 
+def test_slip_flow_limit_of_the_channel():
+    """Near-continuum check of the discretisation against theory: at
+    Kn_H = 0.03 (mean free path about one voxel at H = 32) the permeability
+    of the plane channel converges with H, about first order, towards the
+    slip-corrected Poiseuille value (H^2/12)(1 + 6 sigma (2/sqrt(pi)) Kn_H),
+    sigma = 1.016 the viscous slip coefficient of the BGK model. A wrong
+    collision frequency, slip or normalisation of k would move the limit."""
+    kn_h, r = 0.03, []
+    for H in (32, 64, 128):
+        n1, n2 = 2, H + 2
+        m = geometry.plane_channel(n1, n2)
+        kn = kn_h * H / n1
+        fp = solve_fixed_point(m, [8, 8], kn)
+        gp = fp["u"][0][m == 0].mean() * H / n2
+        k = 2 / math.sqrt(math.pi) * kn * gp
+        r.append(k / ((H / n1) ** 2 / 12 * (H / n2)))
+    slip = 1 + 6 * 1.016 * (2 / math.sqrt(math.pi)) * kn_h
+    d1, d2 = r[0] - r[1], r[1] - r[2]
+    assert d1 > 0 and d2 > 0 and d2 < 0.8 * d1       # monotone, converging
+    limit = r[2] - d2 * (d2 / d1) / (1 - d2 / d1)    # geometric extrapolation
+    assert abs(limit / slip - 1) < 0.01, (r, limit, slip)
+
+
 def test_finite_kn_channel_translation_invariant_and_direct():
     m = geometry.plane_channel(6, 9)
     o = OracleSolver(m, [6, 6], 0.3, threads=4)
