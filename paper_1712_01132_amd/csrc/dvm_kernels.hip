@@ -1454,8 +1454,11 @@ hipError_t launch_moments(const Batch<T> &B, hipStream_t st) {
 #define PDVM_MOM(D, S, P) launch_moments_as<T, D, S, P>(B, blocks, st)
   // paired slots (2 per lane and 128-slot block) in 2D: 9 % faster in FP32 on
   // the 512^2 rock, unchanged in FP64; slower on the 96^3 pack, so not in 3D
-  if (B.dim == 2 && B.Ko % 2 == 0 && B.Ko >= 2) {
-    const int ns = 2 * ((B.Ko + 2 * kWave - 1) / (2 * kWave));
+  // pairs only where they cover the octant with no more slots than single
+  // slots do (Ko = 144: 256 paired slots against 192 single ones)
+  const int ns1 = (B.Ko + kWave - 1) / kWave, ns2 = 2 * ((B.Ko + 2 * kWave - 1) / (2 * kWave));
+  if (B.dim == 2 && B.Ko % 2 == 0 && B.Ko >= 2 && ns2 <= ns1) {
+    const int ns = ns2;
     if (ns <= 2) PDVM_MOM(2, 2, true);
     else if (ns <= 4) PDVM_MOM(2, 4, true);
     else if (ns <= 8) PDVM_MOM(2, 8, true);
