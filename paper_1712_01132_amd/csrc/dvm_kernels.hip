@@ -738,6 +738,21 @@ __global__ void __launch_bounds__(kWave * NW)
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
     __builtin_amdgcn_wave_barrier();
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    // 4 x 4 tiles: the voxel codes and this lane's reciprocal denominators of
+    // the whole tile are read before the walk, so that no voxel waits on two
+    // chained LDS reads (code, then denominator); they depend only on this
+    // wavefront's records, so they are read before the wait for the halo and
+    // their latency overlaps it
+    constexpr bool PRE = TT == 4;
+    uint32_t cw[PRE ? NC : 1];
+    T rdv[PRE ? NC : 1];
+    if (PRE) {
+#pragma unroll
+      for (int k = 0; k < NC; ++k) cw[k] = __builtin_amdgcn_readfirstlane(rcode[k]);
+#pragma unroll
+      for (int k = 0; k < NC; ++k) rdv[k] = *(const T *)((const char *)rd_lane + (cw[k] & kRdMask));
+    }
+
     // --- bottom halo ------------------------------------------------------------
     T B1[TT], B2[TT];
     if (lwait) {
@@ -779,19 +794,6 @@ __global__ void __launch_bounds__(kWave * NW)
     // lowest-addressed voxel, with wavefront-constant row and column offsets
     const __amdgpu_buffer_rsrc_t tile_rsrc = __builtin_amdgcn_make_buffer_rsrc(
         (void *)(T *)(hz + (int64_t)(ylo * n0 + (s[0] > 0 ? xs : xs - (TT - 1))) * Kp), (short)0, -1, kBufferFlags);
-
-    // 4 x 4 tiles: the voxel codes and this lane's reciprocal denominators of
-    // the whole tile are read before the walk, so that no voxel waits on two
-    // chained LDS reads (code, then denominator)
-    constexpr bool PRE = TT == 4;
-    uint32_t cw[PRE ? NC : 1];
-    T rdv[PRE ? NC : 1];
-    if (PRE) {
-#pragma unroll
-      for (int k = 0; k < NC; ++k) cw[k] = __builtin_amdgcn_readfirstlane(rcode[k]);
-#pragma unroll
-      for (int k = 0; k < NC; ++k) rdv[k] = *(const T *)((const char *)rd_lane + (cw[k] & kRdMask));
-    }
 
     // --- the tile's anti-diagonals (as in sweep_kernel) ---------------------
     // FULL: a whole TT x TT tile, so the columns and rows handed on are
