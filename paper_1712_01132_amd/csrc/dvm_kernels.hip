@@ -753,6 +753,14 @@ __global__ void __launch_bounds__(kWave * NW)
       for (int k = 0; k < NC; ++k) rdv[k] = *(const T *)((const char *)rd_lane + (cw[k] & kRdMask));
     }
 
+    // records of voxels (0,0), (1,0) and (0,1): the walk's first two anti-diagonals
+    T rpre[PRE ? 3 : 1][RW];
+    if (PRE) {
+#pragma unroll
+      for (int v = 0; v < 3; ++v)
+#pragma unroll
+        for (int k = 0; k < RW; ++k) rpre[v][k] = rec[(v == 0 ? 0 : (v == 1 ? 1 : TT)) * RW + k];
+    }
     // --- bottom halo ------------------------------------------------------------
     T B1[TT], B2[TT];
     if (lwait) {
@@ -822,10 +830,12 @@ __global__ void __launch_bounds__(kWave * NW)
           if (i < 0 || i >= TT) continue;
           const uint32_t code = PRE ? cw[PRE ? i + TT * r : 0] : __builtin_amdgcn_readfirstlane(rcode[i + TT * r]);
           const T *rp = rec + (i + TT * r) * RW;
-          T num = fma(rp[1], vv[0], TAU ? rp[0] * ph : rp[0]);
-          num = fma(rp[2], vv[1], num);
-          if (TAU) num = fma(rp[9], vsqm, num);
-          if (SH) num = fma(rp[11], cq[1], fma(rp[10], cq[0], num));
+          // the first two anti-diagonals' records come from registers read before the halo wait
+          auto rv = [&](int k) __attribute__((always_inline)) { return (PRE && d <= 1) ? rpre[d == 0 ? 0 : (r == 0 ? 1 : 2)][k] : rp[k]; };
+          T num = fma(rv(1), vv[0], TAU ? rv(0) * ph : rv(0));
+          num = fma(rv(2), vv[1], num);
+          if (TAU) num = fma(rv(9), vsqm, num);
+          if (SH) num = fma(rv(11), cq[1], fma(rv(10), cq[0], num));
           if (MW) {
             // the voxel's own previous iterate at the mirrored velocity (a uniform branch)
             const gptr<const T> hv_prev = hp + (int64_t)((ys + r * s[1]) * n0 + xs + i * s[0]) * Kp;
@@ -837,8 +847,8 @@ __global__ void __launch_bounds__(kWave * NW)
           const T x1b = i >= 2 ? D2[r] : (i == 1 ? L1[r] : L2[r]);
           const T x2a = r >= 1 ? D1[r >= 1 ? r - 1 : 0] : B1[i];
           const T x2b = r >= 2 ? D2[r >= 2 ? r - 2 : 0] : (r == 1 ? B1[i] : B2[i]);
-          num = fma(aa[0], fma(rp[3], x1a, fma(rp[4], x1b, TAU ? rp[5] * ph : rp[5])), num);
-          num = fma(aa[1], fma(rp[6], x2a, fma(rp[7], x2b, TAU ? rp[8] * ph : rp[8])), num);
+          num = fma(aa[0], fma(rv(3), x1a, fma(rv(4), x1b, TAU ? rv(5) * ph : rv(5))), num);
+          num = fma(aa[1], fma(rv(6), x2a, fma(rv(7), x2b, TAU ? rv(8) * ph : rv(8))), num);
           Nw[r] = num * (PRE ? rdv[PRE ? i + TT * r : 0] : *(const T *)((const char *)rd_lane + (code & kRdMask)));
           Nc[r] = code;
           if (FULL) {
