@@ -753,13 +753,18 @@ __global__ void __launch_bounds__(kWave * NW)
       for (int k = 0; k < NC; ++k) rdv[k] = *(const T *)((const char *)rd_lane + (cw[k] & kRdMask));
     }
 
-    // records of voxels (0,0), (1,0) and (0,1): the walk's first two anti-diagonals
-    T rpre[PRE ? 3 : 1][RW];
+    // records of the voxels on the walk's first NPD anti-diagonals (i + r <
+    // NPD), indexed by i + 3 r: three diagonals in FP32; two in FP64, where a
+    // third costs more registers than its latency saves
+    constexpr int NPD = sizeof(T) == 4 ? 3 : 2;
+    T rpre[PRE ? 9 : 1][RW];
     if (PRE) {
 #pragma unroll
-      for (int v = 0; v < 3; ++v)
+      for (int v = 0; v < 9; ++v)
+        if (v % 3 + v / 3 < NPD) {
 #pragma unroll
-        for (int k = 0; k < RW; ++k) rpre[v][k] = rec[(v == 0 ? 0 : (v == 1 ? 1 : TT)) * RW + k];
+          for (int k = 0; k < RW; ++k) rpre[v][k] = rec[(v % 3 + TT * (v / 3)) * RW + k];
+        }
     }
     // --- bottom halo ------------------------------------------------------------
     T B1[TT], B2[TT];
@@ -830,8 +835,8 @@ __global__ void __launch_bounds__(kWave * NW)
           if (i < 0 || i >= TT) continue;
           const uint32_t code = PRE ? cw[PRE ? i + TT * r : 0] : __builtin_amdgcn_readfirstlane(rcode[i + TT * r]);
           const T *rp = rec + (i + TT * r) * RW;
-          // the first two anti-diagonals' records come from registers read before the halo wait
-          auto rv = [&](int k) __attribute__((always_inline)) { return (PRE && d <= 1) ? rpre[d == 0 ? 0 : (r == 0 ? 1 : 2)][k] : rp[k]; };
+          // the first NPD anti-diagonals' records come from registers read before the halo wait
+          auto rv = [&](int k) __attribute__((always_inline)) { return (PRE && d < NPD) ? rpre[PRE && d < NPD ? i + 3 * r : 0][k] : rp[k]; };
           T num = fma(rv(1), vv[0], TAU ? rv(0) * ph : rv(0));
           num = fma(rv(2), vv[1], num);
           if (TAU) num = fma(rv(9), vsqm, num);
