@@ -114,13 +114,17 @@ def _linear_field(o, a, b=0.3):
     return f
 
 
-@pytest.mark.parametrize("dim", [2, 3])
-def test_upwind_operator_exact_on_linear_fields(dim):
+@pytest.mark.parametrize("dim,rule", [(2, 1), (3, 1), (2, 0), (3, 0)])
+def test_upwind_operator_exact_on_linear_fields(dim, rule):
+    """Both stencils reproduce v.a exactly for h = a.x + b. Under stencil rule
+    0 a solid second upstream image enters the second-order stencil with the
+    wall value seen from the first (fluid) upstream node, which the lagged
+    half-fluxes below make equal to the linear field there."""
     rng = np.random.default_rng(11)
     shape = (9, 11) if dim == 2 else (7, 8, 9)
     solid = (rng.random(shape) < 0.25).astype(np.uint8)
     J = 1.0
-    o = OracleSolver(solid, [4] * dim, 1.0, jump=J, threads=1)
+    o = OracleSolver(solid, [4] * dim, 1.0, jump=J, threads=1, stencil_rule=rule)
     a = np.array([-J, 0.7, -0.4][:dim])  # slope -J along x1 matches the jump
     f = _linear_field(o, a)
     dx = 1.0 / o.n[0]
@@ -261,16 +265,22 @@ def _random_mask(shape, frac, seed):
             return m
 
 
-@pytest.mark.parametrize("shape,nv,kn,seed", [
-    ((8, 8), 4, 0.7, 3),
-    ((10, 10), 8, 0.25, 4),
-    ((6, 6, 6), 4, 1.3, 5),
+@pytest.mark.parametrize("shape,nv,kn,seed,rule", [
+    ((8, 8), 4, 0.7, 3, 1),
+    ((10, 10), 8, 0.25, 4, 1),
+    ((6, 6, 6), 4, 1.3, 5, 1),
+    # stencil rule 0 (a solid second upstream image keeps the second-order
+    # stencil with its wall value): on these grids it differs from rule 1 by
+    # 13 % and 20 % of max|u|, so the comparison sees the rule-0 wall term
+    ((8, 8), 4, 0.7, 3, 0),
+    ((10, 10), 8, 0.25, 4, 0),
+    ((6, 6, 6), 4, 1.3, 5, 0),
 ])
-def test_dense_bordered_lu_matches_iteration(shape, nv, kn, seed):
+def test_dense_bordered_lu_matches_iteration(shape, nv, kn, seed, rule):
     m = _random_mask(shape, 0.3, seed)
     dim = len(shape)
-    fp = solve_fixed_point(m, [nv] * dim, kn)
-    o = OracleSolver(m, [nv] * dim, kn, threads=8)
+    fp = solve_fixed_point(m, [nv] * dim, kn, stencil_rule=rule)
+    o = OracleSolver(m, [nv] * dim, kn, threads=8, stencil_rule=rule)
     r = o.iterate(200000, 1e-13)
     assert r["converged"]
     rho, u, _, _ = o.moments()
@@ -281,10 +291,70 @@ def test_dense_bordered_lu_matches_iteration(shape, nv, kn, seed):
     assert np.max(np.abs((rr - fp["rho"])[fl])) <= 1e-10 * max(np.abs(rr).max(), scale)
 
 
-def test_dense_lu_symmetric_geometry_has_no_drift():
+@pytest.mark.parametrize("rule", [1, 0])
+def test_dense_lu_symmetric_geometry_has_no_drift(rule):
     m = geometry.centred_disc(8, 2.0)
-    fp = solve_fixed_point(m, [4, 4], 0.5)
+    fp = solve_fixed_point(m, [4, 4], 0.5, stencil_rule=rule)
     assert abs(fp["delta"]) < 1e-13
+    o = OracleSolver(m, [4, 4], 0.5, threads=4, stencil_rule=rule)
+    assert o.iterate(100000, 1e-13)["converged"]
+    rho, u, _, _ = o.moments()
+    assert np.max(np.abs(u - fp["u"])) <= 1e-10 * np.abs(u).max()
+    assert np.max(np.abs((rho - fp["rho"])[m == 0])) <= 1e-10 * np.abs(u).max()
+
+
+# --- convergence criterion (Sec. 3.1 step (v), Eq. convergence_criterion) -----
+
+def _k_from_field(o, kn):
+    """k = (2/sqrt(pi)) Kn G_p with G_p the mean of u1 over all cells, solid = 0
+    (Eq. k_Gp), computed here from the oracle's velocity field."""
+    _, u, _, _ = o.moments()
+    return 2.0 / math.sqrt(math.pi) * kn * float(np.mean(u[0]))
+
+
+def test_paper_err_recomputed_from_the_permeability_history():
+    """Err(l) = (1/100) |(k^(l) - k^(l-100)) / k^(l)| at every multiple of 100
+    iterations, undefined before the second one. The k history is recomputed
+    here from the oracle's field after each block of 100 iterations, so a wrong
+    denominator (k^(l-100)), a dropped 1/100 or a stale ring entry fails."""
+    m = _random_mask((12, 14), 0.3, 21)
+    kn = 0.8
+    o = OracleSolver(m, [6, 6], kn, threads=1)
+    ks, errs = [], []
+    for _ in range(8):
+        st = o.iterate(100)
+        ks.append(_k_from_field(o, kn))
+        assert abs(st["k"] - ks[-1]) <= 1e-13 * abs(ks[-1])
+        errs.append(st["err"])
+    assert errs[0] == -1.0
+    mine = [abs((ks[i] - ks[i - 1]) / ks[i]) / 100.0 for i in range(1, 8)]
+    for e_or, e in zip(errs[1:], mine):
+        # k carries ~1e-16 of summation-order rounding; Err is a difference of two k
+        assert abs(e_or - e) <= 1e-8 * e + 1e-17, (e_or, e)
+    assert min(mine) > 1e-9  # the k history still moves: the differences are far above rounding
+
+
+def test_paper_stop_mode_halts_at_first_multiple_of_100_below_tol():
+    """STOP_PAPER_ERR: the first multiple of 100 at which the recomputed Err(l)
+    is below tol ends the run, and not a later or earlier one."""
+    m = _random_mask((12, 14), 0.3, 21)
+    kn = 0.8
+    o = OracleSolver(m, [6, 6], kn, threads=1)
+    ks = []
+    for _ in range(10):
+        o.iterate(100)
+        ks.append(_k_from_field(o, kn))
+    mine = [abs((ks[i] - ks[i - 1]) / ks[i]) / 100.0 for i in range(1, 10)]
+    for target in (3, 6, 8):  # stop at 100 (target + 1)
+        tol = mine[target - 1] * (1 + 1e-6)
+        want = next(i for i in range(1, 10) if mine[i - 1] < tol)
+        p = OracleSolver(m, [6, 6], kn, threads=1)
+        st = p.iterate(5000, tol, stop_mode=1)
+        assert st["converged"]
+        assert st["iters"] == 100 * (want + 1), (st["iters"], want)
+        # field mode ignores Err: the same run with stop_mode 0 and a tiny tol runs on
+        q = OracleSolver(m, [6, 6], kn, threads=1)
+        assert q.iterate(100 * (want + 1), tol, stop_mode=0)["iters"] == 100 * (want + 1)
 
 
 # --- invariants of the iteration ---------------------------------------------
