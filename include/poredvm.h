@@ -49,7 +49,8 @@ enum {
   PDVM_E_NOMEM = -2,        /* allocation failed or workspace too small */
   PDVM_E_HIP = -3,          /* a HIP runtime call failed */
   PDVM_E_NONFINITE = -4,    /* r or k became NaN/Inf; the last good state is kept */
-  PDVM_E_STATE = -5,        /* checkpoint buffer of the wrong size or problem */
+  PDVM_E_STATE = -5,        /* checkpoint buffer of the wrong size or problem; or iterating a
+                               solver whose earlier sweep was abandoned (see pdvm_set_wait_limit) */
   PDVM_E_UNSUPPORTED = -6   /* valid but not implemented (e.g. the row pipeline in 3D) */
 };
 
@@ -153,7 +154,12 @@ int pdvm_set_initial(pdvm_solver *s, const double *rho, const double *u);
 /* Run up to max_iters iterations (Algorithm 1). stop_mode PDVM_STOP_FIELD:
  * stop when r <= tol; PDVM_STOP_PAPER_ERR: stop when Err(l) < tol at a
  * multiple of 100 iterations (Eq. convergence_criterion). tol <= 0 runs all
- * max_iters. Returns PDVM_OK (converged), PDVM_NOT_CONVERGED, or an error. */
+ * max_iters. Returns PDVM_OK (converged), PDVM_NOT_CONVERGED, or an error.
+ * PDVM_E_HIP when a row-pipeline sweep was abandoned (a wait for the upstream
+ * row exceeded its limit, or the blocks of one velocity chain were found on
+ * different XCDs): that iterate is discarded, the state is the last completed
+ * iteration, and the solver then returns PDVM_E_STATE from every iterate until
+ * pdvm_set_initial or pdvm_set_state restores a state. */
 int pdvm_iterate(pdvm_solver *s, int64_t max_iters, double tol, int32_t stop_mode,
                  pdvm_stats *out);
 
@@ -221,6 +227,13 @@ int pdvm_batch_get_flux(pdvm_solver *s, int32_t i, double *gp, double *k, double
  * XCD (chosen only after a probe of the block placement confirms it);
  * -1 for NULL. */
 int32_t pdvm_sweep_schedule(const pdvm_solver *s);
+
+/* Wall-clock bound on each wait of the row-pipeline sweep for its upstream row
+ * (default 2 s; seconds in [0, 3600]). A wait that exceeds it abandons the
+ * sweep as described at pdvm_iterate; every kernel still runs to its end. For
+ * callers that want a tighter bound, and for tests of the fault path (0 gives
+ * up at the first check, after 128 polls). PDVM_E_INVAL outside the range. */
+int pdvm_set_wait_limit(pdvm_solver *s, double seconds);
 
 void pdvm_destroy(pdvm_solver *s);
 

@@ -15,6 +15,7 @@
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
+#include <cstddef>
 #include <cstring>
 #include <limits>
 #include <new>
@@ -29,6 +30,7 @@ using namespace pdvm;
 namespace {
 
 thread_local std::string g_thread_error;
+
 
 void set_thread_error(const char *fmt, ...) {
   char buf[512];
@@ -567,6 +569,7 @@ struct pdvm_solver {
   Batch<double> bd;
   Batch<float> bf;
   Ctl *host_ctl = nullptr;         // pinned, one per problem
+  uint8_t *d_xcc = nullptr;        // device: the XCD of every row-pipeline block (in meta)
   hipGraphExec_t graph = nullptr;
   int graph_iters = 0;
   bool rows = false;               // the sweep is one row-pipeline launch (2D, single problem)
@@ -722,12 +725,14 @@ int finalize_batch(pdvm_solver *s) {
   const size_t blk_b = align256(s->h_blk_off.size() * 4);
   const size_t row_b = align256(s->h_row_off.size() * 4);
   const size_t ctl_b = align256(n * sizeof(Ctl));
+  const size_t xcc_b = align256((size_t)s->h_row_off[n]);
   void *m = nullptr;
-  if (hipMalloc(&m, geo_b + item_b + blk_b + row_b + ctl_b) != hipSuccess)
+  if (hipMalloc(&m, geo_b + item_b + blk_b + row_b + ctl_b + xcc_b) != hipSuccess)
     return s->fail(PDVM_E_NOMEM, "hipMalloc of the batch tables failed");
   s->meta = (char *)m;
   char *geo = s->meta, *item = geo + geo_b, *blk = item + item_b, *rowo = blk + blk_b;
   s->d_ctl_all = (Ctl *)(rowo + row_b);
+  s->d_xcc = (uint8_t *)(rowo + row_b + ctl_b);
   HIPCHK(s, hipMemcpyAsync(rowo, s->h_row_off.data(), s->h_row_off.size() * 4, hipMemcpyHostToDevice, s->stream));
   HIPCHK(s, hipMemcpyAsync(geo, geos<T>(s).data(), n * sizeof(Geo<T>), hipMemcpyHostToDevice, s->stream));
   HIPCHK(s, hipMemcpyAsync(item, s->h_item_off.data(), s->h_item_off.size() * 4, hipMemcpyHostToDevice, s->stream));
@@ -856,6 +861,34 @@ int probe_xcd_locality(pdvm_solver *s) {
   return PDVM_OK;
 }
 
+// Point every problem's descriptor at its range of the per-block XCD records
+// (block = row_off[p] + band * stride + chain) and upload the descriptors.
+template <typename T>
+int enable_xcc_check(pdvm_solver *s) {
+  std::vector<Geo<T>> &G = geos<T>(s);
+  const Batch<T> &B = batch<T>(s);
+  for (int p = 0; p < s->n(); ++p) {
+    G[p].xcc_seen = s->d_xcc + s->h_row_off[p];
+    G[p].row_blocks = s->h_row_off[p + 1] - s->h_row_off[p];
+    G[p].row_stride = B.row_stride;
+  }
+  HIPCHK(s, hipMemcpyAsync((void *)B.d_geo, G.data(), s->n() * sizeof(Geo<T>), hipMemcpyHostToDevice, s->stream));
+  HIPCHK(s, hipStreamSynchronize(s->stream));
+  return PDVM_OK;
+}
+
+// A problem whose sweep was abandoned stays stopped until its state is restored.
+int check_not_poisoned(pdvm_solver *s) {
+  int rc = read_ctl(s);
+  if (rc != PDVM_OK) return rc;
+  for (int i = 0; i < s->n(); ++i)
+    if (s->host_ctl[i].fault)
+      return s->fail(PDVM_E_STATE,
+                     "problem %d: an earlier sweep was abandoned and its iterate discarded; restore a state "
+                     "(set_initial or set_state) before iterating again", i);
+  return PDVM_OK;
+}
+
 int create_common(const pdvm_config *cfgs, int n, void *dev_workspace, size_t ws_bytes, void *hip_stream,
                   pdvm_solver **out) {
   if (!out) { set_thread_error("out is NULL"); return PDVM_E_INVAL; }
@@ -959,6 +992,16 @@ int create_common(const pdvm_config *cfgs, int n, void *dev_workspace, size_t ws
     // automatic choice: the row pipeline only with the cheap XCD-local protocol
     if (!s->rows_local && P0.schedule == PDVM_SCHEDULE_AUTO) s->rows = false;
   }
+  if (s->rows && s->rows_local) {
+    // the XCD-local protocol is checked on every sweep: each block records its
+    // XCD and the reduction discards an iterate whose chains were split
+    const int rc3 = s->precision == PDVM_FP64 ? enable_xcc_check<double>(s) : enable_xcc_check<float>(s);
+    if (rc3 != PDVM_OK) {
+      g_thread_error = s->err;
+      pdvm_destroy(s);
+      return rc3;
+    }
+  }
   *out = s;
   return PDVM_OK;
 }
@@ -981,6 +1024,7 @@ int set_initial_one(pdvm_solver *s, int i, const double *rho, const double *u) {
   c.iter = 0;
   c.stop = 1;
   c.status = 0;
+  c.fault = 0;
   c.err = -1.0;
   c.r = c.k = c.gp = 0;
   for (double &v : c.kring) v = 0;
@@ -997,9 +1041,9 @@ int iterate_batch(pdvm_solver *s, int64_t max_iters, double tol, int32_t stop_mo
   if (max_iters < 0 || (stop_mode != PDVM_STOP_FIELD && stop_mode != PDVM_STOP_PAPER_ERR) || std::isnan(tol))
     return s->fail(PDVM_E_INVAL, "max_iters >= 0, a valid stop mode and a non-NaN tol are required");
   const auto t0 = std::chrono::steady_clock::now();
-  int rc = build_graph(s);
+  int rc = check_not_poisoned(s);
   if (rc != PDVM_OK) return rc;
-  rc = read_ctl(s);
+  rc = build_graph(s);
   if (rc != PDVM_OK) return rc;
   const int n = s->n();
   std::vector<int64_t> start(n);
@@ -1036,7 +1080,12 @@ int iterate_batch(pdvm_solver *s, int64_t max_iters, double tol, int32_t stop_mo
       out[i].seconds = secs;
       out[i].converged = c.status == 1;
     }
-    if (c.fault) return s->fail(PDVM_E_HIP, "problem %d: a row-pipeline sweep gave up waiting for its upstream row", i);
+    if (c.fault == 1)
+      return s->fail(PDVM_E_HIP, "problem %d: a row-pipeline sweep gave up waiting for its upstream row; the iterate "
+                                 "was discarded and the previous state kept", i);
+    if (c.fault)
+      return s->fail(PDVM_E_HIP, "problem %d: the blocks of a row-pipeline velocity chain ran on different XCDs; the "
+                                 "iterate was discarded and the previous state kept", i);
     if (c.status == -4) worst = PDVM_E_NONFINITE;
     else if (c.status != 1 && worst == PDVM_OK) worst = PDVM_NOT_CONVERGED;
   }
@@ -1250,6 +1299,8 @@ int set_state_one(pdvm_solver *s, int i, const void *buf, size_t bytes) {
   if (rc != PDVM_OK) return rc;
   c.par = s->host_ctl[i].par;  // restore into this solver's current buffers
   c.stop = 1;
+  c.fault = 0;
+  if (c.status == -3) c.status = 0;
   s->host_ctl[i] = c;
   HIPCHK(s, hipMemcpyAsync(dev_ctl(s, i), &s->host_ctl[i], sizeof(Ctl), hipMemcpyHostToDevice, s->stream));
   HIPCHK(s, hipStreamSynchronize(s->stream));
@@ -1345,7 +1396,9 @@ int pdvm_batch_get_flux(pdvm_solver *s, int32_t i, double *gp, double *k, double
 
 int pdvm_time_kernels(pdvm_solver *s, int32_t iters, pdvm_timing *out) {
   if (!s || !out || iters <= 0) { set_thread_error("bad arguments"); return PDVM_E_INVAL; }
-  int rc = arm(s, 0.0, 0, 2 * (int64_t)iters + 1);
+  int rc = check_not_poisoned(s);
+  if (rc != PDVM_OK) return rc;
+  rc = arm(s, 0.0, 0, 2 * (int64_t)iters + 1);
   if (rc != PDVM_OK) return rc;
   const bool f64 = s->precision == PDVM_FP64;
   const int nd = s->rows ? 1 : (f64 ? s->bd.ndiag_max : s->bf.ndiag_max);
@@ -1407,6 +1460,11 @@ int pdvm_time_kernels(pdvm_solver *s, int32_t iters, pdvm_timing *out) {
   }
   cleanup();
   if (e != hipSuccess) return s->fail(PDVM_E_HIP, "kernel timing: %s", hipGetErrorString(e));
+  rc = read_ctl(s);
+  if (rc != PDVM_OK) return rc;
+  for (int i = 0; i < s->n(); ++i)
+    if (s->host_ctl[i].fault)
+      return s->fail(PDVM_E_HIP, "problem %d: a row-pipeline sweep was abandoned during timing; the previous state is kept", i);
   const double es = f64 ? 8.0 : 4.0;
   double fluid = 0, vel = 0;
   for (auto &P : s->P) {
@@ -1430,6 +1488,35 @@ int pdvm_time_kernels(pdvm_solver *s, int32_t iters, pdvm_timing *out) {
 int32_t pdvm_sweep_schedule(const pdvm_solver *s) {
   if (!s) return -1;
   return s->rows ? (s->rows_local ? 2 : 1) : 0;
+}
+
+int pdvm_set_wait_limit(pdvm_solver *s, double seconds) {
+  if (!s) { set_thread_error("solver is NULL"); return PDVM_E_INVAL; }
+  if (!(seconds >= 0 && seconds <= 3600)) return s->fail(PDVM_E_INVAL, "wait limit must be in [0, 3600] seconds");
+  int khz = 0, dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess || hipDeviceGetAttribute(&khz, hipDeviceAttributeWallClockRate, dev) != hipSuccess ||
+      khz <= 0)
+    khz = 100000;
+  const int64_t ticks = (int64_t)(seconds * 1000.0 * khz);
+  for (int i = 0; i < s->n(); ++i) {
+    size_t off;
+    int64_t *host;
+    const void *dgeo;
+    if (s->precision == PDVM_FP64) {
+      s->gd[i].wait_ticks = ticks;
+      host = &s->gd[i].wait_ticks;
+      dgeo = s->bd.d_geo + i;
+      off = offsetof(Geo<double>, wait_ticks);
+    } else {
+      s->gf[i].wait_ticks = ticks;
+      host = &s->gf[i].wait_ticks;
+      dgeo = s->bf.d_geo + i;
+      off = offsetof(Geo<float>, wait_ticks);
+    }
+    HIPCHK(s, hipMemcpyAsync((char *)dgeo + off, host, sizeof(int64_t), hipMemcpyHostToDevice, s->stream));
+  }
+  HIPCHK(s, hipStreamSynchronize(s->stream));
+  return PDVM_OK;
 }
 
 void pdvm_destroy(pdvm_solver *s) {

@@ -34,9 +34,13 @@ __host__ __device__ constexpr uint32_t f_y2s(int j, int sidx) { return 1u << (fb
 struct Ctl {
   int32_t par;
   int32_t stop;
-  int32_t status;       // 0 running, 1 converged, 2 budget reached, -4 non-finite
+  int32_t status;       // 0 running, 1 converged, 2 budget reached, -4 non-finite,
+                        // -3 sweep abandoned (see fault)
   int32_t mode;         // 0 field residual, 1 paper Err(l)
-  int32_t fault;        // 1 if a row-pipeline sweep gave up waiting (results invalid)
+  int32_t fault;        // a row-pipeline sweep was abandoned: 1 a wait gave up, 2 the
+                        // blocks of a velocity chain ran on different XCDs. The iterate
+                        // is discarded (par kept); only the host clears it
+                        // (set_initial / set_state), so a poisoned problem stays stopped
   int32_t pad_;
   int64_t iter;         // iterations since the initial state
   int64_t iter_limit;   // stop (status 2) when iter reaches this
@@ -100,6 +104,11 @@ struct Geo {
   int32_t seq = 0;            // advanced by every arm and reduction: stamps of the row pipeline
   int32_t *progress = nullptr;  // [bands][chains] tiles completed per band (row-pipeline sweep)
   int64_t wait_ticks = 0;       // a row-pipeline wait gives up after this many wall-clock ticks (2 s)
+  // XCD-local row pipeline only (else null): every block records the XCD it ran
+  // on, [row_blocks] bytes (block = band * row_stride + chain); the reduction
+  // kernel discards the iterate unless all blocks of each chain agree
+  uint8_t *xcc_seen = nullptr;
+  int32_t row_blocks = 0, row_stride = 0;
 };
 
 // Square sweep tile edges in (x1, x2) compiled into the kernel; the host
@@ -126,7 +135,8 @@ struct Batch {
   int row_stride = 8;
 };
 
-// Kernel launchers (dvm_kernels.hip). All enqueue on `st`.
+// Kernel launchers (dvm_sweep_diag.hip, dvm_sweep_rows.hip, dvm_iter.hip).
+// All enqueue on `st`.
 template <typename T>
 hipError_t launch_sweep(const Batch<T> &B, int diag, hipStream_t st);
 // The whole 2D sweep of every problem of the batch as one row-pipeline launch

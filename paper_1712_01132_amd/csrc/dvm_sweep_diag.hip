@@ -1,0 +1,350 @@
+// Step (i) of the iteration (Sec. 3.1, Algorithm 1) on gfx950: the upwind sweep
+// (Eq. numerical stencil, Eq. Discretised_linearised_Boltzmann_equations) as one
+// launch per diagonal of sweep tiles, for 2D and 3D problems and batches.
+#include "dvm_device.h"
+
+namespace pdvm {
+namespace {
+
+// Step (i) for one diagonal of tiles. One wavefront = one tile x 64 discrete
+// velocities of one sign octant (lanes = velocities), so every per-voxel
+// decision is wavefront-uniform and each voxel's 64 values are one contiguous
+// store. The tile is TT x TT voxels in (x1, x2), any depth along x3, walked
+// plane by plane in the octant's order. Per plane, each lane first decodes one
+// voxel of the plane into an LDS record (source coefficients and, per axis,
+// the stencil weights on the two upstream values and the wall term); the
+// wavefront then walks the plane's 2 TT - 1 anti-diagonals, whose voxels are
+// independent of each other, so their loads and FMA chains overlap. The two
+// previous anti-diagonals stay in registers; values outside the tile come
+// from the current sweep of upstream tiles (earlier launches) or from the
+// lagged images outside the domain.
+// EXT bit 0 (PSI, 2D): slots of h and of psi; bit 1 (SH): the Shakhov
+// heat-flux source, whose per-voxel values nu (4/5)(1 - Pr) q_j end the record;
+// bit 2 (MW): Maxwell walls. A voxel whose axis-j stencil meets a wall (code
+// bit 4 + j) adds a_j (1 - alpha) times its own previous-iteration value of
+// the velocity mirrored in e_j; the record's wall term is alpha rho_w.
+template <typename T, int DIM, int TT, bool Y2WALL, int EXT>
+__global__ void __launch_bounds__(kWave)
+    sweep_kernel(const Geo<T> *__restrict__ G, const int *__restrict__ item_off, int nprob, int diag) {
+  constexpr bool PSI = (EXT & 1) != 0, SH = (EXT & 2) != 0, MW = (EXT & 4) != 0;
+  static_assert(!(MW && Y2WALL), "Maxwell walls need stencil rule 1");
+  constexpr int NC = TT * TT;
+  constexpr int RW = 5 + 3 * DIM + (SH ? DIM : 0);  // record: src (4), nu tau, per axis (c1, c2, w), [q]
+  __shared__ T rd_lds[8 * kWave];
+  __shared__ T rec[NC * RW];
+  __shared__ uint32_t rcode[NC];
+  const int p = nprob > 1 ? owner_of(item_off, nprob, blockIdx.x) : 0;
+  const Geo<T> &G_ = G[p];
+  if (!G_.run) return;  // converged problems retire
+  // every per-problem value is read once here; the loops below see registers
+  const Dom<T> dm = dom_of(G_);
+  const int ngroups = G_.ngroups, Ko = G_.Ko, Ko_pad = G_.Ko_pad, tau_fb = G_.tau_fb;
+  const int tile[3] = {G_.tile[0], G_.tile[1], G_.tile[2]};
+  const int ntile[3] = {G_.ntile[0], G_.ntile[1], G_.ntile[2]};
+  const gptr<const T> absv = as_global(G_.absv), avv = as_global(G_.av), rden = as_global(G_.rden),
+                      vsq = as_global(G_.vsqm);
+  const gptr<T> hc = as_global(G_.hcur);
+  const gptr<const T> hp = as_global(G_.hprev);
+  const gptr<const T> src = as_global(G_.srccur);
+  const gptr<const T> srct = as_global(G_.srctcur);
+  const gptr<const T> srcq = as_global(G_.srcqcur);
+  const gptr<const T> wall = as_global(G_.wallcur);
+  const gptr<const uint32_t> flags = as_global(G_.flags);
+  const int n0 = dm.n[0], n1 = dm.n[1];
+  // tiles of diagonal `diag`: in 2D (a, b) with a + b = diag, computed; in 3D from the table
+  int d0 = 0, ntd;
+  if (DIM == 2) {
+    const int amin = max(0, diag - (ntile[1] - 1)), amax = min(diag, ntile[0] - 1);
+    d0 = amin;
+    ntd = amax - amin + 1;
+  } else {
+    const gptr<const int32_t> diag_off = as_global(G_.diag_off);
+    d0 = diag_off[diag];
+    ntd = diag_off[diag + 1] - d0;
+  }
+  int item = nprob > 1 ? blockIdx.x - item_off[p] : blockIdx.x;
+  const int t = item % ntd;
+  item /= ntd;
+  const int grp = item % ngroups;
+  const int o = item / ngroups;
+  const int lane = threadIdx.x;
+  const int q = grp * kWave + lane;
+  const bool active = q < Ko;
+  const int qq = active ? q : 0;
+  int s[3], sidx[3], pin[3];
+#pragma unroll
+  for (int j = 0; j < 3; ++j) {
+    sidx[j] = (o >> j) & 1;
+    s[j] = sidx[j] ? -1 : 1;
+    pin[j] = 1 - sidx[j];  // incoming half at a wall emitting along s e_j has sign -s
+  }
+  // PSI: the lane's slot holds h (ph = 1) or psi (ph = 0), which has no
+  // rho, u or wall term and no jump at the x1 wrap
+  const T ph = PSI ? as_global(G_.phm)[qq] : T(1);
+  Dom<T> dv = dm;  // as dm, with the jump this lane's values take
+  if (PSI) dv.jump = dm.jump * ph;
+  T vv[3] = {T(0), T(0), T(0)}, aa[3] = {T(0), T(0), T(0)}, cq[3] = {T(0), T(0), T(0)}, am[3] = {T(0), T(0), T(0)};
+  const T qs = SH ? as_global(G_.qsf)[qq] : T(0);  // the Shakhov source's q.v factor
+  const T spec = G_.spec, alpha = G_.alpha;
+#pragma unroll
+  for (int j = 0; j < DIM; ++j) {
+    const T a = absv[j * Ko_pad + qq];
+    const T av = a * ph;
+    vv[j] = s[j] > 0 ? av : -av;
+    aa[j] = avv[j * Ko_pad + qq];
+    if (SH) cq[j] = (s[j] > 0 ? a : -a) * qs;
+    if (MW) am[j] = aa[j] * spec;
+  }
+#pragma unroll
+  for (int c = 0; c < (1 << DIM); ++c) rd_lds[c * kWave + lane] = rden[c * Ko_pad + qq];
+  const T vsqm = tau_fb ? vsq[qq] : T(0);
+  const int kofs = o * Ko_pad + qq;
+  int kmir[3];
+#pragma unroll
+  for (int j = 0; j < 3; ++j) kmir[j] = (o ^ (1 << j)) * Ko_pad + qq;
+
+  int lo[3] = {0, 0, 0}, cnt[3] = {1, 1, 1};
+  int tpos[3] = {0, 0, 0};
+  if (DIM == 2) {
+    tpos[0] = d0 + t;
+    tpos[1] = diag - tpos[0];
+  } else {
+    const gptr<const int32_t> diag_tiles = as_global(G_.diag_tiles);
+#pragma unroll
+    for (int j = 0; j < 3; ++j) tpos[j] = diag_tiles[(d0 + t) * 4 + j];
+  }
+#pragma unroll
+  for (int j = 0; j < DIM; ++j) {
+    const int tp = tpos[j];
+    const int tj = s[j] > 0 ? tp : ntile[j] - 1 - tp;
+    lo[j] = tj * tile[j];
+    cnt[j] = min(tile[j], dm.n[j] - lo[j]);
+  }
+  const int xs = s[0] > 0 ? lo[0] : lo[0] + cnt[0] - 1;
+  const int ys = s[1] > 0 ? lo[1] : lo[1] + cnt[1] - 1;
+
+  for (int c3 = 0; c3 < cnt[2]; ++c3) {
+    const int z = s[2] > 0 ? lo[2] + c3 : lo[2] + cnt[2] - 1 - c3;
+    // --- halos of the plane (before any store of this plane), issued first:
+    // they depend on nothing below. Away from the domain faces they are plain
+    // loads of the current sweep; only tiles touching a face resolve images.
+    T L1[TT], L2[TT], B1[TT], B2[TT];
+    const int64_t Kp = dm.Kpad;
+    const gptr<T> hz = hc + (int64_t)(n1 * z) * n0 * Kp + kofs;  // plane z of the current sweep
+    const bool xin = xs - 2 * s[0] >= 0 && xs - 2 * s[0] < n0;
+    const bool yin = ys - 2 * s[1] >= 0 && ys - 2 * s[1] < n1;
+#pragma unroll
+    for (int k = 0; k < TT; ++k) {
+      L1[k] = L2[k] = B1[k] = B2[k] = T(0);
+      if (k < cnt[1]) {
+        const int y = ys + k * s[1];
+        if (xin) {
+          L1[k] = hz[(int64_t)(y * n0 + xs - s[0]) * Kp];
+          L2[k] = hz[(int64_t)(y * n0 + xs - 2 * s[0]) * Kp];
+        } else {
+          L1[k] = upstream_fluid(dv, hc, hp, 0, xs - s[0], y, z, kofs, kmir[0]);
+          L2[k] = upstream_fluid(dv, hc, hp, 0, xs - 2 * s[0], y, z, kofs, kmir[0]);
+        }
+      }
+      if (k < cnt[0]) {
+        const int x = xs + k * s[0];
+        if (yin) {
+          B1[k] = hz[(int64_t)((ys - s[1]) * n0 + x) * Kp];
+          B2[k] = hz[(int64_t)((ys - 2 * s[1]) * n0 + x) * Kp];
+        } else {
+          B1[k] = upstream_fluid(dv, hc, hp, 1, x, ys - s[1], z, kofs, kmir[1]);
+          B2[k] = upstream_fluid(dv, hc, hp, 1, x, ys - 2 * s[1], z, kofs, kmir[1]);
+        }
+      }
+    }
+    // --- stage: lane = voxel of the plane ---------------------------------
+    // The voxel's sources and wall values are loaded together with its flags
+    // (valid addresses whatever the flags say), so one round trip serves all.
+    if (lane < NC) {
+      const int i = lane % TT, r = lane / TT;
+      uint32_t code = R_SKIP;
+      T *rp = rec + lane * RW;
+#pragma unroll
+      for (int k = 0; k < RW; ++k) rp[k] = T(0);  // a skipped voxel computes 0
+      if (i < cnt[0] && r < cnt[1]) {
+        const int x = xs + i * s[0], y = ys + r * s[1];
+        const int c = (y + n1 * z) * n0 + x;
+        const uint32_t f = flags[c];
+        const gptr<const T> sp = src + c * kSrcStride;
+        const T sv0 = sp[0], sv1 = sp[1], sv2 = sp[2], sv3 = DIM == 3 ? sp[3] : T(0);
+        const T svt = tau_fb ? srct[c] : T(0);
+        T wv[DIM];
+#pragma unroll
+        for (int j = 0; j < DIM; ++j) wv[j] = wall[c * 6 + 2 * j + pin[j]];
+        if (!(f & F_SOLID)) {
+          rp[0] = sv0;
+          rp[1] = sv1;
+          rp[2] = sv2;
+          rp[3] = sv3;
+          rp[4] = svt;
+          if (SH) {
+#pragma unroll
+            for (int j = 0; j < DIM; ++j) rp[5 + 3 * DIM + j] = srcq[c * 4 + j];
+          }
+          code = 0;
+#pragma unroll
+          for (int j = 0; j < DIM; ++j) {
+            const uint32_t fj = f >> fbit(j, sidx[j]);
+            const bool first = fj & 1u, y1s = fj & 2u, y2s = fj & 4u;
+            T c1 = first ? (y1s ? T(0) : T(1)) : T(2);
+            T c2 = first ? T(0) : T(-0.5);
+            T w = (first && y1s) ? (MW ? alpha * wv[j] : wv[j]) : T(0);
+            if (Y2WALL && !first && y2s) {
+              c2 = T(0);
+              w = T(-0.5) * wall_at_y1(dm, wall, j, s[j], pin[j], x, y, z);
+            }
+            rp[5 + 3 * j] = c1;
+            rp[6 + 3 * j] = c2;
+            rp[7 + 3 * j] = w;
+            code |= (first ? 1u : 0u) << j;
+            if (MW && first && y1s) code |= 16u << j;
+          }
+        }
+      }
+      rcode[lane] = code;
+    }
+    const bool zin = DIM == 3 && z - 2 * s[2] >= 0 && z - 2 * s[2] < dm.n[2];
+    const int64_t zstep = (int64_t)n1 * n0 * Kp * s[2];
+    __syncthreads();
+    // store addresses: row r of the tile starts at hrow[r]; voxel i of a row is icol[i] further
+    gptr<T> hrow[TT];
+    int64_t icol[TT];
+#pragma unroll
+    for (int k = 0; k < TT; ++k) {
+      hrow[k] = hz + (int64_t)((ys + k * s[1]) * n0 + xs) * Kp;
+      icol[k] = (int64_t)k * s[0] * Kp;
+    }
+    // --- the plane's anti-diagonals ---------------------------------------
+    T D1[TT], D2[TT];
+#pragma unroll
+    for (int k = 0; k < TT; ++k) D1[k] = D2[k] = T(0);
+#pragma unroll
+    for (int d = 0; d < 2 * TT - 1; ++d) {
+      T Nw[TT];
+      uint32_t Nc[TT];
+      T Z1[TT], Z2[TT];
+#pragma unroll
+      for (int r = 0; r < TT; ++r) {
+        Nw[r] = T(0);
+        Nc[r] = R_SKIP;
+        Z1[r] = Z2[r] = T(0);
+        const int i = d - r;
+        if (DIM == 3 && i >= 0 && i < TT && i < cnt[0] && r < cnt[1]) {
+          const int x = xs + i * s[0], y = ys + r * s[1];
+          if (zin) {
+            const gptr<const T> hv0 = hz + (int64_t)(y * n0 + x) * Kp;
+            Z1[r] = hv0[-zstep];
+            Z2[r] = hv0[-2 * zstep];
+          } else {
+            Z1[r] = upstream_fluid(dv, hc, hp, 2, x, y, z - s[2], kofs, kmir[2]);
+            Z2[r] = upstream_fluid(dv, hc, hp, 2, x, y, z - 2 * s[2], kofs, kmir[2]);
+          }
+        }
+      }
+#pragma unroll
+      for (int r = 0; r < TT; ++r) {
+        const int i = d - r;
+        if (i < 0 || i >= TT) continue;
+        // no branch before the store: the loads of all voxels of the
+        // anti-diagonal can be issued together (a skipped voxel's record is 0)
+        const uint32_t code = __builtin_amdgcn_readfirstlane(rcode[i + TT * r]);
+        const T *rp = rec + (i + TT * r) * RW;
+        T num = fma(rp[1], vv[0], PSI ? rp[0] * ph : rp[0]);
+        num = fma(rp[2], vv[1], num);
+        if (DIM == 3) num = fma(rp[3], vv[2], num);
+        num = fma(rp[4], vsqm, num);  // rp[4] = vsqm = 0 without the feedback
+        if (SH) {
+#pragma unroll
+          for (int j = 0; j < DIM; ++j) num = fma(rp[5 + 3 * DIM + j], cq[j], num);
+        }
+        if (MW) {
+          // the voxel's own previous iterate at the mirrored velocity (a uniform branch)
+          const gptr<const T> hv_prev = hp + ((hrow[r] + icol[i]) - hc) - kofs;
+#pragma unroll
+          for (int j = 0; j < DIM; ++j)
+            if (code & (16u << j)) num = fma(am[j], hv_prev[kmir[j]], num);
+        }
+        const T x1a = i >= 1 ? D1[r] : L1[r];
+        const T x1b = i >= 2 ? D2[r] : (i == 1 ? L1[r] : L2[r]);
+        const T x2a = r >= 1 ? D1[r >= 1 ? r - 1 : 0] : B1[i];
+        const T x2b = r >= 2 ? D2[r >= 2 ? r - 2 : 0] : (r == 1 ? B1[i] : B2[i]);
+        num = fma(aa[0], fma(rp[5], x1a, fma(rp[6], x1b, PSI ? rp[7] * ph : rp[7])), num);
+        num = fma(aa[1], fma(rp[8], x2a, fma(rp[9], x2b, PSI ? rp[10] * ph : rp[10])), num);
+        if (DIM == 3) num = fma(aa[2], fma(rp[11], Z1[r], fma(rp[12], Z2[r], rp[13])), num);
+        Nw[r] = num * rd_lds[(code & 7u) * kWave + lane];
+        Nc[r] = code;
+      }
+      // the stores after the whole anti-diagonal: the loop above stays free
+      // of control flow, so its loads and FMA chains interleave
+#pragma unroll
+      for (int r = 0; r < TT; ++r) {
+        const int i = d - r;
+        if (i < 0 || i >= TT) continue;
+        if (active && !(Nc[r] & R_SKIP)) __builtin_nontemporal_store(Nw[r], &hrow[r][icol[i]]);
+      }
+#pragma unroll
+      for (int r = 0; r < TT; ++r) {
+        D2[r] = D1[r];
+        D1[r] = Nw[r];
+      }
+    }
+    __syncthreads();  // the next plane's staging overwrites the records
+  }
+}
+
+}  // namespace
+
+template <typename T, bool Y2WALL>
+void launch_sweep_rule(const Batch<T> &B, int diag, hipStream_t st) {
+  const int items = B.h_item_off[(size_t)diag * (B.nprob + 1) + B.nprob];
+  if (items == 0) return;
+  const int *off = B.d_item_off + (size_t)diag * (B.nprob + 1);
+#define PDVM_SWEEP_E(D, X, E)                                                                           \
+  hipLaunchKernelGGL((sweep_kernel<T, D, X, Y2WALL, E>), dim3(items), dim3(kWave), 0, st, B.d_geo, off, \
+                     B.nprob, diag)
+#define PDVM_SWEEP_T(D, E)              \
+  if (B.tile_edge <= 4) PDVM_SWEEP_E(D, 4, E); \
+  else PDVM_SWEEP_E(D, 8, E)
+  // EXT: bit 0 psi (2D with tau fed back), bit 1 Shakhov, bit 2 Maxwell walls
+  // (stencil rule 1 only, so never with Y2WALL)
+  if constexpr (!Y2WALL) {
+    if (B.maxwell) {
+      if (B.dim == 2) {
+        if (B.shakhov) { PDVM_SWEEP_T(2, 7); }
+        else if (B.psi) { PDVM_SWEEP_T(2, 5); }
+        else { PDVM_SWEEP_T(2, 4); }
+      } else {
+        if (B.shakhov) { PDVM_SWEEP_T(3, 6); }
+        else { PDVM_SWEEP_T(3, 4); }
+      }
+      return;
+    }
+  }
+  if (B.dim == 2) {
+    if (B.shakhov) { PDVM_SWEEP_T(2, 3); }
+    else if (B.psi) { PDVM_SWEEP_T(2, 1); }
+    else { PDVM_SWEEP_T(2, 0); }
+  } else {
+    if (B.shakhov) { PDVM_SWEEP_T(3, 2); }
+    else { PDVM_SWEEP_T(3, 0); }
+  }
+#undef PDVM_SWEEP_T
+#undef PDVM_SWEEP_E
+}
+
+template <typename T>
+hipError_t launch_sweep(const Batch<T> &B, int diag, hipStream_t st) {
+  if (B.y2wall) launch_sweep_rule<T, true>(B, diag, st);
+  else launch_sweep_rule<T, false>(B, diag, st);
+  return hipGetLastError();
+}
+
+template hipError_t launch_sweep<double>(const Batch<double> &, int, hipStream_t);
+template hipError_t launch_sweep<float>(const Batch<float> &, int, hipStream_t);
+
+}  // namespace pdvm

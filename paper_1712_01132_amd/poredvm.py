@@ -81,7 +81,7 @@ EXPORTED = [
     "pdvm_iterate", "pdvm_get_moments", "pdvm_get_flux", "pdvm_get_state",
     "pdvm_set_state", "pdvm_time_kernels", "pdvm_destroy", "pdvm_last_error",
     "pdvm_batch_create", "pdvm_batch_size", "pdvm_batch_set_initial", "pdvm_batch_iterate",
-    "pdvm_batch_get_moments", "pdvm_batch_get_flux", "pdvm_sweep_schedule",
+    "pdvm_batch_get_moments", "pdvm_batch_get_flux", "pdvm_sweep_schedule", "pdvm_set_wait_limit",
 ]
 
 _lib = None
@@ -125,6 +125,7 @@ def load():
     lib.pdvm_sweep_schedule.restype = ctypes.c_int32
     lib.pdvm_sweep_schedule.argtypes = [vp]
     lib.pdvm_batch_get_flux.argtypes = [vp, ctypes.c_int32, _dp, _dp, _dp]
+    lib.pdvm_set_wait_limit.argtypes = [vp, ctypes.c_double]
     lib.pdvm_destroy.argtypes = [vp]
     lib.pdvm_last_error.restype = ctypes.c_char_p
     lib.pdvm_last_error.argtypes = [vp]
@@ -297,6 +298,10 @@ class Solver:
     def schedule(self):
         """"diagonals", "rows" (agent-scope) or "rows-xcd" (XCD-local row pipeline)."""
         return {0: "diagonals", 1: "rows", 2: "rows-xcd"}[load().pdvm_sweep_schedule(self._h)]
+
+    def set_wait_limit(self, seconds):
+        """Bound on each row-pipeline wait for the upstream row (default 2 s)."""
+        self._check(load().pdvm_set_wait_limit(self._h, float(seconds)))
 
 
 class Batch:
