@@ -163,6 +163,20 @@ int pdvm_set_initial(pdvm_solver *s, const double *rho, const double *u);
 int pdvm_iterate(pdvm_solver *s, int64_t max_iters, double tol, int32_t stop_mode,
                  pdvm_stats *out);
 
+/* pdvm_iterate for callers that cannot allocate (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the same
+ * iterations with the same kernels and results, but no HIP graph is built and
+ * no device or pinned memory is allocated; the kernels' scratch (per-block
+ * partial sums, the row pipeline's progress counters and XCD records) lives in
+ * a static array of the library, 4 MiB per GPU, held until the process ends.
+ * PDVM_E_NOMEM if the solve needs more of it (a problem needs at most 32 KiB
+ * plus 5 bytes per row-pipeline block: about 0.2 MiB at 16384 voxel rows and
+ * 1024 velocities). Calls on one GPU share that array: calls that overlap in
+ * time on one GPU (several host threads or streams) race and must not be made.
+ * Returns and stats as pdvm_iterate. */
+int pdvm_iterate_noalloc(pdvm_solver *s, int64_t max_iters, double tol, int32_t stop_mode,
+                         pdvm_stats *out);
+
 /* Macroscopic fields of the current state (Eq. perturbed_quantities), host
  * arrays of N (rho, tau) or dim*N (u, q) doubles, solid voxels read 0; NULL
  * skips. tau and q are diagnostics (2D: reduced forms with v3 integrated

@@ -18,6 +18,7 @@
 #include <cstddef>
 #include <cstring>
 #include <limits>
+#include <mutex>
 #include <new>
 #include <string>
 #include <vector>
@@ -27,10 +28,41 @@
 
 using namespace pdvm;
 
+// Static device scratch of pdvm_iterate_noalloc (callers that cannot
+// allocate): the moment kernel's per-block partial sums, the row pipeline's
+// progress counters and XCD records, for one solve at a time per GPU. Each GPU
+// holds its own copy until the process ends. The array's name is a host-side
+// stand-in, not a device address: host code uses only the address that
+// hipGetSymbolAddress returns for the current device (scratch_address).
+constexpr size_t kNoAllocScratchBytes = size_t(4) << 20;
+static __device__ __align__(256) unsigned char scratch[kNoAllocScratchBytes];
+
 namespace {
 
 thread_local std::string g_thread_error;
 
+// The device address of `scratch` on device `dev` (that device current), taken
+// once per device; the result (address or error) is kept for later calls.
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void *g_scratch_ptr[kMaxDevices];
+hipError_t g_scratch_err[kMaxDevices];
+bool g_scratch_done[kMaxDevices];
+
+hipError_t scratch_address(int dev, void **out) {
+  *out = nullptr;
+  if (dev < 0 || dev >= kMaxDevices) return hipErrorInvalidDevice;
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_done[dev]) {
+    void *ptr = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+    g_scratch_err[dev] = e;
+    g_scratch_ptr[dev] = e == hipSuccess ? ptr : nullptr;
+    g_scratch_done[dev] = true;
+  }
+  *out = g_scratch_ptr[dev];
+  return g_scratch_err[dev];
+}
 
 void set_thread_error(const char *fmt, ...) {
   char buf[512];
@@ -570,6 +602,13 @@ struct pdvm_solver {
   Batch<float> bf;
   Ctl *host_ctl = nullptr;         // pinned, one per problem
   uint8_t *d_xcc = nullptr;        // device: the XCD of every row-pipeline block (in meta)
+  // pdvm_iterate_noalloc: this GPU's static scratch (null if its address could
+  // not be taken: scratch_err), the regions the batch needs in it, and room for
+  // the per-problem start counters (sized at creation)
+  char *scratch_dev = nullptr;
+  hipError_t scratch_err = hipSuccess;
+  size_t scr_part = 0, scr_prog = 0, scr_xcc = 0, scr_need = 0;
+  std::vector<int64_t> start_iters;
   hipGraphExec_t graph = nullptr;
   int graph_iters = 0;
   bool rows = false;               // the sweep is one row-pipeline launch (2D, single problem)
@@ -763,28 +802,30 @@ int finalize_batch(pdvm_solver *s) {
 }
 
 template <typename T>
-int enqueue_sweep(pdvm_solver *s) {
+int enqueue_sweep(pdvm_solver *s, const Scratch &scr) {
   const Batch<T> &B = batch<T>(s);
   if (s->rows) {
-    HIPCHK(s, launch_sweep_rows<T>(B, s->rows_local, s->stream));
+    HIPCHK(s, launch_sweep_rows<T>(B, s->rows_local, s->stream, scr));
   } else {
     for (int d = 0; d < B.ndiag_max; ++d) HIPCHK(s, launch_sweep<T>(B, d, s->stream));
   }
   return PDVM_OK;
 }
 
+// One iteration: sweep, moments, reduction. `scr`: the kernels' scratch (the
+// problems' own workspaces when empty).
 template <typename T>
-int enqueue_iteration(pdvm_solver *s) {
+int enqueue_iteration(pdvm_solver *s, const Scratch &scr) {
   const Batch<T> &B = batch<T>(s);
-  const int rc = enqueue_sweep<T>(s);
+  const int rc = enqueue_sweep<T>(s, scr);
   if (rc != PDVM_OK) return rc;
-  HIPCHK(s, launch_moments<T>(B, s->stream));
-  HIPCHK(s, launch_reduce<T>(B, s->stream));
+  HIPCHK(s, launch_moments<T>(B, s->stream, scr));
+  HIPCHK(s, launch_reduce<T>(B, s->stream, scr));
   return PDVM_OK;
 }
 
-int enqueue_iteration_any(pdvm_solver *s) {
-  return s->precision == PDVM_FP64 ? enqueue_iteration<double>(s) : enqueue_iteration<float>(s);
+int enqueue_iteration_any(pdvm_solver *s, const Scratch &scr = Scratch{}) {
+  return s->precision == PDVM_FP64 ? enqueue_iteration<double>(s, scr) : enqueue_iteration<float>(s, scr);
 }
 
 int build_graph(pdvm_solver *s) {
@@ -1002,6 +1043,20 @@ int create_common(const pdvm_config *cfgs, int n, void *dev_workspace, size_t ws
       return rc3;
     }
   }
+  // pdvm_iterate_noalloc: this GPU's static scratch (its address is taken
+  // here, once per device) and the regions of it this batch would use
+  {
+    int dev = 0;
+    void *ptr = nullptr;
+    s->scratch_err = hipGetDevice(&dev);
+    if (s->scratch_err == hipSuccess) s->scratch_err = scratch_address(dev, &ptr);
+    s->scratch_dev = (char *)ptr;
+    s->scr_part = 0;
+    s->scr_prog = align256((size_t)s->h_blk_off[n] * 4 * sizeof(double));
+    s->scr_xcc = s->scr_prog + align256((size_t)s->h_row_off[n] * sizeof(int32_t));
+    s->scr_need = s->scr_xcc + align256((size_t)s->h_row_off[n]);
+    s->start_iters.assign(n, 0);
+  }
   *out = s;
   return PDVM_OK;
 }
@@ -1086,6 +1141,73 @@ int iterate_batch(pdvm_solver *s, int64_t max_iters, double tol, int32_t stop_mo
     if (c.fault)
       return s->fail(PDVM_E_HIP, "problem %d: the blocks of a row-pipeline velocity chain ran on different XCDs; the "
                                  "iterate was discarded and the previous state kept", i);
+    if (c.status == -4) worst = PDVM_E_NONFINITE;
+    else if (c.status != 1 && worst == PDVM_OK) worst = PDVM_NOT_CONVERGED;
+  }
+  if (worst == PDVM_E_NONFINITE)
+    return s->fail(PDVM_E_NONFINITE, "residual or permeability became non-finite; the previous state is kept");
+  return worst;
+}
+
+// pdvm_iterate without allocating: no graph (its instantiation allocates);
+// the kernels are enqueued directly, with their scratch in this GPU's static
+// array; host work uses only what the solver allocated at creation.
+int iterate_noalloc(pdvm_solver *s, int64_t max_iters, double tol, int32_t stop_mode, pdvm_stats *out) {
+  if (max_iters < 0 || (stop_mode != PDVM_STOP_FIELD && stop_mode != PDVM_STOP_PAPER_ERR) || std::isnan(tol))
+    return s->fail(PDVM_E_INVAL, "max_iters >= 0, a valid stop mode and a non-NaN tol are required");
+  if (!s->scratch_dev)
+    return s->fail(PDVM_E_HIP, "no device address for the library's static scratch on this GPU: %s",
+                   hipGetErrorString(s->scratch_err));
+  if (s->scr_need > kNoAllocScratchBytes)
+    return s->fail(PDVM_E_NOMEM, "this solve needs %zu bytes of the library's static scratch; it holds %zu (use "
+                                 "pdvm_iterate)", s->scr_need, kNoAllocScratchBytes);
+  const auto t0 = std::chrono::steady_clock::now();
+  int rc = check_not_poisoned(s);
+  if (rc != PDVM_OK) return rc;
+  const int n = s->n();
+  for (int i = 0; i < n; ++i) s->start_iters[i] = s->host_ctl[i].iter;
+  Scratch scr;
+  scr.part = (double *)(s->scratch_dev + s->scr_part);
+  scr.progress = (int32_t *)(s->scratch_dev + s->scr_prog);
+  scr.xcc = (uint8_t *)(s->scratch_dev + s->scr_xcc);
+  rc = arm(s, tol, stop_mode, max_iters);
+  if (rc != PDVM_OK) return rc;
+  // the counters hold whatever an earlier solve on this GPU left: set them
+  // below every stamp of this call
+  if (s->rows) {
+    if (s->precision == PDVM_FP64) HIPCHK(s, launch_progress_reset<double>(s->bd, scr.progress, s->stream));
+    else HIPCHK(s, launch_progress_reset<float>(s->bf, scr.progress, s->stream));
+  }
+  const int64_t poll = std::max(1, s->P[0].check_every);
+  int64_t launched = 0;
+  while (launched < max_iters) {
+    for (int64_t b = 0; b < poll && launched < max_iters; ++b, ++launched) {
+      rc = enqueue_iteration_any(s, scr);
+      if (rc != PDVM_OK) return rc;
+    }
+    rc = read_ctl(s);
+    if (rc != PDVM_OK) return rc;
+    bool all = true;
+    for (int i = 0; i < n; ++i) all = all && s->host_ctl[i].stop;
+    if (all) break;
+  }
+  const double secs = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+  int worst = PDVM_OK;
+  for (int i = 0; i < n; ++i) {
+    const Ctl &c = s->host_ctl[i];
+    if (out) {
+      out[i].iters = c.iter - s->start_iters[i];
+      out[i].total_iters = c.iter;
+      out[i].r = c.r;
+      out[i].err = c.err;
+      out[i].k = c.k;
+      out[i].gp = c.gp;
+      out[i].seconds = secs;
+      out[i].converged = c.status == 1;
+    }
+    if (c.fault)
+      return s->fail(PDVM_E_HIP, "problem %d: a row-pipeline sweep was abandoned; the iterate was discarded and the "
+                                 "previous state kept", i);
     if (c.status == -4) worst = PDVM_E_NONFINITE;
     else if (c.status != 1 && worst == PDVM_OK) worst = PDVM_NOT_CONVERGED;
   }
@@ -1342,6 +1464,11 @@ int pdvm_set_initial(pdvm_solver *s, const double *rho, const double *u) {
 int pdvm_iterate(pdvm_solver *s, int64_t max_iters, double tol, int32_t stop_mode, pdvm_stats *out) {
   int rc = single(s);
   return rc != PDVM_OK ? rc : iterate_batch(s, max_iters, tol, stop_mode, out);
+}
+
+int pdvm_iterate_noalloc(pdvm_solver *s, int64_t max_iters, double tol, int32_t stop_mode, pdvm_stats *out) {
+  int rc = single(s);
+  return rc != PDVM_OK ? rc : iterate_noalloc(s, max_iters, tol, stop_mode, out);
 }
 
 int pdvm_get_moments(pdvm_solver *s, double *rho, double *u, double *tau, double *q) {

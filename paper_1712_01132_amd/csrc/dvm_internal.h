@@ -135,6 +135,18 @@ struct Batch {
   int row_stride = 8;
 };
 
+// Scratch memory of the iteration's kernels: the moment kernel's per-block
+// partial sums, the row pipeline's progress counters and per-block XCD
+// records. A null member means each problem's own, in its workspace
+// (Geo::part, progress, xcc_seen). Otherwise it is one region for the whole
+// batch: problem p's partial sums at part + 4 blk_off[p], its counters and XCD
+// records at progress + row_off[p] and xcc + row_off[p].
+struct Scratch {
+  double *part = nullptr;
+  int32_t *progress = nullptr;
+  uint8_t *xcc = nullptr;
+};
+
 // Kernel launchers (dvm_sweep_diag.hip, dvm_sweep_rows.hip, dvm_iter.hip).
 // All enqueue on `st`.
 template <typename T>
@@ -143,13 +155,18 @@ hipError_t launch_sweep(const Batch<T> &B, int diag, hipStream_t st);
 // of bands of band_waves(tile edge) tile rows per block; `local`: every
 // chain's bands run on one XCD (checked with launch_xcd_probe).
 template <typename T>
-hipError_t launch_sweep_rows(const Batch<T> &B, bool local, hipStream_t st);
+hipError_t launch_sweep_rows(const Batch<T> &B, bool local, hipStream_t st, const Scratch &scr = Scratch{});
+// The row pipeline's progress counters of a batch-wide scratch region, set
+// below every stamp the next sweep of each problem publishes (its seq *
+// ntile0), as a fill kernel (no memset node when the caller captures a graph).
+template <typename T>
+hipError_t launch_progress_reset(const Batch<T> &B, int32_t *progress, hipStream_t st);
 // out[b] = the XCD that block b of a `blocks`-block grid runs on.
 hipError_t launch_xcd_probe(uint32_t *out, int blocks, int threads, hipStream_t st);
 template <typename T>
-hipError_t launch_moments(const Batch<T> &B, hipStream_t st);
+hipError_t launch_moments(const Batch<T> &B, hipStream_t st, const Scratch &scr = Scratch{});
 template <typename T>
-hipError_t launch_reduce(const Batch<T> &B, hipStream_t st);
+hipError_t launch_reduce(const Batch<T> &B, hipStream_t st, const Scratch &scr = Scratch{});
 template <typename T>
 hipError_t launch_arm(const Batch<T> &B, double tol, int mode, int64_t max_iters, hipStream_t st);
 template <typename T>

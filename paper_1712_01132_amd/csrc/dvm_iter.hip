@@ -61,7 +61,7 @@ using vec2_t = T __attribute__((ext_vector_type(2)));
 // W |v_j| (|v|^2 - 5/2)), stored as the Shakhov source nu (4/5)(1 - Pr) q_j.
 template <typename T, int DIM, int NS, bool PAIR, bool SH>
 __global__ void __launch_bounds__(kMomBlock)
-    moments_kernel(const Geo<T> *__restrict__ G, const int *__restrict__ blk_off, int nprob) {
+    moments_kernel(const Geo<T> *__restrict__ G, const int *__restrict__ blk_off, int nprob, double *part_scr) {
   const int pb = nprob > 1 ? owner_of(blk_off, nprob, blockIdx.x) : 0;
   const Geo<T> &g = G[pb];
   const int blk = nprob > 1 ? blockIdx.x - blk_off[pb] : blockIdx.x;
@@ -77,7 +77,7 @@ __global__ void __launch_bounds__(kMomBlock)
   const gptr<T> wall_n = as_global(np ? g.wall[1] : g.wall[0]);
   const gptr<const int32_t> fidx = as_global(g.fluid_idx);
   const gptr<const double> wq = as_global(g.wq);
-  const gptr<double> part = as_global(g.part);
+  const gptr<double> part = as_global(part_scr ? part_scr + 4 * (int64_t)(nprob > 1 ? blk_off[pb] : 0) : g.part);
   const int64_t N = g.N, Kpad = g.Kpad, nf = g.nfluid;
   const int Ko = g.Ko, Ko_pad = g.Ko_pad, tau_fb = g.tau_fb, mom_blocks = g.mom_blocks;
   const double nu = g.nu, Dj[3] = {g.D[0], g.D[1], g.D[2]};
@@ -240,12 +240,14 @@ __device__ void resolve(Geo<T> &g, int par, int run) {
 }
 
 template <typename T>
-__global__ void __launch_bounds__(256) reduce_kernel(Geo<T> *__restrict__ G) {
+__global__ void __launch_bounds__(256)
+    reduce_kernel(Geo<T> *__restrict__ G, const int *__restrict__ blk_off, const int *__restrict__ row_off,
+                  double *part_scr, uint8_t *xcc_scr) {
   Geo<T> &g = G[blockIdx.x];
   Ctl *ctl = g.ctl;
   if (ctl->stop) return;
-  const double *part = g.part;
-  const uint8_t *xcc_seen = g.xcc_seen;
+  const double *part = part_scr ? part_scr + 4 * (int64_t)blk_off[blockIdx.x] : g.part;
+  const uint8_t *xcc_seen = g.xcc_seen && xcc_scr ? xcc_scr + row_off[blockIdx.x] : g.xcc_seen;
   const int nblocks = g.mom_blocks;
   const int64_t N = g.N;
   __shared__ double sa[256], sb[256], sc[256];
@@ -470,19 +472,19 @@ int grid_for(int64_t work, int block) {
 }  // namespace
 
 template <typename T, int D, int S, bool P>
-void launch_moments_as(const Batch<T> &B, int blocks, hipStream_t st) {
+void launch_moments_as(const Batch<T> &B, int blocks, hipStream_t st, double *part) {
   if (B.shakhov)
     hipLaunchKernelGGL((moments_kernel<T, D, S, P, true>), dim3(blocks), dim3(kMomBlock), 0, st, B.d_geo, B.d_blk_off,
-                       B.nprob);
+                       B.nprob, part);
   else
     hipLaunchKernelGGL((moments_kernel<T, D, S, P, false>), dim3(blocks), dim3(kMomBlock), 0, st, B.d_geo, B.d_blk_off,
-                       B.nprob);
+                       B.nprob, part);
 }
 
 template <typename T>
-hipError_t launch_moments(const Batch<T> &B, hipStream_t st) {
+hipError_t launch_moments(const Batch<T> &B, hipStream_t st, const Scratch &scr) {
   const int blocks = B.h_blk_off[B.nprob];
-#define PDVM_MOM(D, S, P) launch_moments_as<T, D, S, P>(B, blocks, st)
+#define PDVM_MOM(D, S, P) launch_moments_as<T, D, S, P>(B, blocks, st, scr.part)
   // paired slots (2 per lane and 128-slot block) in 2D: 9 % faster in FP32 on
   // the 512^2 rock, unchanged in FP64; slower on the 96^3 pack, so not in 3D
   // pairs only where they cover the octant with no more slots than single
@@ -516,8 +518,9 @@ hipError_t launch_moments(const Batch<T> &B, hipStream_t st) {
 }
 
 template <typename T>
-hipError_t launch_reduce(const Batch<T> &B, hipStream_t st) {
-  hipLaunchKernelGGL((reduce_kernel<T>), dim3(B.nprob), dim3(256), 0, st, const_cast<Geo<T> *>(B.d_geo));
+hipError_t launch_reduce(const Batch<T> &B, hipStream_t st, const Scratch &scr) {
+  hipLaunchKernelGGL((reduce_kernel<T>), dim3(B.nprob), dim3(256), 0, st, const_cast<Geo<T> *>(B.d_geo), B.d_blk_off,
+                     B.d_row_off, scr.part, scr.xcc);
   return hipGetLastError();
 }
 
@@ -568,10 +571,10 @@ hipError_t launch_face_copy(const Geo<T> &g, int axis, int r, T *buf, int to_buf
   return hipGetLastError();
 }
 
-template hipError_t launch_moments<double>(const Batch<double> &, hipStream_t);
-template hipError_t launch_moments<float>(const Batch<float> &, hipStream_t);
-template hipError_t launch_reduce<double>(const Batch<double> &, hipStream_t);
-template hipError_t launch_reduce<float>(const Batch<float> &, hipStream_t);
+template hipError_t launch_moments<double>(const Batch<double> &, hipStream_t, const Scratch &);
+template hipError_t launch_moments<float>(const Batch<float> &, hipStream_t, const Scratch &);
+template hipError_t launch_reduce<double>(const Batch<double> &, hipStream_t, const Scratch &);
+template hipError_t launch_reduce<float>(const Batch<float> &, hipStream_t, const Scratch &);
 template hipError_t launch_arm<double>(const Batch<double> &, double, int, int64_t, hipStream_t);
 template hipError_t launch_ctl_gather<double>(const Batch<double> &, Ctl *, hipStream_t);
 template hipError_t launch_ctl_gather<float>(const Batch<float> &, Ctl *, hipStream_t);

@@ -50,7 +50,8 @@ namespace {
 // walls (never with Y2WALL).
 template <typename T, int TT, bool Y2WALL, bool LOCAL, int NW, int EXT>
 __global__ void __launch_bounds__(kWave * NW)
-    sweep_rows_kernel(const Geo<T> *__restrict__ G, const int *__restrict__ row_off, int nprob, int stride) {
+    sweep_rows_kernel(const Geo<T> *__restrict__ G, const int *__restrict__ row_off, int nprob, int stride,
+                      int32_t *__restrict__ prog_scr, uint8_t *__restrict__ xcc_scr) {
   constexpr int DIM = 2;
   constexpr int NC = TT * TT;
   constexpr bool TAU = (EXT & 1) != 0, SH = (EXT & 2) != 0, MW = (EXT & 4) != 0;
@@ -81,7 +82,9 @@ __global__ void __launch_bounds__(kWave * NW)
   const gptr<const T> srct = as_global(G_.srctcur);
   const gptr<const T> wall = as_global(G_.wallcur);
   const gptr<const uint32_t> flags = as_global(G_.flags);
-  const gptr<int32_t> progress = as_global(G_.progress);
+  const int row0 = nprob > 1 ? row_off[p] : 0;
+  // counters and XCD records: the problem's own, or its range of a scratch region
+  const gptr<int32_t> progress = as_global(prog_scr ? prog_scr + row0 : G_.progress);
   const gptr<int32_t> fault = as_global(&G_.ctl->fault);
   const uint32_t seq = (uint32_t)G_.seq;
   const int n0 = dm.n[0], n1 = dm.n[1];
@@ -98,7 +101,7 @@ __global__ void __launch_bounds__(kWave * NW)
     // unless every block of this chain ran on one XCD (the LOCAL protocol's premise)
     uint32_t xcc;
     asm volatile("s_getreg_b32 %0, hwreg(HW_REG_XCC_ID)" : "=s"(xcc));
-    as_global(G_.xcc_seen)[local_b] = (uint8_t)(xcc & 0xFFu);
+    as_global(xcc_scr ? xcc_scr + row0 : G_.xcc_seen)[local_b] = (uint8_t)(xcc & 0xFFu);
   }
   // the wavefront index, held in a scalar register so that everything that
   // depends on the row is wavefront-uniform to the compiler
@@ -504,10 +507,11 @@ __global__ void __launch_bounds__(kWave * NW)
 }  // namespace
 
 template <typename T, bool LOCAL>
-void launch_rows_local(const Batch<T> &B, dim3 grid, hipStream_t st) {
+void launch_rows_local(const Batch<T> &B, dim3 grid, hipStream_t st, const Scratch &scr) {
 #define PDVM_ROWS(TTV, Y2, E)                                                                   \
   hipLaunchKernelGGL((sweep_rows_kernel<T, TTV, Y2, LOCAL, band_waves(TTV), E>), grid,         \
-                     dim3(kWave * band_waves(TTV)), 0, st, B.d_geo, B.d_row_off, B.nprob, B.row_stride)
+                     dim3(kWave * band_waves(TTV)), 0, st, B.d_geo, B.d_row_off, B.nprob, B.row_stride, \
+                     scr.progress, scr.xcc)
   // EXT: bit 0 tau fed back (psi), bit 1 Shakhov, bit 2 Maxwell walls (rule 1 only)
 #define PDVM_ROWS_EXT(TTV, Y2)                                   \
   if (B.shakhov) PDVM_ROWS(TTV, Y2, 3);                          \
@@ -532,10 +536,26 @@ void launch_rows_local(const Batch<T> &B, dim3 grid, hipStream_t st) {
 }
 
 template <typename T>
-hipError_t launch_sweep_rows(const Batch<T> &B, bool local, hipStream_t st) {
+hipError_t launch_sweep_rows(const Batch<T> &B, bool local, hipStream_t st, const Scratch &scr) {
   const dim3 grid((unsigned)B.h_row_off[B.nprob]);
-  if (local) launch_rows_local<T, true>(B, grid, st);
-  else launch_rows_local<T, false>(B, grid, st);
+  if (local) launch_rows_local<T, true>(B, grid, st, scr);
+  else launch_rows_local<T, false>(B, grid, st, scr);
+  return hipGetLastError();
+}
+
+namespace {
+template <typename T>
+__global__ void progress_reset_kernel(const Geo<T> *__restrict__ G, const int *__restrict__ row_off, int32_t *prog) {
+  const int p = blockIdx.x;
+  const int32_t below = (int32_t)((uint32_t)G[p].seq * (uint32_t)G[p].ntile[0]);
+  for (int i = row_off[p] + threadIdx.x; i < row_off[p + 1]; i += blockDim.x) prog[i] = below;
+}
+}  // namespace
+
+template <typename T>
+hipError_t launch_progress_reset(const Batch<T> &B, int32_t *progress, hipStream_t st) {
+  hipLaunchKernelGGL((progress_reset_kernel<T>), dim3((unsigned)B.nprob), dim3(256), 0, st, B.d_geo, B.d_row_off,
+                     progress);
   return hipGetLastError();
 }
 
@@ -551,7 +571,9 @@ hipError_t launch_xcd_probe(uint32_t *out, int blocks, int threads, hipStream_t 
   return hipGetLastError();
 }
 
-template hipError_t launch_sweep_rows<double>(const Batch<double> &, bool, hipStream_t);
-template hipError_t launch_sweep_rows<float>(const Batch<float> &, bool, hipStream_t);
+template hipError_t launch_sweep_rows<double>(const Batch<double> &, bool, hipStream_t, const Scratch &);
+template hipError_t launch_sweep_rows<float>(const Batch<float> &, bool, hipStream_t, const Scratch &);
+template hipError_t launch_progress_reset<double>(const Batch<double> &, int32_t *, hipStream_t);
+template hipError_t launch_progress_reset<float>(const Batch<float> &, int32_t *, hipStream_t);
 
 }  // namespace pdvm

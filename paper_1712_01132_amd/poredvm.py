@@ -82,6 +82,7 @@ EXPORTED = [
     "pdvm_set_state", "pdvm_time_kernels", "pdvm_destroy", "pdvm_last_error",
     "pdvm_batch_create", "pdvm_batch_size", "pdvm_batch_set_initial", "pdvm_batch_iterate",
     "pdvm_batch_get_moments", "pdvm_batch_get_flux", "pdvm_sweep_schedule", "pdvm_set_wait_limit",
+    "pdvm_iterate_noalloc",
 ]
 
 _lib = None
@@ -110,6 +111,8 @@ def load():
     lib.pdvm_set_initial.argtypes = [vp, _dp, _dp]
     lib.pdvm_iterate.argtypes = [vp, ctypes.c_int64, ctypes.c_double, ctypes.c_int32,
                                  ctypes.POINTER(PdvmStats)]
+    lib.pdvm_iterate_noalloc.argtypes = [vp, ctypes.c_int64, ctypes.c_double, ctypes.c_int32,
+                                         ctypes.POINTER(PdvmStats)]
     lib.pdvm_get_moments.argtypes = [vp, _dp, _dp, _dp, _dp]
     lib.pdvm_get_flux.argtypes = [vp, _dp, _dp, _dp]
     lib.pdvm_get_state.argtypes = [vp, vp, ctypes.POINTER(ctypes.c_size_t)]
@@ -256,6 +259,16 @@ class Solver:
         st = PdvmStats()
         mode = {"field": PDVM_STOP_FIELD, "paper": PDVM_STOP_PAPER_ERR}[stop_mode]
         rc = self._check(load().pdvm_iterate(self._h, int(max_iters), float(tol), mode, ctypes.byref(st)),
+                         ok=(PDVM_OK, PDVM_NOT_CONVERGED))
+        return {"converged": rc == PDVM_OK, "iters": st.iters, "total_iters": st.total_iters,
+                "r": st.r, "err": st.err, "k": st.k, "Gp": st.gp, "seconds": st.seconds}
+
+    def iterate_noalloc(self, max_iters, tol=0.0, stop_mode="field"):
+        """iterate() through pdvm_iterate_noalloc: no allocation, the kernels'
+        scratch in the library's static per-GPU array."""
+        st = PdvmStats()
+        mode = {"field": PDVM_STOP_FIELD, "paper": PDVM_STOP_PAPER_ERR}[stop_mode]
+        rc = self._check(load().pdvm_iterate_noalloc(self._h, int(max_iters), float(tol), mode, ctypes.byref(st)),
                          ok=(PDVM_OK, PDVM_NOT_CONVERGED))
         return {"converged": rc == PDVM_OK, "iters": st.iters, "total_iters": st.total_iters,
                 "r": st.r, "err": st.err, "k": st.k, "Gp": st.gp, "seconds": st.seconds}
