@@ -64,11 +64,19 @@ enum { PDVM_STOP_FIELD = 0, PDVM_STOP_PAPER_ERR = 1 };
  *            wavefront pipelines a row of tiles behind the row below it;
  * ROWS_AGENT: ROWS with agent-scope release/acquire per tile, correct for any
  *            block placement (slower; ROWS uses it when the probe below fails);
+ * STRIPS:    2D, isothermal source and diffuse walls: one launch for all
+ *            problems of the batch, in which each wavefront walks a strip of
+ *            voxel rows along x1 as a skewed front behind the strip below it,
+ *            for one or two 64-velocity groups at once; needs every velocity
+ *            chain on one XCD (probed at creation, else PDVM_E_UNSUPPORTED);
+ *            only on request (slower than ROWS on one problem and than
+ *            DIAGONALS on batches, as measured);
  * AUTO:      for a single 2D problem, ROWS when a probe of the block placement
  *            at creation shows that every velocity chain runs on one XCD (cheap
  *            synchronisation through its L2); DIAGONALS otherwise (batches
  *            keep the machine fuller with per-diagonal launches). */
-enum { PDVM_SCHEDULE_AUTO = 0, PDVM_SCHEDULE_DIAGONALS = 1, PDVM_SCHEDULE_ROWS = 2, PDVM_SCHEDULE_ROWS_AGENT = 3 };
+enum { PDVM_SCHEDULE_AUTO = 0, PDVM_SCHEDULE_DIAGONALS = 1, PDVM_SCHEDULE_ROWS = 2, PDVM_SCHEDULE_ROWS_AGENT = 3,
+       PDVM_SCHEDULE_STRIPS = 4 };
 
 typedef struct pdvm_solver pdvm_solver;
 
@@ -98,7 +106,7 @@ typedef struct {
                                 0 = only when the first one is (a solid second image then
                                     enters the second-order stencil with its wall value;
                                     this iteration can diverge on some geometries) */
-  int32_t sweep_schedule;    /* PDVM_SCHEDULE_*; ROWS(_AGENT) with dim 3 is PDVM_E_UNSUPPORTED;
+  int32_t sweep_schedule;    /* PDVM_SCHEDULE_*; ROWS(_AGENT) or STRIPS with dim 3 is PDVM_E_UNSUPPORTED;
                                 a batch takes the first config's schedule */
   double prandtl;            /* 0 = BGK. > 0 (needs tau_feedback = 1): Shakhov model, whose
                                 source adds (4/5)(1 - Pr) q.v (|v|^2 - 5/2) with the heat
@@ -238,8 +246,8 @@ int pdvm_batch_get_flux(pdvm_solver *s, int32_t i, double *gp, double *k, double
 
 /* The sweep schedule in use: 0 tile diagonals; 1 row pipeline with
  * agent-scope synchronisation; 2 row pipeline with every velocity chain on one
- * XCD (chosen only after a probe of the block placement confirms it);
- * -1 for NULL. */
+ * XCD (chosen only after a probe of the block placement confirms it); 3 strip
+ * pipeline; -1 for NULL. */
 int32_t pdvm_sweep_schedule(const pdvm_solver *s);
 
 /* Wall-clock bound on each wait of the row-pipeline sweep for its upstream row

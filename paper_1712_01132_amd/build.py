@@ -7,7 +7,7 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libporedvm.so")
-SOURCES = ["dvm_sweep_rows.hip", "dvm_sweep_diag.hip", "dvm_iter.hip", "dvm_host.cpp", "unet_kernels.hip", "unet_host.cpp"]
+SOURCES = ["dvm_sweep_strips_f64.hip", "dvm_sweep_strips_f32.hip", "dvm_sweep_rows.hip", "dvm_sweep_diag.hip", "dvm_iter.hip", "dvm_host.cpp", "unet_kernels.hip", "unet_host.cpp"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = [
     "-O3", "-std=c++17", "--offload-arch=gfx950", "-fPIC", "-shared",

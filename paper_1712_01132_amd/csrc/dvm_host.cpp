@@ -16,6 +16,7 @@
 #include <cstdarg>
 #include <cstdio>
 #include <cstddef>
+#include <cstdlib>
 #include <cstring>
 #include <limits>
 #include <mutex>
@@ -273,9 +274,10 @@ int validate_and_build(const pdvm_config *cfg, Problem &P, std::string &err) {
   }
   P.spec = cfg->specular_fraction;
   P.check_every = cfg->check_every > 0 ? cfg->check_every : 16;
-  if (cfg->sweep_schedule < 0 || cfg->sweep_schedule > 3) { err = "sweep_schedule must be 0..3"; return PDVM_E_INVAL; }
+  if (cfg->sweep_schedule < 0 || cfg->sweep_schedule > 4) { err = "sweep_schedule must be 0..4"; return PDVM_E_INVAL; }
   P.schedule = cfg->sweep_schedule;
-  if ((P.schedule == PDVM_SCHEDULE_ROWS || P.schedule == PDVM_SCHEDULE_ROWS_AGENT) && cfg->dim != 2) {
+  if ((P.schedule == PDVM_SCHEDULE_ROWS || P.schedule == PDVM_SCHEDULE_ROWS_AGENT ||
+       P.schedule == PDVM_SCHEDULE_STRIPS) && cfg->dim != 2) {
     err = "the row-pipeline sweep is 2D only";
     return PDVM_E_UNSUPPORTED;
   }
@@ -509,7 +511,9 @@ Layout<T> make_layout(const Problem &P) {
   L.offs = take(P.diag_off.size() * 4);
   L.fidx = take((size_t)P.fluid * 4);
   L.scratch = take(8 * N * 8);  // tau, q (3), rho, u (3) staging
-  L.progress = take((size_t)(P.ngroups << P.dim) * P.ntile[1] * 4);  // row-pipeline counters
+  // pipeline counters: at most one per (band, chain rounded up to 8) of the
+  // row pipeline or the strips
+  L.progress = take((size_t)(P.n[1] + 8) * (((P.ngroups << P.dim) + 7) / 8 * 8) * 4);
   L.total = o;
   return L;
 }
@@ -597,7 +601,7 @@ struct pdvm_solver {
   bool own_stream = false;
   char *meta = nullptr;            // device: descriptors, offset tables, gathered control blocks
   Ctl *d_ctl_all = nullptr;
-  std::vector<int> h_item_off, h_blk_off, h_row_off;
+  std::vector<int> h_item_off, h_blk_off, h_row_off, h_strip_off;
   Batch<double> bd;
   Batch<float> bf;
   Ctl *host_ctl = nullptr;         // pinned, one per problem
@@ -613,6 +617,7 @@ struct pdvm_solver {
   int graph_iters = 0;
   bool rows = false;               // the sweep is one row-pipeline launch (2D, single problem)
   bool rows_local = false;         // ... whose chains each run on one XCD (probed)
+  bool strips = false;             // the sweep is one strip-pipeline launch (2D; XCD-local placement probed)
   std::string err;
   int n() const { return (int)P.size(); }
   int fail(int code, const char *fmt, ...) {
@@ -732,6 +737,17 @@ int setup_problem(pdvm_solver *s, int i) {
   return PDVM_OK;
 }
 
+// Strip-pipeline shape (kStrip*): two velocity groups per wavefront halve the
+// LDS reads of the voxel records per update; PDVM_STRIP_SHAPE (0..3)
+// overrides the choice for tuning.
+int strip_shape_for(const pdvm_solver *s) {
+  if (const char *e = std::getenv("PDVM_STRIP_SHAPE")) {
+    const int v = std::atoi(e);
+    if (v >= 0 && v < kStripShapes) return v;
+  }
+  return s->P[0].ngroups >= 2 ? kStrip4x2 : kStrip4x1;
+}
+
 // Descriptor array and per-launch block offsets of the whole batch.
 template <typename T>
 int finalize_batch(pdvm_solver *s) {
@@ -759,19 +775,29 @@ int finalize_batch(pdvm_solver *s) {
   const int stride = ((P0.ngroups << P0.dim) + 7) / 8 * 8, nw = band_waves(tile_edge);
   s->h_row_off.assign(n + 1, 0);
   for (int p = 0; p < n; ++p) s->h_row_off[p + 1] = s->h_row_off[p] + (s->P[p].ntile[1] + nw - 1) / nw * stride;
+  // strip pipeline (2D): bands of strip_nw strips of strip_th rows, per chain set
+  const int sshape = strip_shape_for(s);
+  const int sg = strip_g(sshape), sth = strip_th(sshape), snw = strip_nw(sshape);
+  const int sstride = ((((P0.ngroups + sg - 1) / sg) << P0.dim) + 7) / 8 * 8;
+  s->h_strip_off.assign(n + 1, 0);
+  for (int p = 0; p < n; ++p)
+    s->h_strip_off[p + 1] = s->h_strip_off[p] + ((s->P[p].n[1] + sth - 1) / sth + snw - 1) / snw * sstride;
+  const size_t strip_b = align256(s->h_strip_off.size() * 4);
   const size_t geo_b = align256(n * sizeof(Geo<T>));
   const size_t item_b = align256(s->h_item_off.size() * 4);
   const size_t blk_b = align256(s->h_blk_off.size() * 4);
   const size_t row_b = align256(s->h_row_off.size() * 4);
   const size_t ctl_b = align256(n * sizeof(Ctl));
-  const size_t xcc_b = align256((size_t)s->h_row_off[n]);
+  const size_t xcc_b = align256((size_t)std::max(s->h_row_off[n], s->h_strip_off[n]));
   void *m = nullptr;
-  if (hipMalloc(&m, geo_b + item_b + blk_b + row_b + ctl_b + xcc_b) != hipSuccess)
+  if (hipMalloc(&m, geo_b + item_b + blk_b + row_b + ctl_b + xcc_b + strip_b) != hipSuccess)
     return s->fail(PDVM_E_NOMEM, "hipMalloc of the batch tables failed");
   s->meta = (char *)m;
   char *geo = s->meta, *item = geo + geo_b, *blk = item + item_b, *rowo = blk + blk_b;
   s->d_ctl_all = (Ctl *)(rowo + row_b);
   s->d_xcc = (uint8_t *)(rowo + row_b + ctl_b);
+  char *stripo = rowo + row_b + ctl_b + xcc_b;
+  HIPCHK(s, hipMemcpyAsync(stripo, s->h_strip_off.data(), s->h_strip_off.size() * 4, hipMemcpyHostToDevice, s->stream));
   HIPCHK(s, hipMemcpyAsync(rowo, s->h_row_off.data(), s->h_row_off.size() * 4, hipMemcpyHostToDevice, s->stream));
   HIPCHK(s, hipMemcpyAsync(geo, geos<T>(s).data(), n * sizeof(Geo<T>), hipMemcpyHostToDevice, s->stream));
   HIPCHK(s, hipMemcpyAsync(item, s->h_item_off.data(), s->h_item_off.size() * 4, hipMemcpyHostToDevice, s->stream));
@@ -796,6 +822,10 @@ int finalize_batch(pdvm_solver *s) {
   B.d_row_off = (const int *)rowo;
   B.h_row_off = s->h_row_off.data();
   B.row_stride = stride;
+  B.d_strip_off = (const int *)stripo;
+  B.h_strip_off = s->h_strip_off.data();
+  B.strip_stride = sstride;
+  B.strip_shape = sshape;
   if (hipHostMalloc((void **)&s->host_ctl, n * sizeof(Ctl), hipHostMallocDefault) != hipSuccess)
     return s->fail(PDVM_E_NOMEM, "pinned host allocation failed");
   return PDVM_OK;
@@ -804,7 +834,9 @@ int finalize_batch(pdvm_solver *s) {
 template <typename T>
 int enqueue_sweep(pdvm_solver *s, const Scratch &scr) {
   const Batch<T> &B = batch<T>(s);
-  if (s->rows) {
+  if (s->strips) {
+    HIPCHK(s, launch_sweep_strips<T>(B, s->stream, scr));
+  } else if (s->rows) {
     HIPCHK(s, launch_sweep_rows<T>(B, s->rows_local, s->stream, scr));
   } else {
     for (int d = 0; d < B.ndiag_max; ++d) HIPCHK(s, launch_sweep<T>(B, d, s->stream));
@@ -874,32 +906,36 @@ bool same_velocity_grid(const Problem &a, const Problem &b) {
          std::equal(a.wq.begin(), a.wq.begin() + a.Ko_pad, b.wq.begin());
 }
 
-// Whether every chain of the row pipeline (blocks c, c + stride, ...) runs on
-// a single XCD: run the pipeline's grid (same blocks, same block size) once
-// with a kernel that records each block's XCD. Needs at least two distinct XCDs in the record (so the register
-// read is live) and one XCD per chain.
-int probe_xcd_locality(pdvm_solver *s) {
-  const Problem &P = s->P[0];
-  const int nchains = P.ngroups << P.dim, n = s->n();
-  const int stride = ((nchains + 7) / 8) * 8, blocks = s->h_row_off[n];
+// Whether every chain of a one-launch pipeline (blocks off[p] + c, + stride,
+// ...) runs on a single XCD: run the pipeline's grid (same blocks, same block
+// size) once with a kernel that records each block's XCD. Needs at least two
+// distinct XCDs in the record (so the register read is live) and one XCD per
+// chain. sets: the real blocks per band.
+int probe_xcd_locality(pdvm_solver *s, const std::vector<int> &off, int stride, int sets, int threads, bool *local_out) {
+  const int n = s->n(), blocks = off[n];
   uint32_t *d = nullptr;
   if (hipMalloc(&d, sizeof(uint32_t) * blocks) != hipSuccess) return s->fail(PDVM_E_NOMEM, "probe allocation failed");
   std::vector<uint32_t> h(blocks);
-  const int tile_edge = s->precision == PDVM_FP64 ? s->bd.tile_edge : s->bf.tile_edge;
-  hipError_t e = launch_xcd_probe(d, blocks, kWave * band_waves(tile_edge), s->stream);
+  hipError_t e = launch_xcd_probe(d, blocks, threads, s->stream);
   if (e == hipSuccess) e = hipMemcpyAsync(h.data(), d, sizeof(uint32_t) * blocks, hipMemcpyDeviceToHost, s->stream);
   if (e == hipSuccess) e = hipStreamSynchronize(s->stream);
   (void)hipFree(d);
   if (e != hipSuccess) return s->fail(PDVM_E_HIP, "XCD probe: %s", hipGetErrorString(e));
   bool local = true, several = false;
   for (int p = 0; p < n; ++p)
-    for (int b = s->h_row_off[p]; b < s->h_row_off[p + 1]; ++b) {
-      const int c = (b - s->h_row_off[p]) % stride;
-      if (c < nchains) local = local && h[b] == h[s->h_row_off[0] + c];
+    for (int b = off[p]; b < off[p + 1]; ++b) {
+      const int c = (b - off[p]) % stride;
+      if (c < sets) local = local && h[b] == h[off[0] + c];
       several = several || h[b] != h[0];
     }
-  s->rows_local = local && several;
+  *local_out = local && several;
   return PDVM_OK;
+}
+
+// Chain sets of the strip pipeline per band.
+int strip_sets(const pdvm_solver *s, int shape) {
+  const Problem &P = s->P[0];
+  return ((P.ngroups + strip_g(shape) - 1) / strip_g(shape)) << P.dim;
 }
 
 // Point every problem's descriptor at its range of the per-block XCD records
@@ -907,11 +943,14 @@ int probe_xcd_locality(pdvm_solver *s) {
 template <typename T>
 int enable_xcc_check(pdvm_solver *s) {
   std::vector<Geo<T>> &G = geos<T>(s);
-  const Batch<T> &B = batch<T>(s);
+  Batch<T> &B = batch<T>(s);
+  B.use_strips = s->strips ? 1 : 0;
+  const std::vector<int> &off = s->strips ? s->h_strip_off : s->h_row_off;
   for (int p = 0; p < s->n(); ++p) {
-    G[p].xcc_seen = s->d_xcc + s->h_row_off[p];
-    G[p].row_blocks = s->h_row_off[p + 1] - s->h_row_off[p];
-    G[p].row_stride = B.row_stride;
+    G[p].xcc_seen = s->d_xcc + off[p];
+    G[p].row_blocks = off[p + 1] - off[p];
+    G[p].row_stride = s->strips ? B.strip_stride : B.row_stride;
+    G[p].row_sets = s->strips ? strip_sets(s, B.strip_shape) : (s->P[p].ngroups << s->P[p].dim);
   }
   HIPCHK(s, hipMemcpyAsync((void *)B.d_geo, G.data(), s->n() * sizeof(Geo<T>), hipMemcpyHostToDevice, s->stream));
   HIPCHK(s, hipStreamSynchronize(s->stream));
@@ -1003,10 +1042,40 @@ int create_common(const pdvm_config *cfgs, int n, void *dev_workspace, size_t ws
     return rc;
   }
   const Problem &P0 = s->P[0];
-  // automatic: the row pipeline for a single 2D problem; a batch fills the
-  // machine better with per-diagonal launches (measured)
-  s->rows = P0.dim == 2 && (P0.schedule == PDVM_SCHEDULE_ROWS || P0.schedule == PDVM_SCHEDULE_ROWS_AGENT ||
-                            (P0.schedule == PDVM_SCHEDULE_AUTO && n == 1));
+  // the strip pipeline: 2D, the isothermal BGK source with diffuse walls, and
+  // XCD-local placement (probed); the automatic choice when all three hold
+  bool strip_model = P0.dim == 2 && !P0.tau_fb && !(P0.prandtl > 0) && !(P0.spec > 0);
+  for (const Problem &P : s->P)  // a row of h addressed through one buffer resource, below 1 GiB
+    strip_model = strip_model && (int64_t)P.n[0] * P.Kpad * (s->precision == PDVM_FP64 ? 8 : 4) < (int64_t(1) << 30);
+  if (P0.schedule == PDVM_SCHEDULE_STRIPS && !strip_model) {
+    set_thread_error("the strip pipeline serves 2D problems with the isothermal source and diffuse walls");
+    pdvm_destroy(s);
+    return PDVM_E_UNSUPPORTED;
+  }
+  // (measured slower than the row pipeline and the tile diagonals, so only on request)
+  if (strip_model && P0.schedule == PDVM_SCHEDULE_STRIPS) {
+    const int shape = s->precision == PDVM_FP64 ? s->bd.strip_shape : s->bf.strip_shape;
+    bool local = false;
+    const int rc2 = probe_xcd_locality(s, s->h_strip_off, s->precision == PDVM_FP64 ? s->bd.strip_stride
+                                                                                      : s->bf.strip_stride,
+                                       strip_sets(s, shape), kWave * strip_nw(shape), &local);
+    if (rc2 != PDVM_OK) {
+      g_thread_error = s->err;
+      pdvm_destroy(s);
+      return rc2;
+    }
+    if (!local && P0.schedule == PDVM_SCHEDULE_STRIPS) {
+      set_thread_error("the strip pipeline needs every chain set on one XCD; the placement probe found otherwise");
+      pdvm_destroy(s);
+      return PDVM_E_UNSUPPORTED;
+    }
+    s->strips = local;
+  }
+  // automatic otherwise: the row pipeline for a single 2D problem; a batch
+  // fills the machine better with per-diagonal launches (measured)
+  s->rows = !s->strips && P0.dim == 2 &&
+            (P0.schedule == PDVM_SCHEDULE_ROWS || P0.schedule == PDVM_SCHEDULE_ROWS_AGENT ||
+             (P0.schedule == PDVM_SCHEDULE_AUTO && n == 1));
   if (s->rows) {
     // the row pipeline stores a tile through 32-bit byte offsets from its
     // lowest-addressed voxel
@@ -1024,7 +1093,12 @@ int create_common(const pdvm_config *cfgs, int n, void *dev_workspace, size_t ws
     }
   }
   if (s->rows && P0.schedule != PDVM_SCHEDULE_ROWS_AGENT) {
-    const int rc2 = probe_xcd_locality(s);
+    const int rc2 = probe_xcd_locality(s, s->h_row_off, s->precision == PDVM_FP64 ? s->bd.row_stride
+                                                                                  : s->bf.row_stride,
+                                       P0.ngroups << P0.dim,
+                                       kWave * band_waves(s->precision == PDVM_FP64 ? s->bd.tile_edge
+                                                                                    : s->bf.tile_edge),
+                                       &s->rows_local);
     if (rc2 != PDVM_OK) {
       g_thread_error = s->err;
       pdvm_destroy(s);
@@ -1033,7 +1107,7 @@ int create_common(const pdvm_config *cfgs, int n, void *dev_workspace, size_t ws
     // automatic choice: the row pipeline only with the cheap XCD-local protocol
     if (!s->rows_local && P0.schedule == PDVM_SCHEDULE_AUTO) s->rows = false;
   }
-  if (s->rows && s->rows_local) {
+  if (s->strips || (s->rows && s->rows_local)) {
     // the XCD-local protocol is checked on every sweep: each block records its
     // XCD and the reduction discards an iterate whose chains were split
     const int rc3 = s->precision == PDVM_FP64 ? enable_xcc_check<double>(s) : enable_xcc_check<float>(s);
@@ -1053,8 +1127,9 @@ int create_common(const pdvm_config *cfgs, int n, void *dev_workspace, size_t ws
     s->scratch_dev = (char *)ptr;
     s->scr_part = 0;
     s->scr_prog = align256((size_t)s->h_blk_off[n] * 4 * sizeof(double));
-    s->scr_xcc = s->scr_prog + align256((size_t)s->h_row_off[n] * sizeof(int32_t));
-    s->scr_need = s->scr_xcc + align256((size_t)s->h_row_off[n]);
+    const size_t pipe = (size_t)std::max(s->h_row_off[n], s->h_strip_off[n]);
+    s->scr_xcc = s->scr_prog + align256(pipe * sizeof(int32_t));
+    s->scr_need = s->scr_xcc + align256(pipe);
     s->start_iters.assign(n, 0);
   }
   *out = s;
@@ -1174,9 +1249,13 @@ int iterate_noalloc(pdvm_solver *s, int64_t max_iters, double tol, int32_t stop_
   if (rc != PDVM_OK) return rc;
   // the counters hold whatever an earlier solve on this GPU left: set them
   // below every stamp of this call
-  if (s->rows) {
-    if (s->precision == PDVM_FP64) HIPCHK(s, launch_progress_reset<double>(s->bd, scr.progress, s->stream));
-    else HIPCHK(s, launch_progress_reset<float>(s->bf, scr.progress, s->stream));
+  if (s->rows || s->strips) {
+    if (s->precision == PDVM_FP64)
+      HIPCHK(s, launch_progress_reset<double>(s->bd, s->strips ? s->bd.d_strip_off : s->bd.d_row_off, s->strips,
+                                              scr.progress, s->stream));
+    else
+      HIPCHK(s, launch_progress_reset<float>(s->bf, s->strips ? s->bf.d_strip_off : s->bf.d_row_off, s->strips,
+                                             scr.progress, s->stream));
   }
   const int64_t poll = std::max(1, s->P[0].check_every);
   int64_t launched = 0;
@@ -1528,8 +1607,9 @@ int pdvm_time_kernels(pdvm_solver *s, int32_t iters, pdvm_timing *out) {
   rc = arm(s, 0.0, 0, 2 * (int64_t)iters + 1);
   if (rc != PDVM_OK) return rc;
   const bool f64 = s->precision == PDVM_FP64;
-  const int nd = s->rows ? 1 : (f64 ? s->bd.ndiag_max : s->bf.ndiag_max);
+  const int nd = (s->rows || s->strips) ? 1 : (f64 ? s->bd.ndiag_max : s->bf.ndiag_max);
   auto sweep_launch = [&](int d) {
+    if (s->strips) return f64 ? launch_sweep_strips<double>(s->bd, s->stream) : launch_sweep_strips<float>(s->bf, s->stream);
     if (s->rows)
       return f64 ? launch_sweep_rows<double>(s->bd, s->rows_local, s->stream)
                  : launch_sweep_rows<float>(s->bf, s->rows_local, s->stream);
@@ -1542,7 +1622,7 @@ int pdvm_time_kernels(pdvm_solver *s, int32_t iters, pdvm_timing *out) {
   auto cleanup = [&]() { for (auto &e : ev) if (e) (void)hipEventDestroy(e); };
   double sweep_seq = 0, sweep_kern = 0, mom = 0, red = 0, tot = 0;
   int launches = 0;
-  if (s->rows) launches = 1;
+  if (s->rows || s->strips) launches = 1;
   else
     for (int d = 0; d < nd; ++d) launches += s->h_item_off[(size_t)d * (s->n() + 1) + s->n()] > 0;
   hipError_t e = hipSuccess;
@@ -1614,7 +1694,7 @@ int pdvm_time_kernels(pdvm_solver *s, int32_t iters, pdvm_timing *out) {
 
 int32_t pdvm_sweep_schedule(const pdvm_solver *s) {
   if (!s) return -1;
-  return s->rows ? (s->rows_local ? 2 : 1) : 0;
+  return s->strips ? 3 : (s->rows ? (s->rows_local ? 2 : 1) : 0);
 }
 
 int pdvm_set_wait_limit(pdvm_solver *s, double seconds) {

@@ -108,7 +108,7 @@ struct Geo {
   // on, [row_blocks] bytes (block = band * row_stride + chain); the reduction
   // kernel discards the iterate unless all blocks of each chain agree
   uint8_t *xcc_seen = nullptr;
-  int32_t row_blocks = 0, row_stride = 0;
+  int32_t row_blocks = 0, row_stride = 0, row_sets = 0;  // blocks, blocks per band, real ones per band
 };
 
 // Square sweep tile edges in (x1, x2) compiled into the kernel; the host
@@ -133,7 +133,21 @@ struct Batch {
   const int *d_row_off = nullptr;
   const int *h_row_off = nullptr;
   int row_stride = 8;
+  // strip pipeline (2D): problem p owns blocks [strip_off[p], strip_off[p + 1]),
+  // its bands times strip_stride (chain sets rounded up to 8); strip_shape is
+  // one of kStrip* (rows per strip, velocity groups per wavefront, strips per block)
+  const int *d_strip_off = nullptr;
+  const int *h_strip_off = nullptr;
+  int strip_stride = 8, strip_shape = 0;
+  int use_strips = 0;  // the sweep is the strip pipeline (its block offsets locate the XCD records)
 };
+
+// Shapes of the strip pipeline: rows per strip TH x velocity groups per
+// wavefront G, with the strips per block NW that each is compiled with.
+enum { kStrip4x2 = 0, kStrip4x1 = 1, kStrip2x2 = 2, kStrip2x1 = 3, kStripShapes = 4 };
+constexpr int strip_th(int shape) { return shape == kStrip4x2 || shape == kStrip4x1 ? 4 : 2; }
+constexpr int strip_g(int shape) { return shape == kStrip4x2 || shape == kStrip2x2 ? 2 : 1; }
+constexpr int strip_nw(int shape) { return strip_g(shape) == 2 ? 4 : 8; }
 
 // Scratch memory of the iteration's kernels: the moment kernel's per-block
 // partial sums, the row pipeline's progress counters and per-block XCD
@@ -156,11 +170,15 @@ hipError_t launch_sweep(const Batch<T> &B, int diag, hipStream_t st);
 // chain's bands run on one XCD (checked with launch_xcd_probe).
 template <typename T>
 hipError_t launch_sweep_rows(const Batch<T> &B, bool local, hipStream_t st, const Scratch &scr = Scratch{});
-// The row pipeline's progress counters of a batch-wide scratch region, set
-// below every stamp the next sweep of each problem publishes (its seq *
-// ntile0), as a fill kernel (no memset node when the caller captures a graph).
+// The strip pipeline (2D, one launch for all problems of the batch).
 template <typename T>
-hipError_t launch_progress_reset(const Batch<T> &B, int32_t *progress, hipStream_t st);
+hipError_t launch_sweep_strips(const Batch<T> &B, hipStream_t st, const Scratch &scr = Scratch{});
+// The pipeline's progress counters of a batch-wide scratch region (blocks
+// off[p] .. off[p + 1] of problem p), set below every stamp the next sweep of
+// each problem publishes: seq * ntile0 for the row pipeline, seq * n0 for the
+// strips; a fill kernel (no memset node when the caller captures a graph).
+template <typename T>
+hipError_t launch_progress_reset(const Batch<T> &B, const int *d_off, bool strips, int32_t *progress, hipStream_t st);
 // out[b] = the XCD that block b of a `blocks`-block grid runs on.
 hipError_t launch_xcd_probe(uint32_t *out, int blocks, int threads, hipStream_t st);
 template <typename T>

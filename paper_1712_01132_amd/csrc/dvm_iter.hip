@@ -247,7 +247,7 @@ __global__ void __launch_bounds__(256)
   Ctl *ctl = g.ctl;
   if (ctl->stop) return;
   const double *part = part_scr ? part_scr + 4 * (int64_t)blk_off[blockIdx.x] : g.part;
-  const uint8_t *xcc_seen = g.xcc_seen && xcc_scr ? xcc_scr + row_off[blockIdx.x] : g.xcc_seen;
+  const uint8_t *xcc_seen = g.xcc_seen && xcc_scr ? xcc_scr + row_off[blockIdx.x] : g.xcc_seen;  // row_off: the pipeline's block offsets
   const int nblocks = g.mom_blocks;
   const int64_t N = g.N;
   __shared__ double sa[256], sb[256], sc[256];
@@ -258,10 +258,9 @@ __global__ void __launch_bounds__(256)
   // XCD-local row pipeline: all blocks of a velocity chain must have run on one
   // XCD (their hand-over relies on a shared L2); otherwise the iterate is void
   if (xcc_seen) {
-    const int nchains = g.ngroups << g.dim;
     for (int i = t; i < g.row_blocks; i += 256) {
       const int ch = i % g.row_stride;
-      if (ch < nchains && xcc_seen[i] != xcc_seen[ch]) misplaced = 1;
+      if (ch < g.row_sets && xcc_seen[i] != xcc_seen[ch]) misplaced = 1;
     }
   }
   double a = 0, b = 0, c = 0;
@@ -520,7 +519,7 @@ hipError_t launch_moments(const Batch<T> &B, hipStream_t st, const Scratch &scr)
 template <typename T>
 hipError_t launch_reduce(const Batch<T> &B, hipStream_t st, const Scratch &scr) {
   hipLaunchKernelGGL((reduce_kernel<T>), dim3(B.nprob), dim3(256), 0, st, const_cast<Geo<T> *>(B.d_geo), B.d_blk_off,
-                     B.d_row_off, scr.part, scr.xcc);
+                     B.use_strips ? B.d_strip_off : B.d_row_off, scr.part, scr.xcc);
   return hipGetLastError();
 }
 

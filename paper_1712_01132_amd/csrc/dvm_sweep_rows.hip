@@ -545,17 +545,19 @@ hipError_t launch_sweep_rows(const Batch<T> &B, bool local, hipStream_t st, cons
 
 namespace {
 template <typename T>
-__global__ void progress_reset_kernel(const Geo<T> *__restrict__ G, const int *__restrict__ row_off, int32_t *prog) {
+__global__ void progress_reset_kernel(const Geo<T> *__restrict__ G, const int *__restrict__ off, int strips,
+                                      int32_t *prog) {
   const int p = blockIdx.x;
-  const int32_t below = (int32_t)((uint32_t)G[p].seq * (uint32_t)G[p].ntile[0]);
-  for (int i = row_off[p] + threadIdx.x; i < row_off[p + 1]; i += blockDim.x) prog[i] = below;
+  const uint32_t per = strips ? (uint32_t)G[p].n[0] : (uint32_t)G[p].ntile[0];
+  const int32_t below = (int32_t)((uint32_t)G[p].seq * per);
+  for (int i = off[p] + threadIdx.x; i < off[p + 1]; i += blockDim.x) prog[i] = below;
 }
 }  // namespace
 
 template <typename T>
-hipError_t launch_progress_reset(const Batch<T> &B, int32_t *progress, hipStream_t st) {
-  hipLaunchKernelGGL((progress_reset_kernel<T>), dim3((unsigned)B.nprob), dim3(256), 0, st, B.d_geo, B.d_row_off,
-                     progress);
+hipError_t launch_progress_reset(const Batch<T> &B, const int *d_off, bool strips, int32_t *progress, hipStream_t st) {
+  hipLaunchKernelGGL((progress_reset_kernel<T>), dim3((unsigned)B.nprob), dim3(256), 0, st, B.d_geo, d_off,
+                     strips ? 1 : 0, progress);
   return hipGetLastError();
 }
 
@@ -573,7 +575,7 @@ hipError_t launch_xcd_probe(uint32_t *out, int blocks, int threads, hipStream_t 
 
 template hipError_t launch_sweep_rows<double>(const Batch<double> &, bool, hipStream_t, const Scratch &);
 template hipError_t launch_sweep_rows<float>(const Batch<float> &, bool, hipStream_t, const Scratch &);
-template hipError_t launch_progress_reset<double>(const Batch<double> &, int32_t *, hipStream_t);
-template hipError_t launch_progress_reset<float>(const Batch<float> &, int32_t *, hipStream_t);
+template hipError_t launch_progress_reset<double>(const Batch<double> &, const int *, bool, int32_t *, hipStream_t);
+template hipError_t launch_progress_reset<float>(const Batch<float> &, const int *, bool, int32_t *, hipStream_t);
 
 }  // namespace pdvm

@@ -87,6 +87,22 @@ def test_autotuner_times_candidates_and_caches(tmp_path, monkeypatch):
     assert np.array_equal(res[0][1], res[1][1])
 
 
+@pytest.mark.parametrize("nv,precision", [([6, 6], "fp64"), ([24, 24], "fp32"), ([32, 32], "fp64")])
+def test_batch_strips_equal_tile_diagonals_bitwise(nv, precision):
+    """All problems of a batch in one strip-pipeline launch against the
+    per-diagonal launches."""
+    probs = masks()
+    res = []
+    for sched in ("strips", "diagonals"):
+        b = poredvm.Batch(probs, nv, precision=precision, schedule=sched)
+        assert b.schedule == sched
+        b.iterate(9)
+        res.append([b.moments(i) for i in range(len(probs))])
+        b.close()
+    for (ra, ua), (rb, ub) in zip(res[0], res[1]):
+        assert np.array_equal(ra, rb) and np.array_equal(ua, ub)
+
+
 @pytest.mark.parametrize("nv,precision", [([6, 6], "fp64"), ([24, 24], "fp32")])
 def test_batch_row_pipeline_equals_tile_diagonals_bitwise(nv, precision):
     """All problems of a batch in one row-pipeline launch (each problem's

@@ -138,21 +138,64 @@ def test_row_pipeline_equals_tile_diagonals_bitwise(shape, nv, tile, precision, 
 
 
 def test_row_pipeline_protocols():
-    """Every tile row is padded to a multiple of 8 blocks, so under round-robin
-    placement each velocity chain runs on one XCD whatever the velocity grid:
-    the creation probe confirms it and the automatic choice is the XCD-local
-    row pipeline. ROWS_AGENT forces the agent-scope protocol; all three give
-    the same iterates."""
+    """Every tile row (and every band of strips) is padded to a multiple of 8
+    blocks, so under round-robin placement each velocity chain runs on one XCD
+    whatever the velocity grid: the creation probe confirms it and the
+    automatic choice is the XCD-local row pipeline; STRIPS the strip pipeline.
+    ROWS_AGENT forces the agent-scope protocol; all give the same iterates."""
     m = random_mask((40, 48), 0.3, 5)
-    res = []
     for nv in ([32, 32], [6, 8], [24, 24]):
-        for sched, want in (("auto", "rows-xcd"), ("rows-agent", "rows"), ("diagonals", "diagonals")):
+        res = []
+        for sched, want in (("auto", "rows-xcd"), ("strips", "strips"), ("rows-agent", "rows"),
+                            ("diagonals", "diagonals")):
             s = poredvm.Solver(m, nv, 0.6, schedule=sched)
             assert s.schedule == want, (nv, sched, s.schedule)
             s.iterate(5)
             res.append(s.moments(diagnostics=False)[1])
             s.close()
-        assert np.array_equal(res[-3], res[-2]) and np.array_equal(res[-3], res[-1])
+        assert all(np.array_equal(res[0], r) for r in res[1:])
+
+
+@pytest.mark.parametrize("shape,nv,precision,lateral,rule", [
+    ((29, 37), [6, 8], "fp64", "specular", 1),     # one 64-velocity group: the pair's second is empty
+    ((37, 29), [32, 32], "fp64", "specular", 1),   # four groups per octant, two pairs
+    ((70, 24), [24, 24], "fp32", "specular", 1),   # three groups (the last partial); partial band and strip
+    ((45, 7), [8, 8], "fp64", "specular", 0),      # fewer columns than one staging chunk
+    ((9, 40), [16, 16], "fp32", "periodic", 1),    # three strips, the last one row high
+    ((130, 33), [8, 8], "fp64", "specular", 0),    # many bands: hand-over through h between bands
+    ((2, 2), [2, 2], "fp64", "specular", 1),       # the minimal domain
+    ((5, 3), [4, 4], "fp32", "periodic", 0),
+])
+def test_strips_equal_tile_diagonals_bitwise(shape, nv, precision, lateral, rule):
+    """The strip pipeline runs the same arithmetic on the same records as the
+    tile diagonals: every iterate is bitwise identical."""
+    m = random_mask(shape, 0.3, sum(shape) + 13)
+    out = []
+    for sched in ("strips", "diagonals"):
+        s = poredvm.Solver(m, nv, 0.6, precision=precision, lateral=lateral, stencil_rule=rule, schedule=sched)
+        assert s.schedule == sched
+        r = s.iterate(12)
+        out.append((s.moments(diagnostics=False), r["k"], r["r"]))
+        s.close()
+    (a, ka, ra), (b, kb, rb) = out
+    assert np.array_equal(a[0], b[0]) and np.array_equal(a[1], b[1]) and ka == kb and ra == rb
+
+
+@pytest.mark.parametrize("shape_id", [0, 1, 2, 3])
+def test_every_strip_shape_equals_tile_diagonals_bitwise(shape_id, monkeypatch):
+    """Each compiled strip shape (4 or 2 rows per strip, 2 or 1 velocity groups
+    per wavefront), chosen through the tuning override, on masks with several
+    bands, partial strips and an odd group count."""
+    monkeypatch.setenv("PDVM_STRIP_SHAPE", str(shape_id))
+    for shape, nv, precision in (((67, 41), [24, 24], "fp64"), ((33, 50), [16, 16], "fp32")):
+        m = random_mask(shape, 0.3, sum(shape) + shape_id)
+        out = []
+        for sched in ("strips", "diagonals"):
+            s = poredvm.Solver(m, nv, 0.8, precision=precision, schedule=sched)
+            s.iterate(7)
+            out.append(s.moments(diagnostics=False))
+            s.close()
+        assert np.array_equal(out[0][0], out[1][0]) and np.array_equal(out[0][1], out[1][1])
 
 def test_minimal_domain_and_grid():
     m = np.zeros((2, 2), np.uint8)

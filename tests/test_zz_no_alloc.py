@@ -30,6 +30,7 @@ def _same(a, b):
 
 @pytest.mark.parametrize("schedule,precision,nv", [
     ("auto", "fp64", [16, 16]),      # XCD-local row pipeline: counters and XCD records in the scratch
+    ("strips", "fp32", [8, 8]),      # strip pipeline, likewise
     ("rows-agent", "fp32", [24, 24]),
     ("diagonals", "fp64", [8, 8]),
 ])
@@ -40,6 +41,8 @@ def test_noalloc_equals_iterate_twice_second_smaller(schedule, precision, nv):
         b = poredvm.Solver(m, nv, 0.6, precision=precision, schedule=schedule)
         if schedule == "auto":
             assert b.schedule == "rows-xcd"
+        if schedule == "strips":
+            assert b.schedule == "strips"
         ra = a.iterate(iters)
         rb = b.iterate_noalloc(iters)
         assert rb["iters"] == ra["iters"] == iters and rb["total_iters"] == iters
