@@ -122,6 +122,14 @@ __global__ void __launch_bounds__(kWave)
   }
   const int xs = s[0] > 0 ? lo[0] : lo[0] + cnt[0] - 1;
   const int ys = s[1] > 0 ? lo[1] : lo[1] + cnt[1] - 1;
+  // 3D with 4 x 4 tiles: the two planes upstream along x3 of every voxel of
+  // the tile's plane, ZA one plane back, ZB two, are loaded from h (or the
+  // images) for the tile's first plane and then carried in registers from
+  // plane to plane (each voxel's new value replaces ZA, whose value moves to
+  // ZB). 8 x 8 tiles read them from h per anti-diagonal (128 more registers
+  // would cost them their occupancy).
+  constexpr bool ZREG = DIM == 3 && TT == 4;
+  T ZA[ZREG ? NC : 1], ZB[ZREG ? NC : 1];
 
   for (int c3 = 0; c3 < cnt[2]; ++c3) {
     const int z = s[2] > 0 ? lo[2] + c3 : lo[2] + cnt[2] - 1 - c3;
@@ -210,6 +218,24 @@ __global__ void __launch_bounds__(kWave)
     }
     const bool zin = DIM == 3 && z - 2 * s[2] >= 0 && z - 2 * s[2] < dm.n[2];
     const int64_t zstep = (int64_t)n1 * n0 * Kp * s[2];
+    if (ZREG && c3 == 0) {
+#pragma unroll
+      for (int v = 0; v < (ZREG ? NC : 0); ++v) {
+        const int i = v % TT, r = v / TT;
+        ZA[v] = ZB[v] = T(0);
+        if (i < cnt[0] && r < cnt[1]) {
+          const int x = xs + i * s[0], y = ys + r * s[1];
+          if (zin) {
+            const gptr<const T> hv0 = hz + (int64_t)(y * n0 + x) * Kp;
+            ZA[v] = hv0[-zstep];
+            ZB[v] = hv0[-2 * zstep];
+          } else {
+            ZA[v] = upstream_fluid(dv, hc, hp, 2, x, y, z - s[2], kofs, kmir[2]);
+            ZB[v] = upstream_fluid(dv, hc, hp, 2, x, y, z - 2 * s[2], kofs, kmir[2]);
+          }
+        }
+      }
+    }
     __syncthreads();
     // store addresses: row r of the tile starts at hrow[r]; voxel i of a row is icol[i] further
     gptr<T> hrow[TT];
@@ -227,14 +253,14 @@ __global__ void __launch_bounds__(kWave)
     for (int d = 0; d < 2 * TT - 1; ++d) {
       T Nw[TT];
       uint32_t Nc[TT];
-      T Z1[TT], Z2[TT];
+      T Z1[TT], Z2[TT];  // 8 x 8 tiles in 3D: the x3-upstream values from h
 #pragma unroll
       for (int r = 0; r < TT; ++r) {
         Nw[r] = T(0);
         Nc[r] = R_SKIP;
         Z1[r] = Z2[r] = T(0);
         const int i = d - r;
-        if (DIM == 3 && i >= 0 && i < TT && i < cnt[0] && r < cnt[1]) {
+        if (DIM == 3 && !ZREG && i >= 0 && i < TT && i < cnt[0] && r < cnt[1]) {
           const int x = xs + i * s[0], y = ys + r * s[1];
           if (zin) {
             const gptr<const T> hv0 = hz + (int64_t)(y * n0 + x) * Kp;
@@ -275,9 +301,16 @@ __global__ void __launch_bounds__(kWave)
         const T x2b = r >= 2 ? D2[r >= 2 ? r - 2 : 0] : (r == 1 ? B1[i] : B2[i]);
         num = fma(aa[0], fma(rp[5], x1a, fma(rp[6], x1b, PSI ? rp[7] * ph : rp[7])), num);
         num = fma(aa[1], fma(rp[8], x2a, fma(rp[9], x2b, PSI ? rp[10] * ph : rp[10])), num);
-        if (DIM == 3) num = fma(aa[2], fma(rp[11], Z1[r], fma(rp[12], Z2[r], rp[13])), num);
+        if (DIM == 3) {
+          const T za = ZREG ? ZA[ZREG ? i + TT * r : 0] : Z1[r], zb = ZREG ? ZB[ZREG ? i + TT * r : 0] : Z2[r];
+          num = fma(aa[2], fma(rp[11], za, fma(rp[12], zb, rp[13])), num);
+        }
         Nw[r] = num * rd_lds[(code & 7u) * kWave + lane];
         Nc[r] = code;
+        if (ZREG) {  // this plane's value is the next plane's one-back, its one-back the two-back
+          ZB[ZREG ? i + TT * r : 0] = ZA[ZREG ? i + TT * r : 0];
+          ZA[ZREG ? i + TT * r : 0] = Nw[r];
+        }
       }
       // the stores after the whole anti-diagonal: the loop above stays free
       // of control flow, so its loads and FMA chains interleave
