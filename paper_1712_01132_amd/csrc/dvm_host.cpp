@@ -456,13 +456,37 @@ int validate_and_build(const pdvm_config *cfg, Problem &P, std::string &err) {
     }
   }
   P.ndiag = P.ntile[0] + P.ntile[1] + P.ntile[2] - 2;
-  std::vector<std::vector<int32_t>> per(P.ndiag);
-  for (int c = 0; c < P.ntile[2]; ++c)
+  std::vector<std::vector<int32_t>> per;
+  if (P.dim == 2) {
+    per.resize(P.ndiag);
     for (int b = 0; b < P.ntile[1]; ++b)
       for (int a = 0; a < P.ntile[0]; ++a) {
-        auto &v = per[a + b + c];
-        v.push_back(a); v.push_back(b); v.push_back(c); v.push_back(0);
+        auto &v = per[a + b];
+        v.push_back(a); v.push_back(b); v.push_back(0); v.push_back(0);
       }
+  } else {
+    // 3D: one list per diagonal and sign octant of the physical tiles that
+    // hold a fluid voxel (the sweep does nothing in an all-solid tile, whose
+    // voxels keep their values); the octant's walk order sets which physical
+    // tile sits at oriented coordinates (a, b, c)
+    std::vector<uint8_t> live((size_t)P.ntile[0] * P.ntile[1] * P.ntile[2], 0);
+    for (int64_t c = 0; c < P.N; ++c) {
+      if (P.flags[c] & F_SOLID) continue;
+      const int64_t x = c % P.n[0], y = (c / P.n[0]) % P.n[1], z = c / ((int64_t)P.n[0] * P.n[1]);
+      live[(x / P.tile[0]) + P.ntile[0] * ((y / P.tile[1]) + (size_t)P.ntile[1] * (z / P.tile[2]))] = 1;
+    }
+    per.resize((size_t)P.ndiag * 8);
+    for (int c = 0; c < P.ntile[2]; ++c)
+      for (int b = 0; b < P.ntile[1]; ++b)
+        for (int a = 0; a < P.ntile[0]; ++a)
+          for (int o = 0; o < 8; ++o) {
+            const int pa = (o & 1) ? P.ntile[0] - 1 - a : a, pb = (o & 2) ? P.ntile[1] - 1 - b : b,
+                      pc = (o & 4) ? P.ntile[2] - 1 - c : c;
+            if (!live[pa + P.ntile[0] * (pb + (size_t)P.ntile[1] * pc)]) continue;
+            auto &v = per[(size_t)(a + b + c) * 8 + o];
+            v.push_back(pa); v.push_back(pb); v.push_back(pc); v.push_back(0);
+          }
+  }
   P.diag_off.assign(1, 0);
   for (auto &v : per) {
     P.diag_tiles.insert(P.diag_tiles.end(), v.begin(), v.end());
@@ -761,7 +785,8 @@ int finalize_batch(pdvm_solver *s) {
     for (int p = 0; p < n; ++p) {
       s->h_item_off[(size_t)d * (n + 1) + p] = acc;
       const Problem &P = s->P[p];
-      if (d < P.ndiag) acc += (P.diag_off[d + 1] - P.diag_off[d]) * (P.ngroups << P.dim);
+      if (d < P.ndiag && P.dim == 2) acc += (P.diag_off[d + 1] - P.diag_off[d]) * (P.ngroups << 2);
+      if (d < P.ndiag && P.dim == 3) acc += (P.diag_off[(d + 1) * 8] - P.diag_off[d * 8]) * P.ngroups;
     }
     s->h_item_off[(size_t)d * (n + 1) + n] = acc;
   }

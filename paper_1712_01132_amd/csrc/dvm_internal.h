@@ -88,8 +88,12 @@ struct Geo {
   const int32_t *fluid_idx;  // [nfluid] the fluid voxels in index order (moment kernel's work list)
   int64_t nfluid;
   int32_t tile[3], ntile[3];
-  const int32_t *diag_tiles;  // [count][4] oriented tile coordinates (x1, x2, x3, pad)
-  const int32_t *diag_off;    // [ndiag + 1]
+  // 2D: the tiles of each diagonal, as oriented coordinates (x1, x2, 0, pad),
+  // diag_off [ndiag + 1]. 3D: per diagonal and sign octant (list d * 8 + o),
+  // the physical coordinates (x1, x2, x3, pad) of the tiles holding fluid,
+  // diag_off [ndiag * 8 + 1].
+  const int32_t *diag_tiles;
+  const int32_t *diag_off;
   int32_t ndiag;
   // Resolved for the next iteration by the kernels that change the state
   // (arm: from the control block; reduce: after its parity decision), so that

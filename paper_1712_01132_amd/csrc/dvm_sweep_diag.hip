@@ -51,22 +51,32 @@ __global__ void __launch_bounds__(kWave)
   const gptr<const T> wall = as_global(G_.wallcur);
   const gptr<const uint32_t> flags = as_global(G_.flags);
   const int n0 = dm.n[0], n1 = dm.n[1];
-  // tiles of diagonal `diag`: in 2D (a, b) with a + b = diag, computed; in 3D from the table
-  int d0 = 0, ntd;
+  // tiles of diagonal `diag`: in 2D (a, b) with a + b = diag, computed, the
+  // same for every octant; in 3D per octant from the table of tiles holding
+  // fluid (items: octant, then group, then tile)
+  int d0 = 0, ntd, t, grp, o;
+  int item = nprob > 1 ? blockIdx.x - item_off[p] : blockIdx.x;
   if (DIM == 2) {
     const int amin = max(0, diag - (ntile[1] - 1)), amax = min(diag, ntile[0] - 1);
     d0 = amin;
     ntd = amax - amin + 1;
+    t = item % ntd;
+    item /= ntd;
+    grp = item % ngroups;
+    o = item / ngroups;
   } else {
-    const gptr<const int32_t> diag_off = as_global(G_.diag_off);
-    d0 = diag_off[diag];
-    ntd = diag_off[diag + 1] - d0;
+    const gptr<const int32_t> diag_off = as_global(G_.diag_off) + diag * 8;
+    const int base = diag_off[0];
+    o = 0;
+#pragma unroll
+    for (int k = 1; k < 8; ++k)
+      if (item >= (diag_off[k] - base) * ngroups) o = k;
+    d0 = diag_off[o];
+    ntd = diag_off[o + 1] - d0;
+    item -= (d0 - base) * ngroups;
+    t = item % ntd;
+    grp = item / ntd;
   }
-  int item = nprob > 1 ? blockIdx.x - item_off[p] : blockIdx.x;
-  const int t = item % ntd;
-  item /= ntd;
-  const int grp = item % ngroups;
-  const int o = item / ngroups;
   const int lane = threadIdx.x;
   const int q = grp * kWave + lane;
   const bool active = q < Ko;
@@ -104,10 +114,13 @@ __global__ void __launch_bounds__(kWave)
   for (int j = 0; j < 3; ++j) kmir[j] = (o ^ (1 << j)) * Ko_pad + qq;
 
   int lo[3] = {0, 0, 0}, cnt[3] = {1, 1, 1};
-  int tpos[3] = {0, 0, 0};
+  int tpos[3] = {0, 0, 0};  // physical tile coordinates
   if (DIM == 2) {
     tpos[0] = d0 + t;
     tpos[1] = diag - tpos[0];
+#pragma unroll
+    for (int j = 0; j < 2; ++j)
+      if (s[j] < 0) tpos[j] = ntile[j] - 1 - tpos[j];
   } else {
     const gptr<const int32_t> diag_tiles = as_global(G_.diag_tiles);
 #pragma unroll
@@ -115,9 +128,7 @@ __global__ void __launch_bounds__(kWave)
   }
 #pragma unroll
   for (int j = 0; j < DIM; ++j) {
-    const int tp = tpos[j];
-    const int tj = s[j] > 0 ? tp : ntile[j] - 1 - tp;
-    lo[j] = tj * tile[j];
+    lo[j] = tpos[j] * tile[j];
     cnt[j] = min(tile[j], dm.n[j] - lo[j]);
   }
   const int xs = s[0] > 0 ? lo[0] : lo[0] + cnt[0] - 1;
