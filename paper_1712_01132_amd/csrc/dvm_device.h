@@ -121,6 +121,19 @@ __device__ __forceinline__ T wall_at_y1(const Dom<T> &g, PW wall, int j, int s, 
   return im.jmp ? v + T(im.jmp) * g.jump : v;
 }
 
+// Offset form: the density ramp rho_r at voxel c, and rho_r(y1) - rho_r(x) for
+// the upstream node y1 of the wall value (axis j, half p) that x stores: half 1
+// serves the sweep along +e_j (y1 = x - e_j), half 0 the sweep along -e_j.
+template <typename T>
+__device__ __forceinline__ double ramp_at(const Geo<T> &g, int64_t c) {
+  const int x = (int)(c % g.n[0]);
+  return g.ramp * (0.5 - (x + 0.5) / (double)g.n[0]);
+}
+template <typename T>
+__device__ __forceinline__ double ramp_step(const Geo<T> &g, int j, int p) {
+  return j == 0 ? (p ? g.ramp : -g.ramp) / (double)g.n[0] : 0.0;
+}
+
 constexpr uint32_t R_SKIP = 0x80000000u;  // solid voxel or outside the tile
 // row pipeline codes: the reciprocal denominators' LDS byte offset below
 // kRdMask, Maxwell-wall bits (axis k: kWallBit << k) above it

@@ -326,6 +326,11 @@ int validate_and_build(const pdvm_config *cfg, Problem &P, std::string &err) {
   P.Ko_pad = (P.Ko + line - 1) / line * line;
   P.Kpad = P.Ko_pad << P.dim;
   P.ngroups = (P.Ko + kWave - 1) / kWave;
+  // the sweeps store a row of h (all voxels along x1) through one buffer resource
+  if ((int64_t)P.n[0] * P.Kpad * elem >= ((int64_t)1 << 30)) {
+    err = "a row of voxels along x1 may hold at most 1 GiB of the distribution";
+    return PDVM_E_INVAL;
+  }
 
   // per-slot tables of one octant (slot q <-> positive node indices p_j)
   const double dx_inv = (double)P.n[0];
@@ -691,7 +696,19 @@ int setup_problem(pdvm_solver *s, int i) {
   g.lateral_periodic = P.lateral_periodic;
   g.tau_fb = P.tau_fb;
   g.y2wall = P.stencil_rule == 0;
-  g.jump = T(P.jump);
+  g.dev = P.spec > 0 ? 0 : 1;
+  g.jump = g.dev ? T(0) : T(P.jump);
+  g.ramp = P.jump;
+  {
+    double w0 = 0, we = 0;
+    for (int q = 0; q < P.Ko; ++q)
+      if (P.vsqm[P.Ko_pad + q] != 0.0) {  // a slot of h (not psi)
+        w0 += P.wq[q];
+        we += P.wq[(1 + P.dim) * P.Ko_pad + q];
+      }
+    g.w0 = w0 * (double)(1 << P.dim);
+    g.we = we * (double)(1 << P.dim);
+  }
   g.nu = P.nu;
   for (int j = 0; j < 3; ++j) g.D[j] = P.D[j] > 0 ? P.D[j] : 1.0;
   g.ctl = (Ctl *)(b + L.ctl);
@@ -757,6 +774,8 @@ int setup_problem(pdvm_solver *s, int i) {
   c.err = -1.0;
   c.stop = 1;
   HIPCHK(s, hipMemcpyAsync(g.ctl, &c, sizeof(Ctl), hipMemcpyHostToDevice, st));
+  // the rest state: zeros, except where the offset form stores h - rho_r
+  if (g.dev) HIPCHK(s, launch_init_state<T>(g, nullptr, nullptr, st));
   HIPCHK(s, hipStreamSynchronize(st));
   return PDVM_OK;
 }

@@ -62,7 +62,16 @@ struct Geo {
   int32_t maxwell;         // Maxwell walls: a wall value is alpha (diffuse) + spec (mirrored previous h)
   T spec, alpha;           // 1 - alpha, alpha
   int32_t y2wall;          // stencil rule 0: a solid second image enters the second-order stencil
-  T jump;
+  T jump;                  // the jump the sweep adds across the x1 wrap (0 in the offset form)
+  // Offset form (every problem without Maxwell walls): h is stored as its
+  // deviation from the linear density ramp rho_r = J (1/2 - (x1 + 1/2) / n1),
+  // which carries the jump of Eq. periodic_BC, so the stored values are of the
+  // size of u and rho - rho_r rather than of J. The sweep is unchanged: the
+  // ramp enters only through the records (see moments_kernel) and the jump
+  // across the wrap is 0.
+  int32_t dev;
+  double ramp;             // J
+  double w0, we;           // 2^dim sums over the slots of h of the rho and energy weights
   double nu, D[3];
   const uint32_t *flags;   // [N]
   const T *absv;           // [3][Ko_pad]   |v_j| of octant slot q

@@ -81,6 +81,7 @@ __global__ void __launch_bounds__(kMomBlock)
   const int64_t N = g.N, Kpad = g.Kpad, nf = g.nfluid;
   const int Ko = g.Ko, Ko_pad = g.Ko_pad, tau_fb = g.tau_fb, mom_blocks = g.mom_blocks;
   const double nu = g.nu, Dj[3] = {g.D[0], g.D[1], g.D[2]};
+  const int dev = g.dev;
   const int lane = threadIdx.x & (kWave - 1), wid = threadIdx.x / kWave;
   constexpr int WPB = kMomBlock / kWave;
   const int64_t nw = (int64_t)mom_blocks * WPB;
@@ -174,20 +175,29 @@ __global__ void __launch_bounds__(kMomBlock)
       }
       const double en = readlane_d(tot, 56);
       if (lane == 0) {
-        rho_n[c] = r;
+        // Offset form: the sums above are moments of h - rho_r. rho_r adds
+        // rho_r w0 to rho, rho_r D_j to each half-flux (so nothing to u) and
+        // rho_r we to the energy. The records then describe the sweep of
+        // h - rho_r: the upwind stencils reproduce a linear field exactly, so
+        // moving rho_r to the right-hand side leaves -nu rho_r in the rho
+        // term, adds J to the coefficient of v1 (a_1 times the ramp's
+        // step), and turns each wall value w into w - rho_r(y1).
+        const double rr = dev ? ramp_at(g, c) : 0.0;
+        const double rt = r + rr * g.w0;
+        rho_n[c] = rt;
         const gptr<T> sp = src_n + c * kSrcStride;
-        sp[0] = T(nu * r);
+        sp[0] = T(nu * (rt - rr));
 #pragma unroll
         for (int j = 0; j < DIM; ++j) {
           const double uj = ph[j][0] - ph[j][1];
           mdu = fmax(mdu, fabs(uj - uold[j * N + c]));
           mu = fmax(mu, fabs(uj));
           u_n[j * N + c] = uj;
-          sp[1 + j] = T(2.0 * nu * uj);
-          wall_n[c * 6 + 2 * j] = T(ph[j][0] / Dj[j]);
-          wall_n[c * 6 + 2 * j + 1] = T(ph[j][1] / Dj[j]);
+          sp[1 + j] = T(2.0 * nu * uj + (dev && j == 0 ? g.ramp : 0.0));
+          wall_n[c * 6 + 2 * j] = T(ph[j][0] / Dj[j] - (dev ? ramp_step(g, j, 0) : 0.0));
+          wall_n[c * 6 + 2 * j + 1] = T(ph[j][1] / Dj[j] - (dev ? ramp_step(g, j, 1) : 0.0));
         }
-        if (tau_fb) srct_n[c] = T(nu * ((2.0 / 3.0) * en - r));
+        if (tau_fb) srct_n[c] = T(nu * ((2.0 / 3.0) * (en + rr * g.we) - rt));
         if (SH) {
 #pragma unroll
           for (int j = 0; j < DIM; ++j) srcq_n[c * 4 + j] = T(shc * qf[j]);
@@ -349,10 +359,12 @@ __global__ void init_moments_kernel(Geo<T> g, const double *rho, const double *u
   for (int64_t c = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; c < g.N; c += (int64_t)gridDim.x * blockDim.x) {
     const bool fl = !(g.flags[c] & F_SOLID);
     const double r = (fl && rho) ? rho[c] : 0.0;
+    const bool dev = g.dev && fl;  // offset form (moments_kernel); solid voxels keep zeros
+    const double rr = dev ? ramp_at(g, c) : 0.0;
     g.rho[par][c] = r;
     T *sp = g.src[par] + c * kSrcStride;
     for (int i = 0; i < kSrcStride; ++i) sp[i] = T(0);
-    sp[0] = T(g.nu * r);
+    sp[0] = T(g.nu * (r - rr));
     g.srct[par][c] = T(0);
     if (g.shakhov)
       for (int j = 0; j < 4; ++j) g.srcq[par][c * 4 + j] = T(0);
@@ -360,10 +372,10 @@ __global__ void init_moments_kernel(Geo<T> g, const double *rho, const double *u
       const double uj = (fl && u && j < DIM) ? u[j * g.N + c] : 0.0;
       if (j < DIM) {
         g.u[par][j * g.N + c] = uj;
-        sp[1 + j] = T(2.0 * g.nu * uj);
-        // Phi_j^+- = rho D_j +- u_j / 2 for h = rho + 2 u.v
-        g.wall[par][c * 6 + 2 * j] = T((r * g.D[j] + 0.5 * uj) / g.D[j]);
-        g.wall[par][c * 6 + 2 * j + 1] = T((r * g.D[j] - 0.5 * uj) / g.D[j]);
+        sp[1 + j] = T(2.0 * g.nu * uj + (dev && j == 0 ? g.ramp : 0.0));
+        // Phi_j^+- = rho D_j +- u_j / 2 for h = rho + 2 u.v (offset form: less rho_r(y1))
+        g.wall[par][c * 6 + 2 * j] = T((r - rr) + 0.5 * uj / g.D[j] - (dev ? ramp_step(g, j, 0) : 0.0));
+        g.wall[par][c * 6 + 2 * j + 1] = T((r - rr) - 0.5 * uj / g.D[j] - (dev ? ramp_step(g, j, 1) : 0.0));
       } else {
         g.wall[par][c * 6 + 2 * j] = T(0);
         g.wall[par][c * 6 + 2 * j + 1] = T(0);
@@ -382,7 +394,7 @@ __global__ void init_h_kernel(Geo<T> g, const double *rho, const double *u) {
     const int o = k / g.Ko_pad, q = k - o * g.Ko_pad;
     double v = 0.0;  // psi of the local equilibrium is tau / 2 = 0
     if (q < g.Ko && g.phm[q] != T(0) && !(g.flags[c] & F_SOLID)) {
-      v = rho ? rho[c] : 0.0;
+      v = (rho ? rho[c] : 0.0) - (g.dev ? ramp_at(g, c) : 0.0);  // offset form: h - rho_r
       if (u)
         for (int j = 0; j < DIM; ++j) {
           const double vj = ((o >> j) & 1) ? -(double)g.absv[j * g.Ko_pad + q] : (double)g.absv[j * g.Ko_pad + q];
@@ -433,6 +445,11 @@ __global__ void __launch_bounds__(kMomBlock) diagnostics_kernel(Geo<T> g, double
       }
     r = wave_sum(r);
     e = wave_sum(e);
+    if (g.dev) {  // offset form: the moments of rho_r
+      const double rr = ramp_at(g, c);
+      r += rr * g.w0;
+      e += rr * g.we;
+    }
     for (int j = 0; j < DIM; ++j) qq[j] = wave_sum(qq[j]);
     if (lane == 0) {
       tau[c] = (2.0 / 3.0) * e - r;

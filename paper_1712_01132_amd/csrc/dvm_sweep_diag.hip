@@ -23,6 +23,28 @@ namespace {
 // bit 2 (MW): Maxwell walls. A voxel whose axis-j stencil meets a wall (code
 // bit 4 + j) adds a_j (1 - alpha) times its own previous-iteration value of
 // the velocity mirrored in e_j; the record's wall term is alpha rho_w.
+// h at an upstream node (x, y, z) along axis j, as upstream_fluid but without
+// the jump across the x1 wrap (the caller adds it where the value is used, so
+// nothing waits for the load early) and with no branch: the buffer, the node
+// and the velocity slot are selected (uniform values), so the load is issued
+// whatever the case and many can be in flight before the first wait.
+template <typename T>
+__device__ __forceinline__ T upstream_sel(const Dom<T> &g, gptr<const T> hc, gptr<const T> hp, int j, int x, int y,
+                                          int z, int kofs, int kmir) {
+  int c[3] = {x, y, z};
+  const bool in = c[j] >= 0 && c[j] < g.n[j];
+  const Img im = image_of(j, c[j], g.n[j], g.latp);
+  c[j] = in ? c[j] : im.r;
+  const int k = (!in && im.mir) ? kmir : kofs;
+  const gptr<const T> b = in ? hc : hp;
+  return b[cell_of(g, c[0], c[1], c[2]) * g.Kpad + k];
+}
+// The jump that upstream_sel leaves out at x1 = x (images across the wrap).
+template <typename T>
+__device__ __forceinline__ T wrap_jump(const Dom<T> &g, int x) {
+  return (x < 0 ? T(1) : (x >= g.n[0] ? T(-1) : T(0))) * g.jump;
+}
+
 template <typename T, int DIM, int TT, bool Y2WALL, int EXT>
 __global__ void __launch_bounds__(kWave)
     sweep_kernel(const Geo<T> *__restrict__ G, const int *__restrict__ item_off, int nprob, int diag) {
@@ -30,9 +52,12 @@ __global__ void __launch_bounds__(kWave)
   static_assert(!(MW && Y2WALL), "Maxwell walls need stencil rule 1");
   constexpr int NC = TT * TT;
   constexpr int RW = 5 + 3 * DIM + (SH ? DIM : 0);  // record: src (4), nu tau, per axis (c1, c2, w), [q]
+  // 3D: the records of PZ planes (128 voxels) are staged at once, before any
+  // store of them; KV voxels per lane
+  constexpr int PZ = DIM == 3 ? 128 / NC : 1, KV = (PZ * NC + kWave - 1) / kWave;
   __shared__ T rd_lds[8 * kWave];
-  __shared__ T rec[NC * RW];
-  __shared__ uint32_t rcode[NC];
+  __shared__ T rec[PZ * NC * RW];
+  __shared__ uint32_t rcode[PZ * NC];
   const int p = nprob > 1 ? owner_of(item_off, nprob, blockIdx.x) : 0;
   const Geo<T> &G_ = G[p];
   if (!G_.run) return;  // converged problems retire
@@ -44,6 +69,7 @@ __global__ void __launch_bounds__(kWave)
   const gptr<const T> absv = as_global(G_.absv), avv = as_global(G_.av), rden = as_global(G_.rden),
                       vsq = as_global(G_.vsqm);
   const gptr<T> hc = as_global(G_.hcur);
+  const gptr<const T> hcc = hc;
   const gptr<const T> hp = as_global(G_.hprev);
   const gptr<const T> src = as_global(G_.srccur);
   const gptr<const T> srct = as_global(G_.srctcur);
@@ -81,6 +107,8 @@ __global__ void __launch_bounds__(kWave)
   const int q = grp * kWave + lane;
   const bool active = q < Ko;
   const int qq = active ? q : 0;
+  const uint32_t colb = (uint32_t)(G_.Kpad * (int64_t)sizeof(T));  // bytes per voxel
+  constexpr uint32_t kDrop = 0x40000000u;  // past any row's range; two of them do not wrap
   int s[3], sidx[3], pin[3];
 #pragma unroll
   for (int j = 0; j < 3; ++j) {
@@ -109,6 +137,7 @@ __global__ void __launch_bounds__(kWave)
   for (int c = 0; c < (1 << DIM); ++c) rd_lds[c * kWave + lane] = rden[c * Ko_pad + qq];
   const T vsqm = tau_fb ? vsq[qq] : T(0);
   const int kofs = o * Ko_pad + qq;
+  const uint32_t kst = active ? (uint32_t)kofs * (uint32_t)sizeof(T) : kDrop;  // the lane's byte offset in a voxel
   int kmir[3];
 #pragma unroll
   for (int j = 0; j < 3; ++j) kmir[j] = (o ^ (1 << j)) * Ko_pad + qq;
@@ -141,121 +170,123 @@ __global__ void __launch_bounds__(kWave)
   // would cost them their occupancy).
   constexpr bool ZREG = DIM == 3 && TT == 4;
   T ZA[ZREG ? NC : 1], ZB[ZREG ? NC : 1];
+  const int64_t Kp = dm.Kpad;
+  auto zof = [&](int c3) { return s[2] > 0 ? lo[2] + c3 : lo[2] + cnt[2] - 1 - c3; };
+  // the halos of plane z (the current sweep, or the images of the previous
+  // iterate outside the domain). Rows and columns past a ragged tile re-read
+  // its last one: only voxels outside the tile, which are never stored, see them.
+  auto load_halo = [&](int z, T(&L1)[TT], T(&L2)[TT], T(&B1)[TT], T(&B2)[TT]) __attribute__((always_inline)) {
+#pragma unroll
+    for (int k = 0; k < TT; ++k) {
+      const int y = ys + min(k, cnt[1] - 1) * s[1], x = xs + min(k, cnt[0] - 1) * s[0];
+      L1[k] = upstream_sel(dv, hcc, hp, 0, xs - s[0], y, z, kofs, kmir[0]);
+      L2[k] = upstream_sel(dv, hcc, hp, 0, xs - 2 * s[0], y, z, kofs, kmir[0]);
+      B1[k] = upstream_sel(dv, hcc, hp, 1, x, ys - s[1], z, kofs, kmir[1]);
+      B2[k] = upstream_sel(dv, hcc, hp, 1, x, ys - 2 * s[1], z, kofs, kmir[1]);
+    }
+  };
+  // records of the voxels of planes c0 .. c0 + np - 1 (lane l takes voxels
+  // l, l + 64, ...). The voxel's sources and wall values are loaded together
+  // with its flags (valid addresses whatever the flags say) and every record
+  // value is selected, not branched on, so one round trip serves them all.
+  auto stage = [&](int c0, int np) __attribute__((always_inline)) {
+#pragma unroll
+    for (int kv = 0; kv < KV; ++kv) {
+      const int v = lane + kv * kWave;
+      if (KV * kWave > PZ * NC && v >= PZ * NC) break;
+      const int pz = v / NC, i = v % TT, r = (v / TT) % TT;
+      const bool in = pz < np && i < cnt[0] && r < cnt[1];
+      const int x = xs + min(i, cnt[0] - 1) * s[0], y = ys + min(r, cnt[1] - 1) * s[1];
+      const int z = zof(c0 + min(pz, np - 1));
+      const int c = (y + n1 * z) * n0 + x;
+      const uint32_t f = flags[c];
+      const gptr<const T> sp = src + c * kSrcStride;
+      const T sv0 = sp[0], sv1 = sp[1], sv2 = sp[2], sv3 = DIM == 3 ? sp[3] : T(0);
+      const T svt = tau_fb ? srct[c] : T(0);
+      T wv[DIM], qv[DIM];
+#pragma unroll
+      for (int j = 0; j < DIM; ++j) {
+        wv[j] = wall[c * 6 + 2 * j + pin[j]];
+        qv[j] = SH ? srcq[c * 4 + j] : T(0);
+      }
+      const bool fl = in && !(f & F_SOLID);
+      T *rp = rec + v * RW;
+      rp[0] = fl ? sv0 : T(0);  // a skipped voxel's record is 0: it computes 0
+      rp[1] = fl ? sv1 : T(0);
+      rp[2] = fl ? sv2 : T(0);
+      rp[3] = fl ? sv3 : T(0);
+      rp[4] = fl ? svt : T(0);
+      if (SH) {
+#pragma unroll
+        for (int j = 0; j < DIM; ++j) rp[5 + 3 * DIM + j] = fl ? qv[j] : T(0);
+      }
+      uint32_t code = 0;
+#pragma unroll
+      for (int j = 0; j < DIM; ++j) {
+        const uint32_t fj = f >> fbit(j, sidx[j]);
+        const bool first = fj & 1u, y1s = fj & 2u, y2s = fj & 4u;
+        T c1 = first ? (y1s ? T(0) : T(1)) : T(2);
+        T c2 = first ? T(0) : T(-0.5);
+        T w = (first && y1s) ? (MW ? alpha * wv[j] : wv[j]) : T(0);
+        if (Y2WALL && fl && !first && y2s) {
+          c2 = T(0);
+          w = T(-0.5) * wall_at_y1(dm, wall, j, s[j], pin[j], x, y, z);
+        }
+        rp[5 + 3 * j] = fl ? c1 : T(0);
+        rp[6 + 3 * j] = fl ? c2 : T(0);
+        rp[7 + 3 * j] = fl ? w : T(0);
+        code |= (first ? 1u : 0u) << j;
+        if (MW && first && y1s) code |= 16u << j;
+      }
+      rcode[v] = fl ? code : R_SKIP;
+    }
+  };
 
-  for (int c3 = 0; c3 < cnt[2]; ++c3) {
-    const int z = s[2] > 0 ? lo[2] + c3 : lo[2] + cnt[2] - 1 - c3;
-    // --- halos of the plane (before any store of this plane), issued first:
-    // they depend on nothing below. Away from the domain faces they are plain
-    // loads of the current sweep; only tiles touching a face resolve images.
-    T L1[TT], L2[TT], B1[TT], B2[TT];
-    const int64_t Kp = dm.Kpad;
-    const gptr<T> hz = hc + (int64_t)(n1 * z) * n0 * Kp + kofs;  // plane z of the current sweep
-    const bool xin = xs - 2 * s[0] >= 0 && xs - 2 * s[0] < n0;
-    const bool yin = ys - 2 * s[1] >= 0 && ys - 2 * s[1] < n1;
+  const T jx1 = wrap_jump(dv, xs - s[0]), jx2 = wrap_jump(dv, xs - 2 * s[0]);  // the same for every plane
+  // the tile's first plane: records, halos and (4 x 4 tiles in 3D) the two
+  // planes below, all issued before any wait
+  T L1[TT], L2[TT], B1[TT], B2[TT];
+  stage(0, min(PZ, cnt[2]));
+  load_halo(zof(0), L1, L2, B1, B2);
+  if (ZREG) {
+    const int z = zof(0);
 #pragma unroll
-    for (int k = 0; k < TT; ++k) {
-      L1[k] = L2[k] = B1[k] = B2[k] = T(0);
-      if (k < cnt[1]) {
-        const int y = ys + k * s[1];
-        if (xin) {
-          L1[k] = hz[(int64_t)(y * n0 + xs - s[0]) * Kp];
-          L2[k] = hz[(int64_t)(y * n0 + xs - 2 * s[0]) * Kp];
-        } else {
-          L1[k] = upstream_fluid(dv, hc, hp, 0, xs - s[0], y, z, kofs, kmir[0]);
-          L2[k] = upstream_fluid(dv, hc, hp, 0, xs - 2 * s[0], y, z, kofs, kmir[0]);
-        }
-      }
-      if (k < cnt[0]) {
-        const int x = xs + k * s[0];
-        if (yin) {
-          B1[k] = hz[(int64_t)((ys - s[1]) * n0 + x) * Kp];
-          B2[k] = hz[(int64_t)((ys - 2 * s[1]) * n0 + x) * Kp];
-        } else {
-          B1[k] = upstream_fluid(dv, hc, hp, 1, x, ys - s[1], z, kofs, kmir[1]);
-          B2[k] = upstream_fluid(dv, hc, hp, 1, x, ys - 2 * s[1], z, kofs, kmir[1]);
-        }
-      }
+    for (int v = 0; v < (ZREG ? NC : 0); ++v) {
+      const int x = xs + min(v % TT, cnt[0] - 1) * s[0], y = ys + min(v / TT, cnt[1] - 1) * s[1];
+      ZA[v] = upstream_sel(dv, hcc, hp, 2, x, y, z - s[2], kofs, kmir[2]);
+      ZB[v] = upstream_sel(dv, hcc, hp, 2, x, y, z - 2 * s[2], kofs, kmir[2]);
     }
-    // --- stage: lane = voxel of the plane ---------------------------------
-    // The voxel's sources and wall values are loaded together with its flags
-    // (valid addresses whatever the flags say), so one round trip serves all.
-    if (lane < NC) {
-      const int i = lane % TT, r = lane / TT;
-      uint32_t code = R_SKIP;
-      T *rp = rec + lane * RW;
-#pragma unroll
-      for (int k = 0; k < RW; ++k) rp[k] = T(0);  // a skipped voxel computes 0
-      if (i < cnt[0] && r < cnt[1]) {
-        const int x = xs + i * s[0], y = ys + r * s[1];
-        const int c = (y + n1 * z) * n0 + x;
-        const uint32_t f = flags[c];
-        const gptr<const T> sp = src + c * kSrcStride;
-        const T sv0 = sp[0], sv1 = sp[1], sv2 = sp[2], sv3 = DIM == 3 ? sp[3] : T(0);
-        const T svt = tau_fb ? srct[c] : T(0);
-        T wv[DIM];
-#pragma unroll
-        for (int j = 0; j < DIM; ++j) wv[j] = wall[c * 6 + 2 * j + pin[j]];
-        if (!(f & F_SOLID)) {
-          rp[0] = sv0;
-          rp[1] = sv1;
-          rp[2] = sv2;
-          rp[3] = sv3;
-          rp[4] = svt;
-          if (SH) {
-#pragma unroll
-            for (int j = 0; j < DIM; ++j) rp[5 + 3 * DIM + j] = srcq[c * 4 + j];
-          }
-          code = 0;
-#pragma unroll
-          for (int j = 0; j < DIM; ++j) {
-            const uint32_t fj = f >> fbit(j, sidx[j]);
-            const bool first = fj & 1u, y1s = fj & 2u, y2s = fj & 4u;
-            T c1 = first ? (y1s ? T(0) : T(1)) : T(2);
-            T c2 = first ? T(0) : T(-0.5);
-            T w = (first && y1s) ? (MW ? alpha * wv[j] : wv[j]) : T(0);
-            if (Y2WALL && !first && y2s) {
-              c2 = T(0);
-              w = T(-0.5) * wall_at_y1(dm, wall, j, s[j], pin[j], x, y, z);
-            }
-            rp[5 + 3 * j] = c1;
-            rp[6 + 3 * j] = c2;
-            rp[7 + 3 * j] = w;
-            code |= (first ? 1u : 0u) << j;
-            if (MW && first && y1s) code |= 16u << j;
-          }
-        }
-      }
-      rcode[lane] = code;
+  }
+  __syncthreads();
+  // one plane; the first is peeled off the loop, so that the loop is entered,
+  // as it is re-entered, right after a plane's stores: its waits for the
+  // halos loaded ahead then never cover those stores
+  auto plane = [&](int c3) __attribute__((always_inline)) {
+    const int z = zof(c3);
+    const int pz = c3 % PZ;
+    if (c3 > 0 && pz == 0) {  // the next chunk of records (only LDS is written here)
+      __syncthreads();
+      stage(c3, min(PZ, cnt[2] - c3));
+      __syncthreads();
     }
-    const bool zin = DIM == 3 && z - 2 * s[2] >= 0 && z - 2 * s[2] < dm.n[2];
-    const int64_t zstep = (int64_t)n1 * n0 * Kp * s[2];
-    if (ZREG && c3 == 0) {
+    // the next plane's halos (the last plane re-reads its own), issued before
+    // this plane's stores: waiting for them then does not wait for the stores
+    T L1n[TT], L2n[TT], B1n[TT], B2n[TT];
+    if (DIM == 3) load_halo(zof(min(c3 + 1, cnt[2] - 1)), L1n, L2n, B1n, B2n);
+    const T *recp = rec + pz * NC * RW;
+    const uint32_t *rcodep = rcode + pz * NC;
+    // stores: one buffer resource per row of the tile (a row of h spans below
+    // 1 GiB, checked by the host); a voxel that is not stored (solid, past a
+    // ragged tile) or a lane past the octant gets an offset past the
+    // resource's range, which the hardware drops. No branch around the
+    // stores, so the wait counts stay exact and a wait for the next plane's
+    // halos never waits for this plane's stores.
+    __amdgpu_buffer_rsrc_t rowrs[TT];
 #pragma unroll
-      for (int v = 0; v < (ZREG ? NC : 0); ++v) {
-        const int i = v % TT, r = v / TT;
-        ZA[v] = ZB[v] = T(0);
-        if (i < cnt[0] && r < cnt[1]) {
-          const int x = xs + i * s[0], y = ys + r * s[1];
-          if (zin) {
-            const gptr<const T> hv0 = hz + (int64_t)(y * n0 + x) * Kp;
-            ZA[v] = hv0[-zstep];
-            ZB[v] = hv0[-2 * zstep];
-          } else {
-            ZA[v] = upstream_fluid(dv, hc, hp, 2, x, y, z - s[2], kofs, kmir[2]);
-            ZB[v] = upstream_fluid(dv, hc, hp, 2, x, y, z - 2 * s[2], kofs, kmir[2]);
-          }
-        }
-      }
-    }
-    __syncthreads();
-    // store addresses: row r of the tile starts at hrow[r]; voxel i of a row is icol[i] further
-    gptr<T> hrow[TT];
-    int64_t icol[TT];
-#pragma unroll
-    for (int k = 0; k < TT; ++k) {
-      hrow[k] = hz + (int64_t)((ys + k * s[1]) * n0 + xs) * Kp;
-      icol[k] = (int64_t)k * s[0] * Kp;
-    }
+    for (int k = 0; k < TT; ++k)
+      rowrs[k] = __builtin_amdgcn_make_buffer_rsrc(
+          (void *)(T *)(hc + (int64_t)(n1 * z + ys + min(k, cnt[1] - 1) * s[1]) * n0 * Kp), (short)0,
+          (int)(colb * (uint32_t)n0), kBufferFlags);
     // --- the plane's anti-diagonals ---------------------------------------
     T D1[TT], D2[TT];
 #pragma unroll
@@ -271,16 +302,10 @@ __global__ void __launch_bounds__(kWave)
         Nc[r] = R_SKIP;
         Z1[r] = Z2[r] = T(0);
         const int i = d - r;
-        if (DIM == 3 && !ZREG && i >= 0 && i < TT && i < cnt[0] && r < cnt[1]) {
-          const int x = xs + i * s[0], y = ys + r * s[1];
-          if (zin) {
-            const gptr<const T> hv0 = hz + (int64_t)(y * n0 + x) * Kp;
-            Z1[r] = hv0[-zstep];
-            Z2[r] = hv0[-2 * zstep];
-          } else {
-            Z1[r] = upstream_fluid(dv, hc, hp, 2, x, y, z - s[2], kofs, kmir[2]);
-            Z2[r] = upstream_fluid(dv, hc, hp, 2, x, y, z - 2 * s[2], kofs, kmir[2]);
-          }
+        if (DIM == 3 && !ZREG && i >= 0 && i < TT) {
+          const int x = xs + min(i, cnt[0] - 1) * s[0], y = ys + min(r, cnt[1] - 1) * s[1];
+          Z1[r] = upstream_sel(dv, hcc, hp, 2, x, y, z - s[2], kofs, kmir[2]);
+          Z2[r] = upstream_sel(dv, hcc, hp, 2, x, y, z - 2 * s[2], kofs, kmir[2]);
         }
       }
 #pragma unroll
@@ -289,8 +314,8 @@ __global__ void __launch_bounds__(kWave)
         if (i < 0 || i >= TT) continue;
         // no branch before the store: the loads of all voxels of the
         // anti-diagonal can be issued together (a skipped voxel's record is 0)
-        const uint32_t code = __builtin_amdgcn_readfirstlane(rcode[i + TT * r]);
-        const T *rp = rec + (i + TT * r) * RW;
+        const uint32_t code = __builtin_amdgcn_readfirstlane(rcodep[i + TT * r]);
+        const T *rp = recp + (i + TT * r) * RW;
         T num = fma(rp[1], vv[0], PSI ? rp[0] * ph : rp[0]);
         num = fma(rp[2], vv[1], num);
         if (DIM == 3) num = fma(rp[3], vv[2], num);
@@ -301,13 +326,14 @@ __global__ void __launch_bounds__(kWave)
         }
         if (MW) {
           // the voxel's own previous iterate at the mirrored velocity (a uniform branch)
-          const gptr<const T> hv_prev = hp + ((hrow[r] + icol[i]) - hc) - kofs;
+          const gptr<const T> hv_prev =
+              hp + (int64_t)((n1 * z + ys + r * s[1]) * n0 + xs + i * s[0]) * Kp;
 #pragma unroll
           for (int j = 0; j < DIM; ++j)
             if (code & (16u << j)) num = fma(am[j], hv_prev[kmir[j]], num);
         }
-        const T x1a = i >= 1 ? D1[r] : L1[r];
-        const T x1b = i >= 2 ? D2[r] : (i == 1 ? L1[r] : L2[r]);
+        const T x1a = i >= 1 ? D1[r] : L1[r] + jx1;
+        const T x1b = i >= 2 ? D2[r] : (i == 1 ? L1[r] + jx1 : L2[r] + jx2);
         const T x2a = r >= 1 ? D1[r >= 1 ? r - 1 : 0] : B1[i];
         const T x2b = r >= 2 ? D2[r >= 2 ? r - 2 : 0] : (r == 1 ? B1[i] : B2[i]);
         num = fma(aa[0], fma(rp[5], x1a, fma(rp[6], x1b, PSI ? rp[7] * ph : rp[7])), num);
@@ -329,7 +355,8 @@ __global__ void __launch_bounds__(kWave)
       for (int r = 0; r < TT; ++r) {
         const int i = d - r;
         if (i < 0 || i >= TT) continue;
-        if (active && !(Nc[r] & R_SKIP)) __builtin_nontemporal_store(Nw[r], &hrow[r][icol[i]]);
+        const uint32_t at = (Nc[r] & R_SKIP) ? kDrop : (uint32_t)(xs + i * s[0]) * colb;
+        buffer_store(Nw[r], rowrs[r], kst + at, 0u);
       }
 #pragma unroll
       for (int r = 0; r < TT; ++r) {
@@ -337,8 +364,18 @@ __global__ void __launch_bounds__(kWave)
         D1[r] = Nw[r];
       }
     }
-    __syncthreads();  // the next plane's staging overwrites the records
-  }
+    if (DIM == 3) {
+#pragma unroll
+      for (int k = 0; k < TT; ++k) {
+        L1[k] = L1n[k];
+        L2[k] = L2n[k];
+        B1[k] = B1n[k];
+        B2[k] = B2n[k];
+      }
+    }
+  };
+  plane(0);
+  for (int c3 = 1; c3 < cnt[2]; ++c3) plane(c3);
 }
 
 }  // namespace
