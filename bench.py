@@ -76,10 +76,20 @@ MOM_TRAFFIC = {("c3239c6f9d2af279", "rows-xcd", (4, 4)): 879.8e6 + 12.8e6}
 
 
 def kernel_source_hash():
+    """sha256 prefix over the iteration's kernel sources (dvm_*.hip, dvm_*.h)."""
+    import glob
     import hashlib
-    p = os.path.join(ROOT, "paper_1712_01132_amd", "csrc", "dvm_kernels.hip")
-    with open(p, "rb") as f:
-        return hashlib.sha256(f.read()).hexdigest()[:16]
+    h = hashlib.sha256()
+    csrc = os.path.join(ROOT, "paper_1712_01132_amd", "csrc")
+    for p in sorted(glob.glob(os.path.join(csrc, "dvm_*.hip")) + glob.glob(os.path.join(csrc, "dvm_*.h"))):
+        h.update(os.path.basename(p).encode())
+        with open(p, "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()[:16]
+
+
+SWEEP_KERNEL = {"diagonals": "sweep_kernel", "queue": "sweep_queue_kernel", "strips": "sweep_strips_kernel",
+                "rows": "sweep_rows_kernel", "rows-xcd": "sweep_rows_kernel"}
 
 
 def roofline(tm, elem, traffic_key=None, schedule="diagonals"):
@@ -92,7 +102,7 @@ def roofline(tm, elem, traffic_key=None, schedule="diagonals"):
     mom_traffic = MOM_TRAFFIC.get(traffic_key) if traffic_key else None
     return {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
             "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
-            "kernel": "sweep_kernel" if schedule == "diagonals" else "sweep_rows_kernel",
+            "kernel": SWEEP_KERNEL.get(schedule, schedule),
             "bytes_per_launch": per_launch, "launch_ms": tm["sweep_ms_per_launch"],
             "launches_per_iter": tm["sweep_launches_per_iter"],
             "moments_kernel": {"bytes_per_launch": per_iter, "launch_ms": tm["moments_ms_per_launch"],
@@ -119,14 +129,67 @@ FP32_MAX_ITERS = 40000
 TTR_MAX_ITERS = 60000
 
 
-def _ttr_fp64(mask, nv, kn, tile, tol=1e-6):
-    from paper_1712_01132_amd import poredvm
+def _fields(s):
+    """rho, u, tau and q of a solver (FP64 host arrays)."""
+    rho, u, tau, q = s.moments(diagnostics=True)
+    return {"rho": rho, "u": u, "tau": tau, "q": q}
+
+
+def field_errors(f32, k32, f64, k64, mask):
+    """Errors of one solution against another, relative to the other's range
+    over the fluid voxels: max |a - b| / max |b| for rho and tau minus their
+    fluid means and for u and q (all components); |k_a - k_b| / |k_b|."""
+    import numpy as np
+    fl = mask == 0
+
+    def rel(a, b, centre):
+        a = a[..., fl]
+        b = b[..., fl]
+        if centre:
+            a = a - a.mean()
+            b = b - b.mean()
+        sc = float(np.abs(b).max())
+        return float(np.abs(a - b).max()) / (sc if sc > 0 else 1.0)
+
+    return {"rho_minus_mean": rel(f32["rho"], f64["rho"], True), "u": rel(f32["u"], f64["u"], False),
+            "tau_minus_mean": rel(f32["tau"], f64["tau"], True), "q": rel(f32["q"], f64["q"], False),
+            "k": abs(k32 - k64) / abs(k64)}
+
+
+def _ttr_fp64(mask, nv, kn, tile, tol=1e-6, ramp=False, keep=None):
+    from paper_1712_01132_amd import poredvm, warmstart
     s = poredvm.Solver(mask, nv, kn, precision="fp64", tile=tile)
+    if ramp:
+        s.set_initial(*warmstart.ramp_start(mask))
     t0 = time.perf_counter()
     r = s.iterate(TTR_MAX_ITERS, tol)
     dt = time.perf_counter() - t0
+    if keep is not None:
+        keep["fields"] = _fields(s)
     s.close()
     return {"seconds": dt, "iterations": r["total_iters"], "k": r["k"], "converged": r["converged"]}
+
+
+def _ttr_fp32_alone(mask, nv, kn, tile32, net=None, trial=50, tol=1e-6, keep=None):
+    """The FP32 iteration by itself to r <= tol (the offset form of h reaches
+    it), from the pressure ramp or from a network's prediction judged against
+    the ramp as in _ttr_fp32_then_fp64."""
+    from paper_1712_01132_amd import poredvm, warmstart
+    t0 = time.perf_counter()
+    used = False
+    if net is not None:
+        start = net.predict(mask, kn)
+        a, used, _, _ = warmstart.judged_start(mask, nv, kn, start, trial=trial, precision="fp32", tile=tile32)
+    else:
+        a = poredvm.Solver(mask, nv, kn, precision="fp32", tile=tile32)
+        a.set_initial(*warmstart.ramp_start(mask))
+    r = a.iterate(TTR_MAX_ITERS, tol)
+    dt = time.perf_counter() - t0
+    if keep is not None:
+        keep["fields"] = _fields(a)
+    a.close()
+    return {"seconds": dt, "iterations": r["total_iters"], "k": r["k"], "converged": r["converged"],
+            "warm_start_used": used}
 
 
 def _ttr_fp32_then_fp64(mask, nv, kn, tile, tile32, net=None, trial=50, tol=1e-6, ramp=False):
@@ -207,9 +270,16 @@ def model_timing(mask, nv, kn, fluid, K, steps=40, warmup=5):
 
 def time_to_residual(mask, nv, kn, tile, tile32):
     out = {}
+    f64 = {}
     log("time to r<=1e-6, FP64 from rest")
-    out["fp64"] = _ttr_fp64(mask, nv, kn, tile)
+    out["fp64"] = _ttr_fp64(mask, nv, kn, tile, keep=f64)
     log("  %s" % json.dumps(out["fp64"]))
+    log("time to r<=1e-6, FP32 alone from the pressure ramp")
+    f32 = {}
+    out["fp32_ramp_alone"] = _ttr_fp32_alone(mask, nv, kn, tile32, keep=f32)
+    out["fp32_ramp_alone"]["errors_vs_fp64"] = field_errors(f32["fields"], out["fp32_ramp_alone"]["k"],
+                                                            f64["fields"], out["fp64"]["k"], mask)
+    log("  %s" % json.dumps(out["fp32_ramp_alone"]))
     log("time to r<=1e-6, FP32 from rest, finished in FP64")
     out["fp32_then_fp64"] = _ttr_fp32_then_fp64(mask, nv, kn, tile, tile32)
     log("  %s" % json.dumps(out["fp32_then_fp64"]))
@@ -228,18 +298,61 @@ def time_to_residual(mask, nv, kn, tile, tile32):
         log("time to r<=1e-6, FP32 from the network's prediction (50-iteration trial against the ramp), "
             "finished in FP64")
         res = _ttr_fp32_then_fp64(mask, nv, kn, tile, tile32, net=net, trial=50)
-        net.close()
         out["fp32_warm_then_fp64"] = res
         log("  %s" % json.dumps(res))
+        log("time to r<=1e-6, FP32 alone from the network's prediction (judged against the ramp)")
+        fw = {}
+        res = _ttr_fp32_alone(mask, nv, kn, tile32, net=net, trial=50, keep=fw)
+        res["errors_vs_fp64"] = field_errors(fw["fields"], res["k"], f64["fields"], out["fp64"]["k"], mask)
+        out["fp32_warm_alone"] = res
+        log("  %s" % json.dumps(res))
+        net.close()
     k64 = out["fp64"]["k"]
-    for key in ("fp32_then_fp64", "fp32_ramp_then_fp64", "fp32_warm_then_fp64"):
+    for key in ("fp32_then_fp64", "fp32_ramp_then_fp64", "fp32_warm_then_fp64", "fp32_ramp_alone",
+                "fp32_warm_alone"):
         if "k" in out[key]:
             out[key]["k_rel_diff_vs_fp64"] = abs(out[key]["k"] - k64) / abs(k64)
             out[key]["speedup_vs_fp64"] = out["fp64"]["seconds"] / out[key]["seconds"]
     out["note"] = ("seconds from the first iteration launch: network inference, the FP32 solvers' "
                    "creation, the 50-iteration trial and the FP32->FP64 handover are included; the FP64 "
                    "solver's creation and weight loading are not. r is the field residual "
-                   "max|du|/max|u| in FP64")
+                   "max|du|/max|u| in FP64. errors_vs_fp64: the FP32 solution at r <= 1e-6 against the "
+                   "FP64 one at r <= 1e-6 (from rest), relative to the FP64 field's range over the fluid")
+    return out
+
+
+def pack3d_precision_errors(m3, tile3, sched3, tol=1e-6):
+    """The 96^3 pack, Kn = 0.5: FP32 and FP64 each from the pressure ramp to
+    r <= tol, per-result errors as in field_errors."""
+    from paper_1712_01132_amd import poredvm, warmstart
+    res, fields = {}, {}
+    for prec in ("fp64", "fp32"):
+        log("pack3d %s from the ramp to r<=%g" % (prec, tol))
+        s = poredvm.Solver(m3, [16, 16, 16], 0.5, precision=prec, tile=tile3, schedule=sched3)
+        s.set_initial(*warmstart.ramp_start(m3))
+        t0 = time.perf_counter()
+        r = s.iterate(20000, tol)
+        res[prec] = {"seconds": time.perf_counter() - t0, "iterations": r["total_iters"], "k": r["k"],
+                     "converged": r["converged"], "schedule": s.schedule}
+        fields[prec] = _fields(s)
+        s.close()
+        log("  %s" % json.dumps(res[prec]))
+    res["errors_vs_fp64"] = field_errors(fields["fp32"], res["fp32"]["k"], fields["fp64"], res["fp64"]["k"], m3)
+    return res
+
+
+def precision_errors(mask, nv, tile, tile32, kns=(0.1, 10.0), tol=1e-6):
+    """FP32 against FP64 on the rock at other Kn: each from the pressure ramp
+    to r <= tol, per-result errors as in field_errors."""
+    out = {}
+    for kn in kns:
+        log("FP32 vs FP64 at Kn=%g, both from the ramp to r<=%g" % (kn, tol))
+        f64, f32 = {}, {}
+        a = _ttr_fp64(mask, nv, kn, tile, tol=tol, ramp=True, keep=f64)
+        b = _ttr_fp32_alone(mask, nv, kn, tile32, tol=tol, keep=f32)
+        out["kn_%g" % kn] = {"fp64": a, "fp32": b,
+                             "errors_vs_fp64": field_errors(f32["fields"], b["k"], f64["fields"], a["k"], mask)}
+        log("  %s" % json.dumps(out["kn_%g" % kn]))
     return out
 
 
@@ -315,31 +428,34 @@ def main():
         s.close()
         extra["rock2d_fp32"] = {"updates_per_s": u32, "ms_per_step": 1e3 * d32 / args.steps,
                                 "tile": list(tile32), "autotune_ms_per_iteration": tune32,
-                                "roofline": roofline(t32, 4, None, sched32)}
+                                "roofline": roofline(t32, 4, (kernel_source_hash(), sched32, tuple(tile32)), sched32)}
         log("FP32: %.3e updates/s" % u32)
         # time to residual 1e-6: FP64 from rest, and the FP32 forms finished in FP64
         extra["rock2d_time_to_residual_1e-6"] = time_to_residual(mask, nv, args.kn, list(tile64), list(tile32))
+        extra["rock2d_fp32_vs_fp64"] = precision_errors(mask, nv, list(tile64), list(tile32))
         # 3D pack
         log("generating the 96^3 sphere pack (seed 7)")
         m3 = geometry.workload_pack3d(seed=7)
         f3 = int((m3 == 0).sum())
-        tile3, tune3 = autotune.best_tile(m3, [16, 16, 16], "fp32", iters=2, use_cache=False)
-        log("3D tile %s (autotuner: %s)" % (tile3, tune3))
-        s = poredvm.Solver(m3, [16, 16, 16], 0.5, precision="fp32", tile=list(tile3))
+        (sched3, tile3), tune3 = autotune.best_config(m3, [16, 16, 16], "fp32", iters=2, use_cache=False)
+        log("3D schedule %s, tile %s (autotuner: %s)" % (sched3, tile3, tune3))
+        s = poredvm.Solver(m3, [16, 16, 16], 0.5, precision="fp32", tile=list(tile3), schedule=sched3)
         u3, d3 = timed_updates(s, f3, 4096, 20, 3)
         t3 = s.time_kernels(3)
         s.close()
         extra["pack3d_fp32"] = {"updates_per_s": u3, "ms_per_step": 1e3 * d3 / 20, "fluid_voxels": f3,
-                                "tile": list(tile3), "autotune_ms_per_iteration": tune3,
-                                "velocities": 4096, "roofline": roofline(t3, 4)}
+                                "tile": list(tile3), "schedule": sched3, "autotune_ms_per_iteration": tune3,
+                                "velocities": 4096,
+                                "roofline": roofline(t3, 4, (kernel_source_hash(), sched3, tuple(tile3)), sched3)}
         log("3D pack FP32: %.3e updates/s, %s" % (u3, json.dumps(t3)))
+        extra["pack3d_fp32_vs_fp64"] = pack3d_precision_errors(m3, list(tile3), sched3)
         # 64-problem batch
         log("generating the 64-problem batch")
         probs = geometry.workload_batch(64)
         fb = sum(int((m == 0).sum()) for m, _ in probs)
-        tileb, tuneb = autotune.best_tile(probs, [24, 24], "fp32", iters=3, use_cache=False)
-        log("batch tile %s (autotuner: %s)" % (tileb, tuneb))
-        b = poredvm.Batch(probs, [24, 24], precision="fp32", tile=list(tileb))
+        (schedb, tileb), tuneb = autotune.best_config(probs, [24, 24], "fp32", iters=3, use_cache=False)
+        log("batch schedule %s, tile %s (autotuner: %s)" % (schedb, tileb, tuneb))
+        b = poredvm.Batch(probs, [24, 24], precision="fp32", tile=list(tileb), schedule=schedb)
         b.iterate(3)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
@@ -349,9 +465,9 @@ def main():
         tb = b.time_kernels(3)
         b.close()
         extra["batch64_fp32"] = {"updates_per_s": fb * 576 * 30 / db, "ms_per_step": 1e3 * db / 30,
-                                 "tile": list(tileb), "autotune_ms_per_iteration": tuneb,
+                                 "tile": list(tileb), "schedule": schedb, "autotune_ms_per_iteration": tuneb,
                                  "fluid_voxels": fb, "velocities": 576, "problems": 64,
-                                 "roofline": roofline(tb, 4)}
+                                 "roofline": roofline(tb, 4, (kernel_source_hash(), schedb, tuple(tileb)), schedb)}
         log("batch64 FP32: %.3e updates/s" % (fb * 576 * 30 / db))
         extra["warmstart_unet"] = unet_timing()
         extra["rock2d_models_fp64"] = model_timing(mask, nv, args.kn, fluid, K)

@@ -71,12 +71,20 @@ enum { PDVM_STOP_FIELD = 0, PDVM_STOP_PAPER_ERR = 1 };
  *            chain on one XCD (probed at creation, else PDVM_E_UNSUPPORTED);
  *            only on request (slower than ROWS on one problem and than
  *            DIAGONALS on batches, as measured);
+ * QUEUE:     one launch for all problems of the batch (2D or 3D): the tiles
+ *            of every velocity chain wait in the queue of one XCD, in diagonal
+ *            order; a block takes tiles from its own XCD's queue and waits for
+ *            each tile's upstream neighbours' done flags (cheap: through that
+ *            XCD's L2). Needs blocks on all 8 XCDs (probed at creation, else
+ *            PDVM_E_UNSUPPORTED); an iterate whose queues were not all drained
+ *            is discarded as for ROWS;
  * AUTO:      for a single 2D problem, ROWS when a probe of the block placement
  *            at creation shows that every velocity chain runs on one XCD (cheap
- *            synchronisation through its L2); DIAGONALS otherwise (batches
- *            keep the machine fuller with per-diagonal launches). */
+ *            synchronisation through its L2); for a 2D batch with tile edge 8,
+ *            QUEUE when the probe finds all 8 XCDs; DIAGONALS otherwise (as
+ *            measured faster for 3D problems and 4x4 tiles). */
 enum { PDVM_SCHEDULE_AUTO = 0, PDVM_SCHEDULE_DIAGONALS = 1, PDVM_SCHEDULE_ROWS = 2, PDVM_SCHEDULE_ROWS_AGENT = 3,
-       PDVM_SCHEDULE_STRIPS = 4 };
+       PDVM_SCHEDULE_STRIPS = 4, PDVM_SCHEDULE_QUEUE = 5 };
 
 typedef struct pdvm_solver pdvm_solver;
 
@@ -247,7 +255,7 @@ int pdvm_batch_get_flux(pdvm_solver *s, int32_t i, double *gp, double *k, double
 /* The sweep schedule in use: 0 tile diagonals; 1 row pipeline with
  * agent-scope synchronisation; 2 row pipeline with every velocity chain on one
  * XCD (chosen only after a probe of the block placement confirms it); 3 strip
- * pipeline; -1 for NULL. */
+ * pipeline; 4 per-XCD tile queues; -1 for NULL. */
 int32_t pdvm_sweep_schedule(const pdvm_solver *s);
 
 /* Wall-clock bound on each wait of the row-pipeline sweep for its upstream row

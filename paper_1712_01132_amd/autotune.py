@@ -1,13 +1,15 @@
-"""Sweep-tile autotuner.
+"""Sweep schedule and tile autotuner.
 
 The sweep kernel is compiled for square tile edges 4 and 8 in (x1, x2). A tile
 may be narrower than its compiled edge along either axis and of any depth
 along x3. The best shape depends on the problem size (tiles per tile diagonal
 against diagonals per iteration), on the precision and on the number of
-velocity groups. `best_tile` times each candidate with the library's own
-per-kernel HIP-event timing (pdvm_time_kernels) on the real problem, or on the
-real batch, and keeps the fastest per size class. The choice is cached in a
-JSON file (PDVM_AUTOTUNE_CACHE, default ~/.cache/poredvm/autotune.json).
+velocity groups; for batches and 3D problems the schedule (per-XCD tile
+queues in one launch, or one launch per tile diagonal) is tuned with it.
+`best_config` times each candidate with the library's own per-kernel HIP-event
+timing (pdvm_time_kernels) on the real problem, or on the real batch, and
+keeps the fastest per size class. The choice is cached in a JSON file
+(PDVM_AUTOTUNE_CACHE, default ~/.cache/poredvm/autotune.json).
 """
 import json
 import math
@@ -66,31 +68,58 @@ def _time(make, iters):
         s.close()
 
 
-def best_tile(problems, nv, precision="fp32", iters=5, candidates=None, use_cache=True, verbose=False):
-    """Fastest tile for `problems`: one mask, or a list of (mask, kn) for a
-    batch (timed as a batch). Returns (tile, {tile: ms per iteration})."""
+# Sweep schedules the tuner compares besides the automatic choice: the
+# per-XCD tile queues (one launch per iteration) and the per-diagonal launches
+# for 3D problems and batches. (A single 2D problem keeps the row pipeline,
+# measured 2-2.5x faster than both on the 512^2 rock.)
+SCHEDULES_MULTI = ("queue", "diagonals")
+
+
+def best_config(problems, nv, precision="fp32", iters=5, candidates=None, schedules=None, use_cache=True,
+                verbose=False):
+    """Fastest (schedule, tile) for `problems`: one mask, or a list of
+    (mask, kn) for a batch (timed as a batch). Returns ((schedule, tile),
+    {"schedule:tile": ms per iteration})."""
     batch = isinstance(problems, list)
     shapes = [m.shape for m, _ in problems] if batch else [problems.shape]
-    key = size_class(shapes, nv, precision)
-    cache = _load_cache() if use_cache else {}
-    if key in cache:
-        return tuple(cache[key]["tile"]), cache[key]["ms"]
     dim = len(shapes[0])
     cands = candidates or (CANDIDATES_2D if dim == 2 else CANDIDATES_3D)
+    if schedules is None:
+        schedules = SCHEDULES_MULTI if (batch or dim == 3) else ("auto",)
+    key = "+".join(schedules) + "-" + size_class(shapes, nv, precision)
+    cache = _load_cache() if use_cache else {}
+    if key in cache:
+        return (cache[key]["schedule"], tuple(cache[key]["tile"])), cache[key]["ms"]
     res = {}
-    for tile in cands:
-        if batch:
-            def make(tile=tile):
-                return poredvm.Batch(problems, nv, precision=precision, tile=list(tile))
-        else:
-            def make(tile=tile):
-                return poredvm.Solver(problems, nv, 1.0, precision=precision, tile=list(tile))
-        res[tile] = _time(make, iters)
-        if verbose:
-            print("[autotune] %s tile %s: %.3f ms/iteration" % (key, tile, res[tile]), flush=True)
+    for sched in schedules:
+        for tile in cands:
+            if batch:
+                def make(tile=tile, sched=sched):
+                    return poredvm.Batch(problems, nv, precision=precision, tile=list(tile), schedule=sched)
+            else:
+                def make(tile=tile, sched=sched):
+                    return poredvm.Solver(problems, nv, 1.0, precision=precision, tile=list(tile), schedule=sched)
+            try:
+                res[(sched, tile)] = _time(make, iters)
+            except poredvm.PdvmError as e:
+                if e.code != poredvm.PDVM_E_UNSUPPORTED:
+                    raise
+                continue  # e.g. the queue without blocks on every XCD
+            if verbose:
+                print("[autotune] %s %s tile %s: %.3f ms/iteration" % (key, sched, tile, res[(sched, tile)]),
+                      flush=True)
     best = min(res, key=res.get)
+    ms = {"%s:%s" % (k[0], "x".join(map(str, k[1]))): v for k, v in res.items()}
     if use_cache:
         cache = _load_cache()
-        cache[key] = {"tile": list(best), "ms": {"x".join(map(str, k)): v for k, v in res.items()}}
+        cache[key] = {"schedule": best[0], "tile": list(best[1]), "ms": ms}
         _save_cache(cache)
-    return best, {"x".join(map(str, k)): v for k, v in res.items()}
+    return best, ms
+
+
+def best_tile(problems, nv, precision="fp32", iters=5, candidates=None, use_cache=True, verbose=False):
+    """Fastest tile for `problems` under the automatic schedule. Returns
+    (tile, {tile: ms per iteration})."""
+    (_, tile), ms = best_config(problems, nv, precision, iters, candidates, schedules=("auto",),
+                                use_cache=use_cache, verbose=verbose)
+    return tile, {k.split(":", 1)[1]: v for k, v in ms.items()}

@@ -37,8 +37,9 @@ struct Ctl {
   int32_t status;       // 0 running, 1 converged, 2 budget reached, -4 non-finite,
                         // -3 sweep abandoned (see fault)
   int32_t mode;         // 0 field residual, 1 paper Err(l)
-  int32_t fault;        // a row-pipeline sweep was abandoned: 1 a wait gave up, 2 the
-                        // blocks of a velocity chain ran on different XCDs. The iterate
+  int32_t fault;        // a pipelined sweep was abandoned: 1 a wait gave up, 2 the
+                        // blocks of a velocity chain ran on different XCDs (row and
+                        // strip pipelines) or a queue sweep left tiles unswept. The iterate
                         // is discarded (par kept); only the host clears it
                         // (set_initial / set_state), so a poisoned problem stays stopped
   int32_t pad_;
@@ -122,6 +123,10 @@ struct Geo {
   // kernel discards the iterate unless all blocks of each chain agree
   uint8_t *xcc_seen = nullptr;
   int32_t row_blocks = 0, row_stride = 0, row_sets = 0;  // blocks, blocks per band, real ones per band
+  // queue sweep: the done flag of tile t of chain c = o * ngroups + group is
+  // qflags[qflag_off + c * ntiles_all + t] (qflags: the batch's flag array)
+  int64_t qflag_off = 0;
+  int32_t ntiles_all = 0;
 };
 
 // Square sweep tile edges in (x1, x2) compiled into the kernel; the host
@@ -153,7 +158,23 @@ struct Batch {
   const int *h_strip_off = nullptr;
   int strip_stride = 8, strip_shape = 0;
   int use_strips = 0;  // the sweep is the strip pipeline (its block offsets locate the XCD records)
+  // queue sweep: per-XCD sub-queues of packed tile items, sub-queue
+  // x * kQueueSub + i at qitems[q_off[.] .. q_off[. + 1]); the batch's
+  // counters [kQueueCounters] and done flags (scratch); q_total items in all
+  int use_queue = 0, q_total = 0;
+  const uint64_t *d_qitems = nullptr;
+  const int32_t *d_q_off = nullptr;
+  int32_t *d_qctr = nullptr;
+  int32_t *d_qflags = nullptr;
 };
+
+// Blocks of a queue-sweep launch: more than the 256 CUs of the GPU can hold at
+// once; blocks that start late find the queues empty and end. Sub-queues per
+// XCD (each with its own counter: one counter per XCD serialised the claims);
+// counters: taken per sub-queue, then handled per XCD.
+constexpr int kQueueBlocks = 4096;
+constexpr int kQueueSub = 8;
+constexpr int kQueueCounters = 8 * kQueueSub + 8;
 
 // Shapes of the strip pipeline: rows per strip TH x velocity groups per
 // wavefront G, with the strips per block NW that each is compiled with.
@@ -172,6 +193,8 @@ struct Scratch {
   double *part = nullptr;
   int32_t *progress = nullptr;
   uint8_t *xcc = nullptr;
+  int32_t *qctr = nullptr;    // queue sweep: counters [kQueueCounters]
+  int32_t *qflags = nullptr;  // queue sweep: done flags
 };
 
 // Kernel launchers (dvm_sweep_diag.hip, dvm_sweep_rows.hip, dvm_iter.hip).
@@ -186,12 +209,18 @@ hipError_t launch_sweep_rows(const Batch<T> &B, bool local, hipStream_t st, cons
 // The strip pipeline (2D, one launch for all problems of the batch).
 template <typename T>
 hipError_t launch_sweep_strips(const Batch<T> &B, hipStream_t st, const Scratch &scr = Scratch{});
+// The tile sweep of every problem of the batch as one launch fed by per-XCD
+// queues (after a fill kernel that clears the queue counters).
+template <typename T>
+hipError_t launch_sweep_queue(const Batch<T> &B, hipStream_t st, const Scratch &scr = Scratch{});
 // The pipeline's progress counters of a batch-wide scratch region (blocks
 // off[p] .. off[p + 1] of problem p), set below every stamp the next sweep of
 // each problem publishes: seq * ntile0 for the row pipeline, seq * n0 for the
 // strips; a fill kernel (no memset node when the caller captures a graph).
 template <typename T>
 hipError_t launch_progress_reset(const Batch<T> &B, const int *d_off, bool strips, int32_t *progress, hipStream_t st);
+// p[0 .. n) = v (a fill kernel).
+hipError_t launch_fill_i32(int32_t *p, int64_t n, int32_t v, hipStream_t st);
 // out[b] = the XCD that block b of a `blocks`-block grid runs on.
 hipError_t launch_xcd_probe(uint32_t *out, int blocks, int threads, hipStream_t st);
 template <typename T>

@@ -252,7 +252,7 @@ __device__ void resolve(Geo<T> &g, int par, int run) {
 template <typename T>
 __global__ void __launch_bounds__(256)
     reduce_kernel(Geo<T> *__restrict__ G, const int *__restrict__ blk_off, const int *__restrict__ row_off,
-                  double *part_scr, uint8_t *xcc_scr) {
+                  double *part_scr, uint8_t *xcc_scr, const int32_t *qctr, int q_total) {
   Geo<T> &g = G[blockIdx.x];
   Ctl *ctl = g.ctl;
   if (ctl->stop) return;
@@ -263,7 +263,16 @@ __global__ void __launch_bounds__(256)
   __shared__ double sa[256], sb[256], sc[256];
   __shared__ int misplaced;
   const int t = threadIdx.x;
-  if (t == 0) misplaced = 0;
+  if (t == 0) {
+    misplaced = 0;
+    // queue sweep: every item must have been handled (a queue whose XCD got
+    // no block would leave its chains unswept)
+    if (qctr) {
+      int h = 0;
+      for (int x = 0; x < 8; ++x) h += qctr[8 * kQueueSub + x];
+      if (h != q_total) misplaced = 1;
+    }
+  }
   __syncthreads();
   // XCD-local row pipeline: all blocks of a velocity chain must have run on one
   // XCD (their hand-over relies on a shared L2); otherwise the iterate is void
@@ -535,8 +544,9 @@ hipError_t launch_moments(const Batch<T> &B, hipStream_t st, const Scratch &scr)
 
 template <typename T>
 hipError_t launch_reduce(const Batch<T> &B, hipStream_t st, const Scratch &scr) {
+  const int32_t *qctr = B.use_queue ? (scr.qctr ? scr.qctr : B.d_qctr) : nullptr;
   hipLaunchKernelGGL((reduce_kernel<T>), dim3(B.nprob), dim3(256), 0, st, const_cast<Geo<T> *>(B.d_geo), B.d_blk_off,
-                     B.use_strips ? B.d_strip_off : B.d_row_off, scr.part, scr.xcc);
+                     B.use_strips ? B.d_strip_off : B.d_row_off, scr.part, scr.xcc, qctr, B.q_total);
   return hipGetLastError();
 }
 

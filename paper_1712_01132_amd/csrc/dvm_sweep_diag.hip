@@ -45,27 +45,37 @@ __device__ __forceinline__ T wrap_jump(const Dom<T> &g, int x) {
   return (x < 0 ? T(1) : (x >= g.n[0] ? T(-1) : T(0))) * g.jump;
 }
 
+// LDS of one tile wavefront: the reciprocal denominators of its 64
+// velocities and the records of up to PZ planes (128 voxels in 3D).
+template <typename T, int DIM, int TT, int EXT>
+struct TileLds {
+  static constexpr int NC = TT * TT;
+  static constexpr int RW = 5 + 3 * DIM + ((EXT & 2) ? DIM : 0);  // src (4), nu tau, per axis (c1, c2, w), [q]
+  static constexpr int PZ = DIM == 3 ? 128 / NC : 1;
+  T rd[8 * kWave];
+  T rec[PZ * NC * RW];
+  uint32_t rcode[PZ * NC];
+};
+
+// The sweep of one tile (physical tile coordinates tpos) for the 64 velocities
+// of group grp in sign octant o; every value it reads outside the tile is final.
 template <typename T, int DIM, int TT, bool Y2WALL, int EXT>
-__global__ void __launch_bounds__(kWave)
-    sweep_kernel(const Geo<T> *__restrict__ G, const int *__restrict__ item_off, int nprob, int diag) {
+__device__ __forceinline__ void sweep_tile(const Geo<T> &G_, int o, int grp, const int (&tpos)[3],
+                                           TileLds<T, DIM, TT, EXT> &L) {
   constexpr bool PSI = (EXT & 1) != 0, SH = (EXT & 2) != 0, MW = (EXT & 4) != 0;
   static_assert(!(MW && Y2WALL), "Maxwell walls need stencil rule 1");
   constexpr int NC = TT * TT;
-  constexpr int RW = 5 + 3 * DIM + (SH ? DIM : 0);  // record: src (4), nu tau, per axis (c1, c2, w), [q]
+  constexpr int RW = TileLds<T, DIM, TT, EXT>::RW;
   // 3D: the records of PZ planes (128 voxels) are staged at once, before any
   // store of them; KV voxels per lane
-  constexpr int PZ = DIM == 3 ? 128 / NC : 1, KV = (PZ * NC + kWave - 1) / kWave;
-  __shared__ T rd_lds[8 * kWave];
-  __shared__ T rec[PZ * NC * RW];
-  __shared__ uint32_t rcode[PZ * NC];
-  const int p = nprob > 1 ? owner_of(item_off, nprob, blockIdx.x) : 0;
-  const Geo<T> &G_ = G[p];
-  if (!G_.run) return;  // converged problems retire
+  constexpr int PZ = TileLds<T, DIM, TT, EXT>::PZ, KV = (PZ * NC + kWave - 1) / kWave;
+  T *const rd_lds = L.rd;
+  T *const rec = L.rec;
+  uint32_t *const rcode = L.rcode;
   // every per-problem value is read once here; the loops below see registers
   const Dom<T> dm = dom_of(G_);
-  const int ngroups = G_.ngroups, Ko = G_.Ko, Ko_pad = G_.Ko_pad, tau_fb = G_.tau_fb;
+  const int Ko = G_.Ko, Ko_pad = G_.Ko_pad, tau_fb = G_.tau_fb;
   const int tile[3] = {G_.tile[0], G_.tile[1], G_.tile[2]};
-  const int ntile[3] = {G_.ntile[0], G_.ntile[1], G_.ntile[2]};
   const gptr<const T> absv = as_global(G_.absv), avv = as_global(G_.av), rden = as_global(G_.rden),
                       vsq = as_global(G_.vsqm);
   const gptr<T> hc = as_global(G_.hcur);
@@ -77,36 +87,12 @@ __global__ void __launch_bounds__(kWave)
   const gptr<const T> wall = as_global(G_.wallcur);
   const gptr<const uint32_t> flags = as_global(G_.flags);
   const int n0 = dm.n[0], n1 = dm.n[1];
-  // tiles of diagonal `diag`: in 2D (a, b) with a + b = diag, computed, the
-  // same for every octant; in 3D per octant from the table of tiles holding
-  // fluid (items: octant, then group, then tile)
-  int d0 = 0, ntd, t, grp, o;
-  int item = nprob > 1 ? blockIdx.x - item_off[p] : blockIdx.x;
-  if (DIM == 2) {
-    const int amin = max(0, diag - (ntile[1] - 1)), amax = min(diag, ntile[0] - 1);
-    d0 = amin;
-    ntd = amax - amin + 1;
-    t = item % ntd;
-    item /= ntd;
-    grp = item % ngroups;
-    o = item / ngroups;
-  } else {
-    const gptr<const int32_t> diag_off = as_global(G_.diag_off) + diag * 8;
-    const int base = diag_off[0];
-    o = 0;
-#pragma unroll
-    for (int k = 1; k < 8; ++k)
-      if (item >= (diag_off[k] - base) * ngroups) o = k;
-    d0 = diag_off[o];
-    ntd = diag_off[o + 1] - d0;
-    item -= (d0 - base) * ngroups;
-    t = item % ntd;
-    grp = item / ntd;
-  }
   const int lane = threadIdx.x;
   const int q = grp * kWave + lane;
   const bool active = q < Ko;
-  const int qq = active ? q : 0;
+  // a lane past the octant (last group only) reads the octant's last slot,
+  // which its own wavefront owns: it touches no other wavefront's lines
+  const int qq = active ? q : Ko - 1;
   const uint32_t colb = (uint32_t)(G_.Kpad * (int64_t)sizeof(T));  // bytes per voxel
   constexpr uint32_t kDrop = 0x40000000u;  // past any row's range; two of them do not wrap
   int s[3], sidx[3], pin[3];
@@ -143,18 +129,6 @@ __global__ void __launch_bounds__(kWave)
   for (int j = 0; j < 3; ++j) kmir[j] = (o ^ (1 << j)) * Ko_pad + qq;
 
   int lo[3] = {0, 0, 0}, cnt[3] = {1, 1, 1};
-  int tpos[3] = {0, 0, 0};  // physical tile coordinates
-  if (DIM == 2) {
-    tpos[0] = d0 + t;
-    tpos[1] = diag - tpos[0];
-#pragma unroll
-    for (int j = 0; j < 2; ++j)
-      if (s[j] < 0) tpos[j] = ntile[j] - 1 - tpos[j];
-  } else {
-    const gptr<const int32_t> diag_tiles = as_global(G_.diag_tiles);
-#pragma unroll
-    for (int j = 0; j < 3; ++j) tpos[j] = diag_tiles[(d0 + t) * 4 + j];
-  }
 #pragma unroll
   for (int j = 0; j < DIM; ++j) {
     lo[j] = tpos[j] * tile[j];
@@ -378,7 +352,212 @@ __global__ void __launch_bounds__(kWave)
   for (int c3 = 1; c3 < cnt[2]; ++c3) plane(c3);
 }
 
+// Step (i) for one diagonal of tiles: block = (octant, group, tile of the
+// diagonal). In 2D the tiles (a, b) with a + b = diag are computed, the same
+// for every octant; in 3D they come per octant from the table of tiles
+// holding fluid.
+template <typename T, int DIM, int TT, bool Y2WALL, int EXT>
+__global__ void __launch_bounds__(kWave)
+    sweep_kernel(const Geo<T> *__restrict__ G, const int *__restrict__ item_off, int nprob, int diag) {
+  __shared__ TileLds<T, DIM, TT, EXT> L;
+  const int p = nprob > 1 ? owner_of(item_off, nprob, blockIdx.x) : 0;
+  const Geo<T> &G_ = G[p];
+  if (!G_.run) return;  // converged problems retire
+  const int ngroups = G_.ngroups;
+  int item = nprob > 1 ? blockIdx.x - item_off[p] : blockIdx.x;
+  int t, grp, o, tpos[3] = {0, 0, 0};
+  if (DIM == 2) {
+    const int amin = max(0, diag - (G_.ntile[1] - 1)), amax = min(diag, G_.ntile[0] - 1);
+    const int ntd = amax - amin + 1;
+    t = item % ntd;
+    item /= ntd;
+    grp = item % ngroups;
+    o = item / ngroups;
+    tpos[0] = amin + t;
+    tpos[1] = diag - tpos[0];
+#pragma unroll
+    for (int j = 0; j < 2; ++j)
+      if ((o >> j) & 1) tpos[j] = G_.ntile[j] - 1 - tpos[j];
+  } else {
+    const gptr<const int32_t> diag_off = as_global(G_.diag_off) + diag * 8;
+    const int base = diag_off[0];
+    o = 0;
+#pragma unroll
+    for (int k = 1; k < 8; ++k)
+      if (item >= (diag_off[k] - base) * ngroups) o = k;
+    const int d0 = diag_off[o], ntd = diag_off[o + 1] - d0;
+    item -= (d0 - base) * ngroups;
+    t = item % ntd;
+    grp = item / ntd;
+    const gptr<const int32_t> diag_tiles = as_global(G_.diag_tiles);
+#pragma unroll
+    for (int j = 0; j < 3; ++j) tpos[j] = diag_tiles[(d0 + t) * 4 + j];
+  }
+  sweep_tile<T, DIM, TT, Y2WALL, EXT>(G_, o, grp, tpos, L);
+}
+
+// Step (i) as one launch: per XCD, kQueueSub queues of packed tile items (the
+// velocity chains, i.e. problem x octant x group, are dealt to the XCDs and
+// their sub-queues, each chain to one), ordered by tile diagonal. Every block
+// takes items from the queues of the XCD it runs on (one claim ahead: the
+// next item's counter update is in flight during a tile, and a claim only
+// ever waits on items claimed before it); before a tile it waits for the done flags of
+// its upstream tiles along each axis (same chain, so the same queue and XCD),
+// and after it drains its stores into the L2 and stamps the tile's flag with
+// the iteration's seq (flags are never reset). A wait only ever concerns an
+// item taken earlier by a running wavefront, so the queue cannot deadlock.
+// Producer and consumer share the XCD's L2: relaxed agent-scope flag stores
+// and polls, no cache write-back or invalidation; the consumer's L1 holds no
+// line of the tile before the flag (a chain's lines are read only by its own
+// downstream tiles, and lanes past the octant read their own group's slot).
+// Waits are bounded (Geo::wait_ticks) and flag ctl->fault; the blocks count
+// the items they handled, and the reduction discards an iterate whose count
+// falls short (a queue without blocks on its XCD).
+// Item: bits 0-23 tile index (x1 fastest), 24-26 octant, 27-31 group,
+// 32-47 problem, 48-53 waits: bit 2 j + k - 1 = wait for the k-th tile
+// upstream along axis j (k = 2 where the first is one voxel thick).
+template <typename T, int DIM, int TT, bool Y2WALL, int EXT>
+__global__ void __launch_bounds__(kWave) __attribute__((amdgpu_waves_per_eu(sizeof(T) == 4 ? 3 : 1)))
+    sweep_queue_kernel(const Geo<T> *__restrict__ G, const uint64_t *__restrict__ items,
+                       const int32_t *__restrict__ q_off, int32_t *__restrict__ qctr, int32_t *__restrict__ qflags) {
+  __shared__ TileLds<T, DIM, TT, EXT> L;
+  uint32_t xcc;
+  asm volatile("s_getreg_b32 %0, hwreg(HW_REG_XCC_ID)" : "=s"(xcc));
+  xcc &= 7u;
+  const int lane = threadIdx.x;
+  int handled = 0;
+  // the XCD's sub-queues, starting with one picked by the block index; a
+  // block that finds one empty moves on to the next
+  const int sub0 = (int)((blockIdx.x >> 3) % kQueueSub);
+  for (int si = 0; si < kQueueSub; ++si) {
+    const int qi = (int)xcc * kQueueSub + (sub0 + si) % kQueueSub;
+    const int qb = q_off[qi], qn = q_off[qi + 1] - qb;
+    int32_t *const ctr = &qctr[qi];
+    int k = 0;
+    if (lane == 0) k = __hip_atomic_fetch_add(ctr, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    k = __builtin_amdgcn_readfirstlane(k);
+    while (k < qn) {
+      // the next item is claimed now, its claim in flight during this tile
+      int kn = 0;
+      if (lane == 0) kn = __hip_atomic_fetch_add(ctr, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      ++handled;
+      const uint64_t it = items[qb + k];
+      const int tile = (int)(it & 0xFFFFFFu), o = (int)((it >> 24) & 7u), grp = (int)((it >> 27) & 31u);
+      const int p = (int)((it >> 32) & 0xFFFFu), wm = (int)((it >> 48) & 63u);
+      const Geo<T> &G_ = G[p];
+      if (G_.run) {
+        const int32_t stamp = G_.seq;
+        const int nt0 = G_.ntile[0], nt1 = G_.ntile[1];
+        int32_t *const fl = qflags + G_.qflag_off + (int64_t)(o * G_.ngroups + grp) * G_.ntiles_all;
+        const int tpos[3] = {tile % nt0, (tile / nt0) % nt1, tile / (nt0 * nt1)};
+        if (wm) {
+          // lane b < 2 DIM polls the flag of wait b, all at once
+          const int j = lane >> 1, kk = (lane & 1) + 1;
+          const bool mine = lane < 2 * DIM && ((wm >> lane) & 1);
+          const int stride = j == 0 ? 1 : (j == 1 ? nt0 : nt0 * nt1);
+          const int up = mine ? tile - (((o >> j) & 1) ? -kk : kk) * stride : tile;
+          int32_t *const fault = &G_.ctl->fault;
+          const int64_t wait_ticks = G_.wait_ticks;
+          int n = 0;
+          int64_t t0 = 0;
+          for (;;) {
+            const bool ok = !mine || __hip_atomic_load(&fl[up], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == stamp;
+            if (__all(ok)) break;
+            if ((++n & 63) == 0) {
+              const int64_t t = wall_clock64();
+              if (__hip_atomic_load(fault, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0) break;
+              if (n == 64) {
+                t0 = t;
+              } else if (t - t0 > wait_ticks) {
+                if (lane == 0) __hip_atomic_store(fault, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                break;
+              }
+            }
+            __builtin_amdgcn_s_sleep(1);
+          }
+        }
+        __atomic_signal_fence(__ATOMIC_SEQ_CST);  // no load of the tile is moved above the polls
+        sweep_tile<T, DIM, TT, Y2WALL, EXT>(G_, o, grp, tpos, L);
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+        __builtin_amdgcn_s_waitcnt(0);  // every store of the tile has reached the L2
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+        if (lane == 0) __hip_atomic_store(&fl[tile], stamp, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();  // the next tile's records overwrite this tile's
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+      }
+      k = __builtin_amdgcn_readfirstlane(kn);
+    }
+  }
+  if (lane == 0)
+    __hip_atomic_fetch_add(&qctr[8 * kQueueSub + xcc], handled, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// The queue counters (taken per sub-queue, handled per XCD) before a queue
+// sweep: a fill kernel, so that a captured graph holds no memset node.
+__global__ void queue_reset_kernel(int32_t *qctr) {
+  if (threadIdx.x < kQueueCounters) qctr[threadIdx.x] = 0;
+}
+
+__global__ void fill_i32_kernel(int32_t *p, int64_t n, int32_t v) {
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) p[i] = v;
+}
+
 }  // namespace
+
+template <typename T, bool Y2WALL>
+void launch_queue_rule(const Batch<T> &B, hipStream_t st, int32_t *qctr, int32_t *qflags) {
+  hipLaunchKernelGGL(queue_reset_kernel, dim3(1), dim3(128), 0, st, qctr);
+  const dim3 grid(kQueueBlocks);
+#define PDVM_QUEUE_E(D, X, E)                                                                             \
+  hipLaunchKernelGGL((sweep_queue_kernel<T, D, X, Y2WALL, E>), grid, dim3(kWave), 0, st, B.d_geo, B.d_qitems, \
+                     B.d_q_off, qctr, qflags)
+#define PDVM_QUEUE_T(D, E)                          \
+  if (B.tile_edge <= 4) PDVM_QUEUE_E(D, 4, E);      \
+  else PDVM_QUEUE_E(D, 8, E)
+  if constexpr (!Y2WALL) {
+    if (B.maxwell) {
+      if (B.dim == 2) {
+        if (B.shakhov) { PDVM_QUEUE_T(2, 7); }
+        else if (B.psi) { PDVM_QUEUE_T(2, 5); }
+        else { PDVM_QUEUE_T(2, 4); }
+      } else {
+        if (B.shakhov) { PDVM_QUEUE_T(3, 6); }
+        else { PDVM_QUEUE_T(3, 4); }
+      }
+      return;
+    }
+  }
+  if (B.dim == 2) {
+    if (B.shakhov) { PDVM_QUEUE_T(2, 3); }
+    else if (B.psi) { PDVM_QUEUE_T(2, 1); }
+    else { PDVM_QUEUE_T(2, 0); }
+  } else {
+    if (B.shakhov) { PDVM_QUEUE_T(3, 2); }
+    else { PDVM_QUEUE_T(3, 0); }
+  }
+#undef PDVM_QUEUE_T
+#undef PDVM_QUEUE_E
+}
+
+template <typename T>
+hipError_t launch_sweep_queue(const Batch<T> &B, hipStream_t st, const Scratch &scr) {
+  int32_t *qctr = scr.qctr ? scr.qctr : B.d_qctr;
+  int32_t *qflags = scr.qflags ? scr.qflags : B.d_qflags;
+  if (B.y2wall) launch_queue_rule<T, true>(B, st, qctr, qflags);
+  else launch_queue_rule<T, false>(B, st, qctr, qflags);
+  return hipGetLastError();
+}
+
+hipError_t launch_fill_i32(int32_t *p, int64_t n, int32_t v, hipStream_t st) {
+  if (n <= 0) return hipSuccess;
+  const int64_t blocks = std::min<int64_t>((n + 255) / 256, 4096);
+  hipLaunchKernelGGL(fill_i32_kernel, dim3((unsigned)blocks), dim3(256), 0, st, p, n, v);
+  return hipGetLastError();
+}
+
+template hipError_t launch_sweep_queue<double>(const Batch<double> &, hipStream_t, const Scratch &);
+template hipError_t launch_sweep_queue<float>(const Batch<float> &, hipStream_t, const Scratch &);
 
 template <typename T, bool Y2WALL>
 void launch_sweep_rule(const Batch<T> &B, int diag, hipStream_t st) {

@@ -117,3 +117,24 @@ def test_batch_row_pipeline_equals_tile_diagonals_bitwise(nv, precision):
         b.close()
     for (ra, ua), (rb, ub) in zip(res[0], res[1]):
         assert np.array_equal(ra, rb) and np.array_equal(ua, ub)
+
+
+def test_autotuner_tunes_schedule_and_tile_for_a_batch(tmp_path, monkeypatch):
+    """For a batch the tuner times both one-launch queues and per-diagonal
+    launches for every tile; its choice runs the same iterates as any other."""
+    from paper_1712_01132_amd import autotune
+    monkeypatch.setenv("PDVM_AUTOTUNE_CACHE", str(tmp_path / "tune.json"))
+    probs = masks()
+    (sched, tile), ms = autotune.best_config(probs, [8, 8], "fp32", iters=2)
+    assert sched in autotune.SCHEDULES_MULTI and tile in autotune.CANDIDATES_2D
+    assert len(ms) == len(autotune.SCHEDULES_MULTI) * len(autotune.CANDIDATES_2D)
+    assert autotune.best_config(probs, [8, 8], "fp32", iters=2)[0] == (sched, tile)  # cached
+    out = []
+    for sc, t in ((sched, tile), ("diagonals", (4, 4))):
+        b = poredvm.Batch(probs, [8, 8], precision="fp32", tile=list(t), schedule=sc)
+        b.iterate(6)
+        out.append([b.moments(i) for i in range(len(probs))])
+        b.close()
+    for a, b in zip(*out):
+        for x, y in zip(a, b):
+            assert np.array_equal(x, y)

@@ -33,6 +33,7 @@ def _same(a, b):
     ("strips", "fp32", [8, 8]),      # strip pipeline, likewise
     ("rows-agent", "fp32", [24, 24]),
     ("diagonals", "fp64", [8, 8]),
+    ("queue", "fp32", [24, 24]),     # per-XCD tile queues: counters and done flags in the scratch
 ])
 def test_noalloc_equals_iterate_twice_second_smaller(schedule, precision, nv):
     cases = [(random_mask((96, 88), 0.3, 41), 13), (random_mask((36, 30), 0.3, 42), 6)]
@@ -41,8 +42,8 @@ def test_noalloc_equals_iterate_twice_second_smaller(schedule, precision, nv):
         b = poredvm.Solver(m, nv, 0.6, precision=precision, schedule=schedule)
         if schedule == "auto":
             assert b.schedule == "rows-xcd"
-        if schedule == "strips":
-            assert b.schedule == "strips"
+        if schedule in ("strips", "queue"):
+            assert b.schedule == schedule
         ra = a.iterate(iters)
         rb = b.iterate_noalloc(iters)
         assert rb["iters"] == ra["iters"] == iters and rb["total_iters"] == iters
@@ -68,10 +69,17 @@ def test_noalloc_stops_on_tolerance_like_iterate():
     _same(a, b)
 
 
-def test_noalloc_3d():
-    m = random_mask((10, 12, 14), 0.25, 44)
-    a = poredvm.Solver(m, [4, 4, 4], 0.7, precision="fp32")
-    b = poredvm.Solver(m, [4, 4, 4], 0.7, precision="fp32")
-    a.iterate(7)
-    b.iterate_noalloc(7)
-    _same(a, b)
+@pytest.mark.parametrize("schedule", ["auto", "queue"])
+def test_noalloc_3d(schedule):
+    """3D, per-diagonal launches (automatic) and the queue sweep: two solves
+    in a row, the second smaller, finding the first one's scratch."""
+    for shape, iters in (((20, 22, 24), 7), ((10, 12, 14), 5)):
+        m = random_mask(shape, 0.25, 44)
+        a = poredvm.Solver(m, [4, 4, 4], 0.7, precision="fp32", schedule=schedule)
+        b = poredvm.Solver(m, [4, 4, 4], 0.7, precision="fp32", schedule=schedule)
+        assert b.schedule == ("diagonals" if schedule == "auto" else "queue")
+        a.iterate(iters)
+        b.iterate_noalloc(iters)
+        _same(a, b)
+        a.close()
+        b.close()
