@@ -110,6 +110,60 @@ def roofline(tm, elem, traffic_key=None, schedule="diagonals"):
                                "traffic": mom_traffic}}
 
 
+# Workloads of --only: (what, precision, default tile)
+ONLY = {"rock2d-fp64": ("rock2d", "fp64", (4, 4)), "rock2d-fp32": ("rock2d", "fp32", (4, 4)),
+        "pack3d-fp32": ("pack3d", "fp32", (4, 4, 4)), "batch64-fp32": ("batch64", "fp32", (8, 8)),
+        "unet-train": ("unet", "bf16", None)}
+
+
+def only_workload(args):
+    """One workload alone, for rocprofv3 runs: `--warmup` untimed and
+    `--steps` timed iterations (training steps for the network)."""
+    import torch
+    from paper_1712_01132_amd import geometry, poredvm
+    what, prec, tile = ONLY[args.only]
+    tile = tuple(args.tile) if args.tile else tile
+    torch.cuda.set_device(0)
+    if what == "unet":
+        import numpy as np
+        from paper_1712_01132_amd import warmstart
+        B = 8
+        net = warmstart.Net(256, 256, batch_max=B, dataset_max=B)
+        net.set_params(warmstart.init_params(0))
+        for i in range(B):
+            m, kn = geometry.workload_warmstart(20000 + i)
+            net.set_sample(i, m, kn, np.zeros(m.shape), np.zeros((2,) + m.shape))
+        net.time(list(range(B)), reps=max(1, args.warmup))
+        t = net.time(list(range(B)), reps=max(1, args.steps))
+        net.close()
+        print(json.dumps({"workload": args.only, "timing": t}), flush=True)
+        return
+    if what == "batch64":
+        probs = geometry.workload_batch(64)
+        s = poredvm.Batch(probs, [24, 24], precision=prec, tile=list(tile), schedule=args.schedule)
+        fluid, K = sum(int((m == 0).sum()) for m, _ in probs), 576
+    else:
+        m = geometry.workload_rock2d(seed=1) if what == "rock2d" else geometry.workload_pack3d(seed=7)
+        nv, kn = ([32, 32], args.kn) if what == "rock2d" else ([16, 16, 16], 0.5)
+        s = poredvm.Solver(m, nv, kn, precision=prec, tile=list(tile), schedule=args.schedule)
+        fluid, K = int((m == 0).sum()), 1024 if what == "rock2d" else 4096
+    if what == "batch64":
+        s.iterate(args.warmup)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        s.iterate(args.steps)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        ups = fluid * K * args.steps / dt
+    else:
+        ups, dt = timed_updates(s, fluid, K, args.steps, args.warmup)
+    sched = s.schedule
+    s.close()
+    print(json.dumps({"workload": args.only, "schedule": sched, "tile": list(tile), "steps": args.steps,
+                      "ms_per_step": 1e3 * dt / args.steps, "updates_per_s": ups,
+                      "kernel_source": kernel_source_hash()}), flush=True)
+
+
 def copy_calibration(mib):
     """A plain device copy of known size: each launch reads and writes
     mib MiB, so FETCH_SIZE / WRITE_SIZE of this kernel give the counters'
@@ -247,6 +301,52 @@ def unet_timing():
     return res
 
 
+def warmstart_heldout(n=16, tol=1e-6, max_iters=30000):
+    """Held-out geometries of the warm-start set (seeds 20000.., never
+    trained on): the unchanged FP32 iteration to r <= tol from rest, from the
+    pressure ramp and from the network's prediction (unjudged), each start as
+    one batch of the n problems. Iterations per problem and the batch's wall
+    time (it ends with its slowest problem)."""
+    import numpy as np
+    import torch
+    from paper_1712_01132_amd import geometry, poredvm, warmstart
+    probs = [geometry.workload_warmstart(20000 + i) for i in range(n)]
+    try:
+        params, _ = warmstart.load_weights()
+    except (OSError, KeyError) as e:
+        return {"skipped": "no trained weights (%s)" % e}
+    net = warmstart.Net(256, 256, batch_max=1, dataset_max=0)
+    net.set_params(params)
+    t0 = time.perf_counter()
+    pred = [net.predict(m, kn) for m, kn in probs]
+    t_pred = time.perf_counter() - t0
+    net.close()
+    starts = {"cold": None, "ramp": [warmstart.ramp_start(m) for m, _ in probs], "warm": pred}
+    out = {"problems": n, "seeds": [20000, 20000 + n - 1], "tol": tol, "precision": "fp32",
+           "prediction_seconds": t_pred}
+    for name in ("cold", "ramp", "warm"):
+        b = poredvm.Batch(probs, [24, 24], precision="fp32", tile=[8, 8])
+        if starts[name] is not None:
+            for i, (rho, u) in enumerate(starts[name]):
+                b.set_initial(i, rho, u)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        st = b.iterate(max_iters, tol)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        b.close()
+        it = [int(x["total_iters"]) for x in st]
+        out[name] = {"iterations": it, "sum": int(np.sum(it)), "median": float(np.median(it)),
+                     "max": int(np.max(it)), "converged": int(sum(x["converged"] for x in st)), "seconds": dt}
+        log("held-out %s: %s" % (name, json.dumps(out[name])))
+    w, r, c = (np.array(out[k]["iterations"], dtype=float) for k in ("warm", "ramp", "cold"))
+    out["warm_vs_ramp"] = {"sum_ratio": float(w.sum() / r.sum()), "median_ratio": float(np.median(w / r)),
+                           "better": int((w < r).sum())}
+    out["warm_vs_cold"] = {"sum_ratio": float(w.sum() / c.sum()), "median_ratio": float(np.median(w / c)),
+                           "better": int((w < c).sum())}
+    return out
+
+
 def model_timing(mask, nv, kn, fluid, K, steps=40, warmup=5):
     """The same 512^2 rock in FP64 with the other models: updates/s count the
     distribution's velocities only (psi, where present, is extra work)."""
@@ -368,6 +468,10 @@ def main():
                     help="sweep tile (default: chosen by the autotuner before the timed region)")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only copy MIB MiB device-to-device 3 times (scale for HBM byte counters)")
+    ap.add_argument("--only", choices=sorted(ONLY), default=None,
+                    help="only run --steps iterations (after --warmup) of one workload with a given schedule "
+                         "and tile, for profilers; prints one JSON line with its timing")
+    ap.add_argument("--schedule", default="auto", help="sweep schedule for --only")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU: the library has no multi-GPU path "
@@ -375,6 +479,9 @@ def main():
         sys.exit(2)
     if args.copy_calibration:
         copy_calibration(args.copy_calibration)
+        return
+    if args.only:
+        only_workload(args)
         return
 
     import torch
@@ -470,6 +577,7 @@ def main():
                                  "roofline": roofline(tb, 4, (kernel_source_hash(), schedb, tuple(tileb)), schedb)}
         log("batch64 FP32: %.3e updates/s" % (fb * 576 * 30 / db))
         extra["warmstart_unet"] = unet_timing()
+        extra["warmstart_heldout"] = warmstart_heldout()
         extra["rock2d_models_fp64"] = model_timing(mask, nv, args.kn, fluid, K)
         out["extra"] = extra
     if not args.no_cpu_baseline:

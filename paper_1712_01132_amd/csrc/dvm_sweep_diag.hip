@@ -59,9 +59,12 @@ struct TileLds {
 
 // The sweep of one tile (physical tile coordinates tpos) for the 64 velocities
 // of group grp in sign octant o; every value it reads outside the tile is final.
-template <typename T, int DIM, int TT, bool Y2WALL, int EXT>
+// `before` runs once the tile's first records are being loaded and before any
+// value outside the tile is read (the queue sweep waits for its upstream tiles
+// there).
+template <typename T, int DIM, int TT, bool Y2WALL, int EXT, typename Before>
 __device__ __forceinline__ void sweep_tile(const Geo<T> &G_, int o, int grp, const int (&tpos)[3],
-                                           TileLds<T, DIM, TT, EXT> &L) {
+                                           TileLds<T, DIM, TT, EXT> &L, Before &&before) {
   constexpr bool PSI = (EXT & 1) != 0, SH = (EXT & 2) != 0, MW = (EXT & 4) != 0;
   static_assert(!(MW && Y2WALL), "Maxwell walls need stencil rule 1");
   constexpr int NC = TT * TT;
@@ -119,8 +122,9 @@ __device__ __forceinline__ void sweep_tile(const Geo<T> &G_, int o, int grp, con
     if (SH) cq[j] = (s[j] > 0 ? a : -a) * qs;
     if (MW) am[j] = aa[j] * spec;
   }
+  T rdv[1 << DIM];  // written to LDS after the first records' loads are issued
 #pragma unroll
-  for (int c = 0; c < (1 << DIM); ++c) rd_lds[c * kWave + lane] = rden[c * Ko_pad + qq];
+  for (int c = 0; c < (1 << DIM); ++c) rdv[c] = rden[c * Ko_pad + qq];
   const T vsqm = tau_fb ? vsq[qq] : T(0);
   const int kofs = o * Ko_pad + qq;
   const uint32_t kst = active ? (uint32_t)kofs * (uint32_t)sizeof(T) : kDrop;  // the lane's byte offset in a voxel
@@ -163,48 +167,61 @@ __device__ __forceinline__ void sweep_tile(const Geo<T> &G_, int o, int grp, con
   // l, l + 64, ...). The voxel's sources and wall values are loaded together
   // with its flags (valid addresses whatever the flags say) and every record
   // value is selected, not branched on, so one round trip serves them all.
-  auto stage = [&](int c0, int np) __attribute__((always_inline)) {
+  // `before` runs between the loads and the LDS writes (the queue sweep polls
+  // its upstream tiles there, so the polls and these loads share a round trip)
+  auto stage = [&](int c0, int np, auto &&before) __attribute__((always_inline)) {
+    uint32_t f[KV];
+    T sv[KV][5], wv[KV][DIM], qv[KV][DIM];
+    int xy[KV][3];
+#pragma unroll
+    for (int kv = 0; kv < KV; ++kv) {
+      const int v = lane + kv * kWave;
+      const int pz = min(v / NC, np - 1), i = v % TT, r = (v / TT) % TT;
+      const int x = xs + min(i, cnt[0] - 1) * s[0], y = ys + min(r, cnt[1] - 1) * s[1];
+      const int z = zof(c0 + pz);
+      xy[kv][0] = x;
+      xy[kv][1] = y;
+      xy[kv][2] = z;
+      const int c = (y + n1 * z) * n0 + x;
+      f[kv] = flags[c];
+      const gptr<const T> sp = src + c * kSrcStride;
+      sv[kv][0] = sp[0];
+      sv[kv][1] = sp[1];
+      sv[kv][2] = sp[2];
+      sv[kv][3] = DIM == 3 ? sp[3] : T(0);
+      sv[kv][4] = tau_fb ? srct[c] : T(0);
+#pragma unroll
+      for (int j = 0; j < DIM; ++j) {
+        wv[kv][j] = wall[c * 6 + 2 * j + pin[j]];
+        qv[kv][j] = SH ? srcq[c * 4 + j] : T(0);
+      }
+    }
+    before();
 #pragma unroll
     for (int kv = 0; kv < KV; ++kv) {
       const int v = lane + kv * kWave;
       if (KV * kWave > PZ * NC && v >= PZ * NC) break;
       const int pz = v / NC, i = v % TT, r = (v / TT) % TT;
       const bool in = pz < np && i < cnt[0] && r < cnt[1];
-      const int x = xs + min(i, cnt[0] - 1) * s[0], y = ys + min(r, cnt[1] - 1) * s[1];
-      const int z = zof(c0 + min(pz, np - 1));
-      const int c = (y + n1 * z) * n0 + x;
-      const uint32_t f = flags[c];
-      const gptr<const T> sp = src + c * kSrcStride;
-      const T sv0 = sp[0], sv1 = sp[1], sv2 = sp[2], sv3 = DIM == 3 ? sp[3] : T(0);
-      const T svt = tau_fb ? srct[c] : T(0);
-      T wv[DIM], qv[DIM];
-#pragma unroll
-      for (int j = 0; j < DIM; ++j) {
-        wv[j] = wall[c * 6 + 2 * j + pin[j]];
-        qv[j] = SH ? srcq[c * 4 + j] : T(0);
-      }
-      const bool fl = in && !(f & F_SOLID);
+      const bool fl = in && !(f[kv] & F_SOLID);
       T *rp = rec + v * RW;
-      rp[0] = fl ? sv0 : T(0);  // a skipped voxel's record is 0: it computes 0
-      rp[1] = fl ? sv1 : T(0);
-      rp[2] = fl ? sv2 : T(0);
-      rp[3] = fl ? sv3 : T(0);
-      rp[4] = fl ? svt : T(0);
+#pragma unroll
+      for (int k = 0; k < 5; ++k) rp[k] = fl ? sv[kv][k] : T(0);  // a skipped voxel's record is 0: it computes 0
       if (SH) {
 #pragma unroll
-        for (int j = 0; j < DIM; ++j) rp[5 + 3 * DIM + j] = fl ? qv[j] : T(0);
+        for (int j = 0; j < DIM; ++j) rp[5 + 3 * DIM + j] = fl ? qv[kv][j] : T(0);
       }
       uint32_t code = 0;
 #pragma unroll
       for (int j = 0; j < DIM; ++j) {
-        const uint32_t fj = f >> fbit(j, sidx[j]);
+        const uint32_t fj = f[kv] >> fbit(j, sidx[j]);
         const bool first = fj & 1u, y1s = fj & 2u, y2s = fj & 4u;
         T c1 = first ? (y1s ? T(0) : T(1)) : T(2);
         T c2 = first ? T(0) : T(-0.5);
-        T w = (first && y1s) ? (MW ? alpha * wv[j] : wv[j]) : T(0);
+        T w = (first && y1s) ? (MW ? alpha * wv[kv][j] : wv[kv][j]) : T(0);
         if (Y2WALL && fl && !first && y2s) {
           c2 = T(0);
-          w = T(-0.5) * wall_at_y1(dm, wall, j, s[j], pin[j], x, y, z);
+          w = T(-0.5) * wall_at_y1(dm, wall, j, s[j], pin[j], xy[kv][0], xy[kv][1], xy[kv][2]);
         }
         rp[5 + 3 * j] = fl ? c1 : T(0);
         rp[6 + 3 * j] = fl ? c2 : T(0);
@@ -220,7 +237,9 @@ __device__ __forceinline__ void sweep_tile(const Geo<T> &G_, int o, int grp, con
   // the tile's first plane: records, halos and (4 x 4 tiles in 3D) the two
   // planes below, all issued before any wait
   T L1[TT], L2[TT], B1[TT], B2[TT];
-  stage(0, min(PZ, cnt[2]));
+  stage(0, min(PZ, cnt[2]), before);
+#pragma unroll
+  for (int c = 0; c < (1 << DIM); ++c) rd_lds[c * kWave + lane] = rdv[c];
   load_halo(zof(0), L1, L2, B1, B2);
   if (ZREG) {
     const int z = zof(0);
@@ -240,7 +259,7 @@ __device__ __forceinline__ void sweep_tile(const Geo<T> &G_, int o, int grp, con
     const int pz = c3 % PZ;
     if (c3 > 0 && pz == 0) {  // the next chunk of records (only LDS is written here)
       __syncthreads();
-      stage(c3, min(PZ, cnt[2] - c3));
+      stage(c3, min(PZ, cnt[2] - c3), [] {});
       __syncthreads();
     }
     // the next plane's halos (the last plane re-reads its own), issued before
@@ -393,7 +412,7 @@ __global__ void __launch_bounds__(kWave)
 #pragma unroll
     for (int j = 0; j < 3; ++j) tpos[j] = diag_tiles[(d0 + t) * 4 + j];
   }
-  sweep_tile<T, DIM, TT, Y2WALL, EXT>(G_, o, grp, tpos, L);
+  sweep_tile<T, DIM, TT, Y2WALL, EXT>(G_, o, grp, tpos, L, [] {});
 }
 
 // Step (i) as one launch: per XCD, kQueueSub queues of packed tile items (the
@@ -433,15 +452,21 @@ __global__ void __launch_bounds__(kWave) __attribute__((amdgpu_waves_per_eu(size
     const int qi = (int)xcc * kQueueSub + (sub0 + si) % kQueueSub;
     const int qb = q_off[qi], qn = q_off[qi + 1] - qb;
     int32_t *const ctr = &qctr[qi];
-    int k = 0;
-    if (lane == 0) k = __hip_atomic_fetch_add(ctr, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    k = __builtin_amdgcn_readfirstlane(k);
+    // claims run two ahead: the item word of the next claim is loaded, and the
+    // claim after it is in flight, while a tile runs
+    auto claim = [&]() __attribute__((always_inline)) {
+      int c = 0;
+      if (lane == 0) c = __hip_atomic_fetch_add(ctr, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      return c;
+    };
+    int k = __builtin_amdgcn_readfirstlane(claim());
+    int kn = claim();
+    uint64_t it = k < qn ? items[qb + k] : 0;
     while (k < qn) {
-      // the next item is claimed now, its claim in flight during this tile
-      int kn = 0;
-      if (lane == 0) kn = __hip_atomic_fetch_add(ctr, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      kn = __builtin_amdgcn_readfirstlane(kn);
+      const uint64_t itn = kn < qn ? items[qb + kn] : 0;
+      const int knn = claim();
       ++handled;
-      const uint64_t it = items[qb + k];
       const int tile = (int)(it & 0xFFFFFFu), o = (int)((it >> 24) & 7u), grp = (int)((it >> 27) & 31u);
       const int p = (int)((it >> 32) & 0xFFFFu), wm = (int)((it >> 48) & 63u);
       const Geo<T> &G_ = G[p];
@@ -450,8 +475,10 @@ __global__ void __launch_bounds__(kWave) __attribute__((amdgpu_waves_per_eu(size
         const int nt0 = G_.ntile[0], nt1 = G_.ntile[1];
         int32_t *const fl = qflags + G_.qflag_off + (int64_t)(o * G_.ngroups + grp) * G_.ntiles_all;
         const int tpos[3] = {tile % nt0, (tile / nt0) % nt1, tile / (nt0 * nt1)};
-        if (wm) {
-          // lane b < 2 DIM polls the flag of wait b, all at once
+        // the upstream tiles' flags, polled by lane b < 2 DIM for wait b, all at
+        // once, while the tile's first records are being loaded
+        auto wait_upstream = [&]() __attribute__((always_inline)) {
+          if (!wm) return;
           const int j = lane >> 1, kk = (lane & 1) + 1;
           const bool mine = lane < 2 * DIM && ((wm >> lane) & 1);
           const int stride = j == 0 ? 1 : (j == 1 ? nt0 : nt0 * nt1);
@@ -475,9 +502,9 @@ __global__ void __launch_bounds__(kWave) __attribute__((amdgpu_waves_per_eu(size
             }
             __builtin_amdgcn_s_sleep(1);
           }
-        }
-        __atomic_signal_fence(__ATOMIC_SEQ_CST);  // no load of the tile is moved above the polls
-        sweep_tile<T, DIM, TT, Y2WALL, EXT>(G_, o, grp, tpos, L);
+          __atomic_signal_fence(__ATOMIC_SEQ_CST);  // no load outside the tile is moved above the polls
+        };
+        sweep_tile<T, DIM, TT, Y2WALL, EXT>(G_, o, grp, tpos, L, wait_upstream);
         __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
         __builtin_amdgcn_s_waitcnt(0);  // every store of the tile has reached the L2
         __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
@@ -486,7 +513,9 @@ __global__ void __launch_bounds__(kWave) __attribute__((amdgpu_waves_per_eu(size
         __builtin_amdgcn_wave_barrier();  // the next tile's records overwrite this tile's
         __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
       }
-      k = __builtin_amdgcn_readfirstlane(kn);
+      k = kn;
+      kn = knn;
+      it = itn;
     }
   }
   if (lane == 0)
