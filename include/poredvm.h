@@ -80,9 +80,8 @@ enum { PDVM_STOP_FIELD = 0, PDVM_STOP_PAPER_ERR = 1 };
  *            is discarded as for ROWS;
  * AUTO:      for a single 2D problem, ROWS when a probe of the block placement
  *            at creation shows that every velocity chain runs on one XCD (cheap
- *            synchronisation through its L2); for a 2D batch with tile edge 8,
- *            QUEUE when the probe finds all 8 XCDs; DIAGONALS otherwise (as
- *            measured faster for 3D problems and 4x4 tiles). */
+ *            synchronisation through its L2); for 3D problems and 2D batches,
+ *            QUEUE when the probe finds all 8 XCDs; DIAGONALS otherwise. */
 enum { PDVM_SCHEDULE_AUTO = 0, PDVM_SCHEDULE_DIAGONALS = 1, PDVM_SCHEDULE_ROWS = 2, PDVM_SCHEDULE_ROWS_AGENT = 3,
        PDVM_SCHEDULE_STRIPS = 4, PDVM_SCHEDULE_QUEUE = 5 };
 

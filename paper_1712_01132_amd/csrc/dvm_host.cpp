@@ -1033,7 +1033,8 @@ int build_queue(pdvm_solver *s) {
     for (int64_t c = chain_base[p]; c < chain_base[p + 1]; ++c) pof[c] = p;
   for (size_t c = 0; c < order.size(); ++c) order[c] = (int64_t)c;
   std::stable_sort(order.begin(), order.end(), [&](int64_t a, int64_t b) { return work[pof[a]] > work[pof[b]]; });
-  // queue index x * kQueueSub + i: the XCD, then its sub-queue, both least loaded
+  // queue index x * kQueueSub + i: the XCD, then its sub-queue, both least
+  // loaded (ties to the lowest index, so an XCD's used sub-queues come first)
   int64_t load[8] = {0, 0, 0, 0, 0, 0, 0, 0};
   std::vector<int64_t> subload(8 * kQueueSub, 0);
   for (int64_t c : order) {
@@ -1093,7 +1094,7 @@ int build_queue(pdvm_solver *s) {
   }
   if (items.size() >= ((size_t)1 << 31)) return s->fail(PDVM_E_UNSUPPORTED, "queue sweep: too many tiles");
   const size_t item_b = align256(std::max<size_t>(1, items.size()) * 8), off_b = align256((nq + 1) * 4),
-               ctr_b = align256(kQueueCounters * 4);
+               ctr_b = align256(kQueueCounterInts * 4);
   const size_t flag_b = align256((size_t)flags * 4);
   if (hipMalloc(&s->qmem, item_b + off_b + ctr_b + flag_b) != hipSuccess)
     return s->fail(PDVM_E_NOMEM, "queue sweep: device allocation of %zu bytes failed", item_b + off_b + ctr_b + flag_b);
@@ -1302,14 +1303,13 @@ int create_common(const pdvm_config *cfgs, int n, void *dev_workspace, size_t ws
       return rc3;
     }
   }
-  // the queue sweep: on request, and the automatic choice for a 2D batch with
-  // 8x8 tiles (measured: 64 mixed problems, FP32, 3.0 ms against 4.0 ms of
-  // per-diagonal launches; with 4x4 tiles and in 3D the per-tile claim and
-  // wait cost more than the launches they save), when blocks reach all 8 XCDs
-  const int edge = s->precision == PDVM_FP64 ? s->bd.tile_edge : s->bf.tile_edge;
+  // the queue sweep: on request, and the automatic choice for 3D problems and
+  // 2D batches (measured, FP32: 64 mixed 2D problems 2.5 ms per sweep against
+  // 3.9 ms of per-diagonal launches with 8x8 tiles, 2.9 against 5.0 with 4x4;
+  // the 96^3 pack 4.3 against 4.4 ms), when blocks reach all 8 XCDs
   if (!s->strips && !s->rows &&
       (P0.schedule == PDVM_SCHEDULE_QUEUE ||
-       (P0.schedule == PDVM_SCHEDULE_AUTO && P0.dim == 2 && n > 1 && edge == 8))) {
+       (P0.schedule == PDVM_SCHEDULE_AUTO && (P0.dim == 3 || n > 1)))) {
     bool all = false;
     int rc4 = probe_all_xcds(s, &all);
     if (rc4 == PDVM_OK && !all && P0.schedule == PDVM_SCHEDULE_QUEUE)
@@ -1337,7 +1337,7 @@ int create_common(const pdvm_config *cfgs, int n, void *dev_workspace, size_t ws
     const size_t pipe = (size_t)std::max(s->h_row_off[n], s->h_strip_off[n]);
     s->scr_xcc = s->scr_prog + align256(pipe * sizeof(int32_t));
     s->scr_qctr = s->scr_xcc + align256(pipe);
-    s->scr_qflags = s->scr_qctr + (s->queue ? align256(kQueueCounters * 4) : 0);
+    s->scr_qflags = s->scr_qctr + (s->queue ? align256(kQueueCounterInts * 4) : 0);
     s->scr_need = s->scr_qflags + (s->queue ? align256(s->qflag_ints * 4) : 0);
     s->start_iters.assign(n, 0);
   }

@@ -160,7 +160,7 @@ struct Batch {
   int use_strips = 0;  // the sweep is the strip pipeline (its block offsets locate the XCD records)
   // queue sweep: per-XCD sub-queues of packed tile items, sub-queue
   // x * kQueueSub + i at qitems[q_off[.] .. q_off[. + 1]); the batch's
-  // counters [kQueueCounters] and done flags (scratch); q_total items in all
+  // counters [kQueueCounterInts] and done flags (scratch); q_total items in all
   int use_queue = 0, q_total = 0;
   const uint64_t *d_qitems = nullptr;
   const int32_t *d_q_off = nullptr;
@@ -173,8 +173,13 @@ struct Batch {
 // XCD (each with its own counter: one counter per XCD serialised the claims);
 // counters: taken per sub-queue, then handled per XCD.
 constexpr int kQueueBlocks = 4096;
-constexpr int kQueueSub = 8;
+constexpr int kQueueSub = 16;
 constexpr int kQueueCounters = 8 * kQueueSub + 8;
+// counter c at qctr[c * kCtrPad]: one 128-byte line each (claims on a shared
+// line serialise: with 8 counters per line the claims alone took 2.9 ms per
+// sweep of the 64-problem batch)
+constexpr int kCtrPad = 32;
+constexpr int kQueueCounterInts = kQueueCounters * kCtrPad;
 
 // Shapes of the strip pipeline: rows per strip TH x velocity groups per
 // wavefront G, with the strips per block NW that each is compiled with.
@@ -193,7 +198,7 @@ struct Scratch {
   double *part = nullptr;
   int32_t *progress = nullptr;
   uint8_t *xcc = nullptr;
-  int32_t *qctr = nullptr;    // queue sweep: counters [kQueueCounters]
+  int32_t *qctr = nullptr;    // queue sweep: counters [kQueueCounterInts]
   int32_t *qflags = nullptr;  // queue sweep: done flags
 };
 

@@ -269,7 +269,7 @@ __global__ void __launch_bounds__(256)
     // no block would leave its chains unswept)
     if (qctr) {
       int h = 0;
-      for (int x = 0; x < 8; ++x) h += qctr[8 * kQueueSub + x];
+      for (int x = 0; x < 8; ++x) h += qctr[(8 * kQueueSub + x) * kCtrPad];
       if (h != q_total) misplaced = 1;
     }
   }

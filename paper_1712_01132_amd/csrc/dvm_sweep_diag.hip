@@ -438,20 +438,26 @@ __global__ void __launch_bounds__(kWave)
 template <typename T, int DIM, int TT, bool Y2WALL, int EXT>
 __global__ void __launch_bounds__(kWave) __attribute__((amdgpu_waves_per_eu(sizeof(T) == 4 ? 3 : 1)))
     sweep_queue_kernel(const Geo<T> *__restrict__ G, const uint64_t *__restrict__ items,
-                       const int32_t *__restrict__ q_off, int32_t *__restrict__ qctr, int32_t *__restrict__ qflags) {
+                       const int32_t *__restrict__ q_off, int32_t *__restrict__ qctr, int32_t *__restrict__ qflags,
+                       int nprob) {
   __shared__ TileLds<T, DIM, TT, EXT> L;
+  if (nprob == 1 && !G[0].run) return;  // a stopped problem (its reduction checks nothing)
   uint32_t xcc;
   asm volatile("s_getreg_b32 %0, hwreg(HW_REG_XCC_ID)" : "=s"(xcc));
   xcc &= 7u;
   const int lane = threadIdx.x;
   int handled = 0;
-  // the XCD's sub-queues, starting with one picked by the block index; a
-  // block that finds one empty moves on to the next
-  const int sub0 = (int)((blockIdx.x >> 3) % kQueueSub);
-  for (int si = 0; si < kQueueSub; ++si) {
-    const int qi = (int)xcc * kQueueSub + (sub0 + si) % kQueueSub;
+  // the XCD's sub-queues holding items (the host fills them from the first
+  // on), starting with one picked by the block index; a block that finds one
+  // drained moves on to the next
+  const int *const xo = q_off + xcc * kQueueSub;
+  int used = 0;
+  for (int i = 0; i < kQueueSub; ++i) used += xo[i + 1] > xo[i];
+  const int sub0 = used ? (int)((blockIdx.x >> 3) % used) : 0;
+  for (int si = 0; si < used; ++si) {
+    const int qi = (int)xcc * kQueueSub + (sub0 + si) % used;
     const int qb = q_off[qi], qn = q_off[qi + 1] - qb;
-    int32_t *const ctr = &qctr[qi];
+    int32_t *const ctr = &qctr[qi * kCtrPad];
     // claims run two ahead: the item word of the next claim is loaded, and the
     // claim after it is in flight, while a tile runs
     auto claim = [&]() __attribute__((always_inline)) {
@@ -519,13 +525,14 @@ __global__ void __launch_bounds__(kWave) __attribute__((amdgpu_waves_per_eu(size
     }
   }
   if (lane == 0)
-    __hip_atomic_fetch_add(&qctr[8 * kQueueSub + xcc], handled, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    __hip_atomic_fetch_add(&qctr[(8 * kQueueSub + xcc) * kCtrPad], handled, __ATOMIC_RELAXED,
+                           __HIP_MEMORY_SCOPE_AGENT);
 }
 
 // The queue counters (taken per sub-queue, handled per XCD) before a queue
 // sweep: a fill kernel, so that a captured graph holds no memset node.
 __global__ void queue_reset_kernel(int32_t *qctr) {
-  if (threadIdx.x < kQueueCounters) qctr[threadIdx.x] = 0;
+  for (int i = threadIdx.x; i < kQueueCounters; i += blockDim.x) qctr[i * kCtrPad] = 0;
 }
 
 __global__ void fill_i32_kernel(int32_t *p, int64_t n, int32_t v) {
@@ -540,7 +547,7 @@ void launch_queue_rule(const Batch<T> &B, hipStream_t st, int32_t *qctr, int32_t
   const dim3 grid(kQueueBlocks);
 #define PDVM_QUEUE_E(D, X, E)                                                                             \
   hipLaunchKernelGGL((sweep_queue_kernel<T, D, X, Y2WALL, E>), grid, dim3(kWave), 0, st, B.d_geo, B.d_qitems, \
-                     B.d_q_off, qctr, qflags)
+                     B.d_q_off, qctr, qflags, B.nprob)
 #define PDVM_QUEUE_T(D, E)                          \
   if (B.tile_edge <= 4) PDVM_QUEUE_E(D, 4, E);      \
   else PDVM_QUEUE_E(D, 8, E)

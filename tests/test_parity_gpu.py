@@ -367,7 +367,7 @@ def test_shakhov_matches_oracle(shape, nv, kn, tile, precision, pr):
     (with psi); 2D takes the row pipeline."""
     m = random_mask(shape, 0.25, sum(shape) + 5)
     o, s = pair(m, nv, kn, precision=precision, tile=tile, tau=True, prandtl=pr)
-    assert s.schedule == "diagonals" if len(shape) == 3 else s.schedule.startswith("rows")
+    assert s.schedule == "queue" if len(shape) == 3 else s.schedule.startswith("rows")
     o.iterate(10)
     s.iterate(10)
     compare(o, s, RTOL64 if precision == "fp64" else RTOL32)
@@ -406,7 +406,7 @@ def test_maxwell_walls_match_oracle(shape, nv, kn, tile, precision, lateral, alp
     Shakhov model, 2D and 3D, on random geometries."""
     m = random_mask(shape, 0.25, sum(shape) + 3)
     o, s = pair(m, nv, kn, precision=precision, lateral=lateral, tile=tile, tau=tau, prandtl=pr, alpha=alpha)
-    assert s.schedule == "diagonals" if len(shape) == 3 else s.schedule.startswith("rows")
+    assert s.schedule == "queue" if len(shape) == 3 else s.schedule.startswith("rows")
     o.iterate(10)
     s.iterate(10)
     compare(o, s, RTOL64 if precision == "fp64" else RTOL32)
