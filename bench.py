@@ -68,11 +68,24 @@ def timed_updates(solver, fluid, K, steps, warmup):
 
 
 # HBM bytes per sweep launch from the rocprofv3 FETCH_SIZE / WRITE_SIZE passes
-# (scaled by a 1 GiB copy), valid only for the kernel source they were taken on
-# Key: (source hash, schedule, tile).
-TRAFFIC = {("c3239c6f9d2af279", "rows-xcd", (4, 4)): 523.4e6 + 841.9e6}
+# (scaled by a 1 GiB copy; summaries in profiles/), valid only for the kernel
+# source they were taken on. Key: (source hash, schedule, tile, bytes per value).
+_H = "a2b8a8c579eb6111"
+TRAFFIC = {
+    (_H, "rows-xcd", (4, 4), 8): 523.6e6 + 841.9e6,            # rock2d FP64
+    (_H, "rows-xcd", (4, 4), 4): 264.4e6 + 421.4e6,            # rock2d FP32
+    (_H, "queue", (4, 4, 4), 4): 15830.8e6 + 5105.9e6,         # pack3d FP32, 1 launch
+    (_H, "diagonals", (4, 4, 4), 4): (16742.0e6 + 5066.1e6) / 70,  # pack3d FP32, mean of 70 launches
+    (_H, "queue", (8, 8), 4): 6383.1e6 + 4601.8e6,             # batch64 FP32, 1 launch
+}
 # the same for the moment kernel of that iteration (h read once, moments written)
-MOM_TRAFFIC = {("c3239c6f9d2af279", "rows-xcd", (4, 4)): 879.8e6 + 12.8e6}
+MOM_TRAFFIC = {
+    (_H, "rows-xcd", (4, 4), 8): 880.1e6 + 12.8e6,
+    (_H, "rows-xcd", (4, 4), 4): 445.2e6 + 9.5e6,
+    (_H, "queue", (4, 4, 4), 4): 5236.3e6 + 35.7e6,
+    (_H, "diagonals", (4, 4, 4), 4): 5236.3e6 + 35.7e6,
+    (_H, "queue", (8, 8), 4): 5538.8e6 + 184.3e6,
+}
 
 
 def kernel_source_hash():
@@ -275,6 +288,22 @@ def _ttr_fp32_then_fp64(mask, nv, kn, tile, tile32, net=None, trial=50, tol=1e-6
 BF16_PEAK_TFLOPS = 2500.0
 
 
+def unet_source_hash():
+    """sha256 prefix over the network's kernel sources."""
+    import hashlib
+    h = hashlib.sha256()
+    for f in ("unet_kernels.hip", "unet_internal.h"):
+        h.update(f.encode())
+        with open(os.path.join(ROOT, "paper_1712_01132_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+# HBM bytes of one training step's MFMA kernels (FETCH_SIZE / WRITE_SIZE,
+# scaled; profiles/unet_train_bf16.md), by network source hash
+UNET_TRAFFIC = {"ddf9230b001a6b44": 5477.1e6 + 1223.3e6}
+
+
 def unet_timing():
     """The network's bf16 matrix-core kernels at the training shape (8 samples
     of 256 x 256): forward pass and training step (forward, backward, Adam)."""
@@ -295,8 +324,9 @@ def unet_timing():
            "forward_tflops": fwd, "step_tflops": t["step_flop"] / (t["step_ms"] * 1e-3) / 1e12,
            "mfma_kernels_ms_per_step": t["mfma_ms_per_step"],
            "roofline": {"bound": "mfma", "achieved": step_mfma, "peak": BF16_PEAK_TFLOPS, "unit": "TFLOP/s",
-                        "frac": step_mfma / BF16_PEAK_TFLOPS,
-                        "note": "convolution FLOP of one training step / summed durations of its MFMA kernels"}}
+                        "frac": step_mfma / BF16_PEAK_TFLOPS, "traffic": UNET_TRAFFIC.get(unet_source_hash()),
+                        "note": "convolution FLOP of one training step / summed durations of its MFMA kernels; "
+                                "traffic: HBM bytes of those kernels per step"}}
     log("warm-start network: %s" % json.dumps(res))
     return res
 
@@ -523,7 +553,7 @@ def main():
                                "32x32 half-range Gauss-Hermite velocities, FP64" % args.kn,
                    "fluid_voxels": fluid, "velocities": K, "parallelism": "1 GPU",
                    "tile": list(tile64), "autotune_ms_per_iteration": tune64},
-        "roofline": roofline(tm, 8, (kernel_source_hash(), sched64, tuple(tile64)), sched64),
+        "roofline": roofline(tm, 8, (kernel_source_hash(), sched64, tuple(tile64), 8), sched64),
     }
     if not args.no_extra:
         extra = {}
@@ -535,7 +565,7 @@ def main():
         s.close()
         extra["rock2d_fp32"] = {"updates_per_s": u32, "ms_per_step": 1e3 * d32 / args.steps,
                                 "tile": list(tile32), "autotune_ms_per_iteration": tune32,
-                                "roofline": roofline(t32, 4, (kernel_source_hash(), sched32, tuple(tile32)), sched32)}
+                                "roofline": roofline(t32, 4, (kernel_source_hash(), sched32, tuple(tile32), 4), sched32)}
         log("FP32: %.3e updates/s" % u32)
         # time to residual 1e-6: FP64 from rest, and the FP32 forms finished in FP64
         extra["rock2d_time_to_residual_1e-6"] = time_to_residual(mask, nv, args.kn, list(tile64), list(tile32))
@@ -553,7 +583,7 @@ def main():
         extra["pack3d_fp32"] = {"updates_per_s": u3, "ms_per_step": 1e3 * d3 / 20, "fluid_voxels": f3,
                                 "tile": list(tile3), "schedule": sched3, "autotune_ms_per_iteration": tune3,
                                 "velocities": 4096,
-                                "roofline": roofline(t3, 4, (kernel_source_hash(), sched3, tuple(tile3)), sched3)}
+                                "roofline": roofline(t3, 4, (kernel_source_hash(), sched3, tuple(tile3), 4), sched3)}
         log("3D pack FP32: %.3e updates/s, %s" % (u3, json.dumps(t3)))
         extra["pack3d_fp32_vs_fp64"] = pack3d_precision_errors(m3, list(tile3), sched3)
         # 64-problem batch
@@ -574,7 +604,7 @@ def main():
         extra["batch64_fp32"] = {"updates_per_s": fb * 576 * 30 / db, "ms_per_step": 1e3 * db / 30,
                                  "tile": list(tileb), "schedule": schedb, "autotune_ms_per_iteration": tuneb,
                                  "fluid_voxels": fb, "velocities": 576, "problems": 64,
-                                 "roofline": roofline(tb, 4, (kernel_source_hash(), schedb, tuple(tileb)), schedb)}
+                                 "roofline": roofline(tb, 4, (kernel_source_hash(), schedb, tuple(tileb), 4), schedb)}
         log("batch64 FP32: %.3e updates/s" % (fb * 576 * 30 / db))
         extra["warmstart_unet"] = unet_timing()
         extra["warmstart_heldout"] = warmstart_heldout()
