@@ -44,6 +44,8 @@ def same(a, b):
     ((16, 12, 14), [6, 6, 6], (8, 8, 2), "fp32", "specular", 1),
     ((9, 17, 11), [4, 6, 4], (8, 3, 4), "fp64", "periodic", 0),
     ((24, 20, 22), [8, 8, 8], (4, 4, 8), "fp32", "specular", 1),
+    ((10, 12, 9), [4, 4, 4], (1, 4, 3), "fp64", "specular", 1),     # tiles one voxel wide along x1
+    ((12, 9, 10), [6, 6, 6], (4, 1, 1), "fp32", "periodic", 0),     # ... along x2 and x3
 ])
 def test_queue_equals_diagonals_bitwise_3d(shape, nv, tile, precision, lateral, rule):
     """Ragged tiles, tiles one voxel thick along x3, both stencil rules, both
@@ -72,6 +74,8 @@ def test_queue_source_variants_3d(kw):
     ((29, 40), [6, 10], (4, 4), "fp64", dict(tau_feedback=True)),
     ((37, 29), [8, 8], (4, 4), "fp64", dict(tau_feedback=True, prandtl=2.0 / 3.0)),
     ((43, 37), [8, 8], (8, 8), "fp32", dict(accommodation=0.65)),
+    ((21, 30), [8, 8], (1, 4), "fp64", {}),                          # tiles one voxel wide along x1
+    ((26, 19), [6, 6], (4, 1), "fp32", dict(stencil_rule=0)),         # ... along x2
 ])
 def test_queue_equals_diagonals_bitwise_2d(shape, nv, tile, precision, kw):
     m = random_mask(shape, 0.3, sum(shape) + 5)
