@@ -78,12 +78,17 @@ enum { PDVM_STOP_FIELD = 0, PDVM_STOP_PAPER_ERR = 1 };
  *            XCD's L2). Needs blocks on all 8 XCDs (probed at creation, else
  *            PDVM_E_UNSUPPORTED); an iterate whose queues were not all drained
  *            is discarded as for ROWS;
+ * COLUMNS:   3D: QUEUE whose items are whole columns of tiles along x3, each
+ *            swept by one wavefront tile after tile (the two planes below a
+ *            tile stay in registers, and a column runs a tile or so behind its
+ *            upstream columns, so the values it reads from them are still in
+ *            the L2); the same requirements as QUEUE;
  * AUTO:      for a single 2D problem, ROWS when a probe of the block placement
  *            at creation shows that every velocity chain runs on one XCD (cheap
  *            synchronisation through its L2); for 3D problems and 2D batches,
  *            QUEUE when the probe finds all 8 XCDs; DIAGONALS otherwise. */
 enum { PDVM_SCHEDULE_AUTO = 0, PDVM_SCHEDULE_DIAGONALS = 1, PDVM_SCHEDULE_ROWS = 2, PDVM_SCHEDULE_ROWS_AGENT = 3,
-       PDVM_SCHEDULE_STRIPS = 4, PDVM_SCHEDULE_QUEUE = 5 };
+       PDVM_SCHEDULE_STRIPS = 4, PDVM_SCHEDULE_QUEUE = 5, PDVM_SCHEDULE_COLUMNS = 6 };
 
 typedef struct pdvm_solver pdvm_solver;
 
@@ -113,7 +118,8 @@ typedef struct {
                                 0 = only when the first one is (a solid second image then
                                     enters the second-order stencil with its wall value;
                                     this iteration can diverge on some geometries) */
-  int32_t sweep_schedule;    /* PDVM_SCHEDULE_*; ROWS(_AGENT) or STRIPS with dim 3 is PDVM_E_UNSUPPORTED;
+  int32_t sweep_schedule;    /* PDVM_SCHEDULE_*; ROWS(_AGENT) or STRIPS with dim 3, or COLUMNS
+                                with dim 2, is PDVM_E_UNSUPPORTED;
                                 a batch takes the first config's schedule */
   double prandtl;            /* 0 = BGK. > 0 (needs tau_feedback = 1): Shakhov model, whose
                                 source adds (4/5)(1 - Pr) q.v (|v|^2 - 5/2) with the heat
@@ -254,7 +260,8 @@ int pdvm_batch_get_flux(pdvm_solver *s, int32_t i, double *gp, double *k, double
 /* The sweep schedule in use: 0 tile diagonals; 1 row pipeline with
  * agent-scope synchronisation; 2 row pipeline with every velocity chain on one
  * XCD (chosen only after a probe of the block placement confirms it); 3 strip
- * pipeline; 4 per-XCD tile queues; -1 for NULL. */
+ * pipeline; 4 per-XCD tile queues; 5 per-XCD queues of tile columns; -1 for
+ * NULL. */
 int32_t pdvm_sweep_schedule(const pdvm_solver *s);
 
 /* Wall-clock bound on each wait of the row-pipeline sweep for its upstream row

@@ -4,8 +4,9 @@ The sweep kernel is compiled for square tile edges 4 and 8 in (x1, x2). A tile
 may be narrower than its compiled edge along either axis and of any depth
 along x3. The best shape depends on the problem size (tiles per tile diagonal
 against diagonals per iteration), on the precision and on the number of
-velocity groups; for batches and 3D problems the schedule (per-XCD tile
-queues in one launch, or one launch per tile diagonal) is tuned with it.
+velocity groups; for batches and 3D problems the schedule (per-XCD queues of
+tiles, or in 3D of tile columns, in one launch, or one launch per tile
+diagonal) is tuned with it.
 `best_config` times each candidate with the library's own per-kernel HIP-event
 timing (pdvm_time_kernels) on the real problem, or on the real batch, and
 keeps the fastest per size class. The choice is cached in a JSON file
@@ -70,9 +71,11 @@ def _time(make, iters):
 
 # Sweep schedules the tuner compares besides the automatic choice: the
 # per-XCD tile queues (one launch per iteration) and the per-diagonal launches
-# for 3D problems and batches. (A single 2D problem keeps the row pipeline,
-# measured 2-2.5x faster than both on the 512^2 rock.)
+# for 3D problems and batches, and in 3D also the queues of tile columns. (A
+# single 2D problem keeps the row pipeline, measured 2-2.5x faster than both
+# on the 512^2 rock.)
 SCHEDULES_MULTI = ("queue", "diagonals")
+SCHEDULES_3D = ("columns", "queue", "diagonals")
 
 
 def best_config(problems, nv, precision="fp32", iters=5, candidates=None, schedules=None, use_cache=True,
@@ -85,7 +88,7 @@ def best_config(problems, nv, precision="fp32", iters=5, candidates=None, schedu
     dim = len(shapes[0])
     cands = candidates or (CANDIDATES_2D if dim == 2 else CANDIDATES_3D)
     if schedules is None:
-        schedules = SCHEDULES_MULTI if (batch or dim == 3) else ("auto",)
+        schedules = SCHEDULES_3D if dim == 3 else (SCHEDULES_MULTI if batch else ("auto",))
     key = "+".join(schedules) + "-" + size_class(shapes, nv, precision)
     cache = _load_cache() if use_cache else {}
     if key in cache:

@@ -275,11 +275,15 @@ int validate_and_build(const pdvm_config *cfg, Problem &P, std::string &err) {
   }
   P.spec = cfg->specular_fraction;
   P.check_every = cfg->check_every > 0 ? cfg->check_every : 16;
-  if (cfg->sweep_schedule < 0 || cfg->sweep_schedule > 5) { err = "sweep_schedule must be 0..5"; return PDVM_E_INVAL; }
+  if (cfg->sweep_schedule < 0 || cfg->sweep_schedule > 6) { err = "sweep_schedule must be 0..6"; return PDVM_E_INVAL; }
   P.schedule = cfg->sweep_schedule;
   if ((P.schedule == PDVM_SCHEDULE_ROWS || P.schedule == PDVM_SCHEDULE_ROWS_AGENT ||
        P.schedule == PDVM_SCHEDULE_STRIPS) && cfg->dim != 2) {
     err = "the row-pipeline sweep is 2D only";
+    return PDVM_E_UNSUPPORTED;
+  }
+  if (P.schedule == PDVM_SCHEDULE_COLUMNS && cfg->dim != 3) {
+    err = "the column-queue sweep is 3D only";
     return PDVM_E_UNSUPPORTED;
   }
   if (cfg->stencil_rule != 0 && cfg->stencil_rule != 1) { err = "stencil_rule must be 0 or 1"; return PDVM_E_INVAL; }
@@ -650,6 +654,7 @@ struct pdvm_solver {
   bool rows_local = false;         // ... whose chains each run on one XCD (probed)
   bool strips = false;             // the sweep is one strip-pipeline launch (2D; XCD-local placement probed)
   bool queue = false;              // the sweep is one launch fed by per-XCD tile queues
+  bool columns = false;            // ... whose items are columns of tiles along x3 (3D)
   char *qmem = nullptr;            // device: queue items, offsets, counters, done flags
   size_t qflag_ints = 0;           // done flags of the whole batch
   std::string err;
@@ -1005,7 +1010,10 @@ int probe_all_xcds(pdvm_solver *s, bool *ok) {
 // (problem, octant, group) are dealt to the 8 XCDs and their sub-queues,
 // largest first to the least loaded; each queue lists its chains' tiles that hold fluid, by
 // diagonal, then problem, octant, tile and group, with the waits each tile
-// needs. Also the done flags (zero: below every stamp) and the counters.
+// needs. With s->columns (3D) an item is a segment of kColumnTiles tiles of
+// a column along x3 holding fluid, by the diagonal of its first tile, and
+// each tile's waits go to the per-octant table Geo::qtinfo. Also the done
+// flags (zero: below every stamp) and the counters.
 template <typename T>
 int build_queue(pdvm_solver *s) {
   const int n = s->n();
@@ -1045,13 +1053,22 @@ int build_queue(pdvm_solver *s) {
     load[x] += work[pof[c]];
     subload[x * kQueueSub + i] += work[pof[c]];
   }
-  // per problem and diagonal: (octant, tile, waits) of the tiles holding fluid
+  // per problem and diagonal: (octant, tile, waits) of the tiles holding
+  // fluid, or (octant, column) of the columns holding fluid; tinfo: per
+  // problem, octant and tile, 128 (fluid) + the waits along x1 and x2
+  const bool col = s->columns;
   std::vector<std::vector<std::vector<uint64_t>>> diag(n);
+  std::vector<int64_t> info_off(n + 1, 0);
+  for (int p = 0; p < n; ++p) info_off[p + 1] = info_off[p] + (col ? 8 * (int64_t)G[p].ntiles_all : 0);
+  std::vector<int32_t> tinfo((size_t)info_off[n], 0);
   for (int p = 0; p < n; ++p) {
     const Problem &P = s->P[p];
     const int nt[3] = {P.ntile[0], P.ntile[1], P.ntile[2]};
     const int64_t stride[3] = {1, nt[0], (int64_t)nt[0] * nt[1]};
     diag[p].assign(P.ndiag, {});
+    const int S = std::min(kColumnTiles, nt[2]), nseg = (nt[2] + S - 1) / S;
+    G[p].col_tiles = S;
+    std::vector<uint8_t> col_live(col ? (size_t)8 * stride[2] * nseg : 0, 0);  // [octant][segment][column]
     for (int o = 0; o < (1 << P.dim); ++o)
       for (int c = 0; c < nt[2]; ++c)
         for (int b = 0; b < nt[1]; ++b)
@@ -1069,13 +1086,28 @@ int build_queue(pdvm_solver *s) {
               const bool thin = u1 >= 0 && u1 < nt[j] && std::min(P.tile[j], P.n[j] - u1 * P.tile[j]) == 1;
               if (thin && u2 >= 0 && u2 < nt[j] && P.live[t - 2 * sj * stride[j]]) waits |= 1ull << (2 * j + 1);
             }
-            diag[p][a + b + c].push_back((uint64_t)t | ((uint64_t)o << 24) | (waits << 48));
+            if (!col) {
+              diag[p][a + b + c].push_back((uint64_t)t | ((uint64_t)o << 24) | (waits << 48));
+            } else {
+              tinfo[info_off[p] + o * G[p].ntiles_all + t] = 128 | (int32_t)waits;
+              col_live[(o * nseg + c / S) * stride[2] + t % stride[2]] = 1;
+            }
           }
+    if (col)
+      for (int o = 0; o < 8; ++o)
+        for (int k = 0; k < nseg; ++k)
+          for (int b = 0; b < nt[1]; ++b)
+            for (int a = 0; a < nt[0]; ++a) {
+              const int pa = (o & 1) ? nt[0] - 1 - a : a, pb = (o & 2) ? nt[1] - 1 - b : b;
+              const int64_t cix = pa + stride[1] * pb;
+              if (col_live[(o * nseg + k) * stride[2] + cix])
+                diag[p][a + b + k * S].push_back((uint64_t)cix | ((uint64_t)o << 24) | ((uint64_t)k << 48));
+            }
   }
   std::vector<std::vector<uint64_t>> q(8 * kQueueSub);
   for (int d = 0; d < maxd; ++d)
     for (int p = 0; p < n; ++p) {
-      if (d >= s->P[p].ndiag) continue;
+      if (d >= (int)diag[p].size()) continue;
       const int ng = s->P[p].ngroups;
       for (uint64_t e : diag[p][d]) {
         const int o = (int)((e >> 24) & 7u);
@@ -1095,13 +1127,20 @@ int build_queue(pdvm_solver *s) {
   if (items.size() >= ((size_t)1 << 31)) return s->fail(PDVM_E_UNSUPPORTED, "queue sweep: too many tiles");
   const size_t item_b = align256(std::max<size_t>(1, items.size()) * 8), off_b = align256((nq + 1) * 4),
                ctr_b = align256(kQueueCounterInts * 4);
-  const size_t flag_b = align256((size_t)flags * 4);
-  if (hipMalloc(&s->qmem, item_b + off_b + ctr_b + flag_b) != hipSuccess)
-    return s->fail(PDVM_E_NOMEM, "queue sweep: device allocation of %zu bytes failed", item_b + off_b + ctr_b + flag_b);
+  const size_t flag_b = align256((size_t)flags * 4), info_b = align256(tinfo.size() * 4);
+  const size_t all_b = item_b + off_b + ctr_b + flag_b + info_b;
+  if (hipMalloc(&s->qmem, all_b) != hipSuccess)
+    return s->fail(PDVM_E_NOMEM, "queue sweep: device allocation of %zu bytes failed", all_b);
   char *m = s->qmem;
   HIPCHK(s, hipMemcpyAsync(m, items.data(), items.size() * 8, hipMemcpyHostToDevice, s->stream));
   HIPCHK(s, hipMemcpyAsync(m + item_b, off.data(), (nq + 1) * 4, hipMemcpyHostToDevice, s->stream));
   HIPCHK(s, hipMemsetAsync(m + item_b + off_b, 0, ctr_b + flag_b, s->stream));
+  if (col) {
+    const int32_t *dinfo = (const int32_t *)(m + item_b + off_b + ctr_b + flag_b);
+    HIPCHK(s, hipMemcpyAsync((void *)dinfo, tinfo.data(), tinfo.size() * 4, hipMemcpyHostToDevice, s->stream));
+    for (int p = 0; p < n; ++p) G[p].qtinfo = dinfo + info_off[p];
+  }
+  B.use_columns = col ? 1 : 0;
   B.use_queue = 1;
   B.q_total = (int)items.size();
   B.d_qitems = (const uint64_t *)m;
@@ -1115,7 +1154,8 @@ int build_queue(pdvm_solver *s) {
 }
 
 const char *sweep_name(const pdvm_solver *s) {
-  return s->queue ? "queue" : (s->strips ? "strip-pipeline" : (s->rows ? "row-pipeline" : "tile-diagonal"));
+  return s->queue ? (s->columns ? "column-queue" : "queue")
+                  : (s->strips ? "strip-pipeline" : (s->rows ? "row-pipeline" : "tile-diagonal"));
 }
 
 // Chain sets of the strip pipeline per band.
@@ -1308,14 +1348,15 @@ int create_common(const pdvm_config *cfgs, int n, void *dev_workspace, size_t ws
   // 3.9 ms of per-diagonal launches with 8x8 tiles, 2.9 against 5.0 with 4x4;
   // the 96^3 pack 4.3 against 4.4 ms), when blocks reach all 8 XCDs
   if (!s->strips && !s->rows &&
-      (P0.schedule == PDVM_SCHEDULE_QUEUE ||
+      (P0.schedule == PDVM_SCHEDULE_QUEUE || P0.schedule == PDVM_SCHEDULE_COLUMNS ||
        (P0.schedule == PDVM_SCHEDULE_AUTO && (P0.dim == 3 || n > 1)))) {
     bool all = false;
     int rc4 = probe_all_xcds(s, &all);
-    if (rc4 == PDVM_OK && !all && P0.schedule == PDVM_SCHEDULE_QUEUE)
+    if (rc4 == PDVM_OK && !all && P0.schedule != PDVM_SCHEDULE_AUTO)
       rc4 = s->fail(PDVM_E_UNSUPPORTED, "the queue sweep needs blocks on all 8 XCDs; the placement probe found fewer");
     if (rc4 == PDVM_OK && all) {
       s->queue = true;
+      s->columns = P0.schedule == PDVM_SCHEDULE_COLUMNS;
       rc4 = s->precision == PDVM_FP64 ? build_queue<double>(s) : build_queue<float>(s);
     }
     if (rc4 != PDVM_OK) {
@@ -1911,7 +1952,7 @@ int pdvm_time_kernels(pdvm_solver *s, int32_t iters, pdvm_timing *out) {
 
 int32_t pdvm_sweep_schedule(const pdvm_solver *s) {
   if (!s) return -1;
-  return s->queue ? 4 : (s->strips ? 3 : (s->rows ? (s->rows_local ? 2 : 1) : 0));
+  return s->queue ? (s->columns ? 5 : 4) : (s->strips ? 3 : (s->rows ? (s->rows_local ? 2 : 1) : 0));
 }
 
 int pdvm_set_wait_limit(pdvm_solver *s, double seconds) {

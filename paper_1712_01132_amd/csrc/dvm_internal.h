@@ -127,6 +127,11 @@ struct Geo {
   // qflags[qflag_off + c * ntiles_all + t] (qflags: the batch's flag array)
   int64_t qflag_off = 0;
   int32_t ntiles_all = 0;
+  // queue of tile columns (3D): per sign octant and tile (physical index),
+  // qtinfo[o * ntiles_all + t] = 128 if the tile holds fluid, plus its waits
+  // in bits 0-5 as in a queue item (null for tile items)
+  const int32_t *qtinfo = nullptr;
+  int32_t col_tiles = 0;  // tiles per column item (its bits 48-63: which segment of the column)
 };
 
 // Square sweep tile edges in (x1, x2) compiled into the kernel; the host
@@ -161,7 +166,9 @@ struct Batch {
   // queue sweep: per-XCD sub-queues of packed tile items, sub-queue
   // x * kQueueSub + i at qitems[q_off[.] .. q_off[. + 1]); the batch's
   // counters [kQueueCounterInts] and done flags (scratch); q_total items in all
-  int use_queue = 0, q_total = 0;
+  // use_columns: an item is a column of tiles along x3 (3D), walked by one
+  // wavefront in the octant's x3 order
+  int use_queue = 0, q_total = 0, use_columns = 0;
   const uint64_t *d_qitems = nullptr;
   const int32_t *d_q_off = nullptr;
   int32_t *d_qctr = nullptr;
@@ -180,6 +187,11 @@ constexpr int kQueueCounters = 8 * kQueueSub + 8;
 // sweep of the 64-problem batch)
 constexpr int kCtrPad = 32;
 constexpr int kQueueCounterInts = kQueueCounters * kCtrPad;
+// Tiles per item of the column queue (3D). Measured on the 96^3 pack (FP32,
+// 4x4x4 tiles): 1: 4.34 ms per sweep, 2: 4.24, 3: 4.34, 4: 4.43, whole
+// columns of 24: 5.21 (a long item started last holds up the end of the
+// sweep); tile items 4.30.
+constexpr int kColumnTiles = 2;
 
 // Shapes of the strip pipeline: rows per strip TH x velocity groups per
 // wavefront G, with the strips per block NW that each is compiled with.

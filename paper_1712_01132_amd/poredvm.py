@@ -19,7 +19,7 @@ PDVM_E_NONFINITE, PDVM_E_STATE, PDVM_E_UNSUPPORTED = -4, -5, -6
 PDVM_FP64, PDVM_FP32 = 0, 1
 PDVM_LATERAL_SPECULAR, PDVM_LATERAL_PERIODIC = 0, 1
 PDVM_STOP_FIELD, PDVM_STOP_PAPER_ERR = 0, 1
-SCHEDULES = {"auto": 0, "diagonals": 1, "rows": 2, "rows-agent": 3, "strips": 4, "queue": 5}
+SCHEDULES = {"auto": 0, "diagonals": 1, "rows": 2, "rows-agent": 3, "strips": 4, "queue": 5, "columns": 6}
 
 _dp = ctypes.POINTER(ctypes.c_double)
 
@@ -311,7 +311,7 @@ class Solver:
     def schedule(self):
         """"diagonals", "rows" (agent-scope), "rows-xcd" (XCD-local row pipeline), "strips" or
         "queue" (per-XCD tile queues)."""
-        return {0: "diagonals", 1: "rows", 2: "rows-xcd", 3: "strips", 4: "queue"}[load().pdvm_sweep_schedule(self._h)]
+        return {0: "diagonals", 1: "rows", 2: "rows-xcd", 3: "strips", 4: "queue", 5: "columns"}[load().pdvm_sweep_schedule(self._h)]
 
     def set_wait_limit(self, seconds):
         """Bound on each row-pipeline wait for the upstream row (default 2 s)."""
@@ -397,7 +397,7 @@ class Batch:
 
     @property
     def schedule(self):
-        return {0: "diagonals", 1: "rows", 2: "rows-xcd", 3: "strips", 4: "queue"}[load().pdvm_sweep_schedule(self._h)]
+        return {0: "diagonals", 1: "rows", 2: "rows-xcd", 3: "strips", 4: "queue", 5: "columns"}[load().pdvm_sweep_schedule(self._h)]
 
     def flux(self, i):
         gp = ctypes.c_double()

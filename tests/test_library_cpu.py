@@ -89,6 +89,7 @@ def test_workspace_bytes_for_valid_config():
     ("maxwell_rule0", "stencil_rule 1"),
     ("maxwell_alpha0", "specular_fraction"),
     ("zero_node", "ascending"),
+    ("columns_2d", "3D only"),
 ])
 def test_invalid_configs_rejected(case, needle):
     m = geometry.centred_disc(16)
@@ -124,6 +125,8 @@ def test_invalid_configs_rejected(case, needle):
     elif case == "tau2d_wide":
         kw["tau_feedback"] = True  # psi doubles the 576 velocities of an octant: over 1024
         nv = [48, 48]
+    elif case == "columns_2d":
+        kw["schedule"] = "columns"
     elif case == "zero_node":
         grid = [(np.array([-1.0, -0.0, 0.0, 1.0]), np.array([0.25, 0.25, 0.25, 0.25]))] * 2
     kn = kw.pop("kn", 1.0)

@@ -49,10 +49,27 @@ def same(a, b):
 ])
 def test_queue_equals_diagonals_bitwise_3d(shape, nv, tile, precision, lateral, rule):
     """Ragged tiles, tiles one voxel thick along x3, both stencil rules, both
-    lateral conditions, one or several (partly empty) 64-velocity groups."""
+    lateral conditions, one or several (partly empty) 64-velocity groups; tile
+    items and column items."""
     m = random_mask(shape, 0.3, sum(shape) + 11)
     kw = dict(precision=precision, lateral=lateral, tile=tile, stencil_rule=rule)
-    same(run(m, nv, 0.6, "queue", 9, **kw), run(m, nv, 0.6, "diagonals", 9, **kw))
+    ref = run(m, nv, 0.6, "diagonals", 9, **kw)
+    same(run(m, nv, 0.6, "queue", 9, **kw), ref)
+    same(run(m, nv, 0.6, "columns", 9, **kw), ref)
+
+
+@pytest.mark.parametrize("tile,precision", [((4, 4, 2), "fp32"), ((4, 4, 3), "fp64"), ((8, 8, 2), "fp32")])
+def test_columns_skip_solid_tiles_bitwise(tile, precision):
+    """Columns interrupted by tiles without fluid (solid slabs across x3 and a
+    solid block): after such a tile the column reloads the planes below from
+    h instead of carrying them."""
+    m = random_mask((21, 13, 14), 0.2, 41)   # (x3, x2, x1)
+    m[6:9] = 1                               # a slab across x3: whole tiles without fluid in every column
+    m[12:18, 0:8, 0:8] = 1                   # a solid block: such tiles in some columns only
+    m = geometry.fill_nonpercolating(m)
+    assert geometry.percolates(m)
+    kw = dict(precision=precision, lateral="specular", tile=tile)
+    same(run(m, [6, 6, 6], 0.5, "columns", 8, **kw), run(m, [6, 6, 6], 0.5, "diagonals", 8, **kw))
 
 
 @pytest.mark.parametrize("kw", [
@@ -63,8 +80,9 @@ def test_queue_equals_diagonals_bitwise_3d(shape, nv, tile, precision, lateral, 
 ])
 def test_queue_source_variants_3d(kw):
     m = random_mask((9, 10, 12), 0.25, 5)
-    same(run(m, [4, 4, 4], 0.8, "queue", 8, tile=(4, 4, 3), **kw),
-         run(m, [4, 4, 4], 0.8, "diagonals", 8, tile=(4, 4, 3), **kw))
+    ref = run(m, [4, 4, 4], 0.8, "diagonals", 8, tile=(4, 4, 3), **kw)
+    same(run(m, [4, 4, 4], 0.8, "queue", 8, tile=(4, 4, 3), **kw), ref)
+    same(run(m, [4, 4, 4], 0.8, "columns", 8, tile=(4, 4, 3), **kw), ref)
 
 
 @pytest.mark.parametrize("shape,nv,tile,precision,kw", [

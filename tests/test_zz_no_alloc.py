@@ -69,16 +69,16 @@ def test_noalloc_stops_on_tolerance_like_iterate():
     _same(a, b)
 
 
-@pytest.mark.parametrize("schedule", ["auto", "queue"])
+@pytest.mark.parametrize("schedule", ["auto", "queue", "columns"])
 def test_noalloc_3d(schedule):
-    """3D (the queue sweep, also the automatic choice): two solves in a row,
-    the second smaller, finding the first one's counters and done flags in
-    the scratch."""
+    """3D (the queue sweeps of tiles, also the automatic choice, and of tile
+    columns): two solves in a row, the second smaller, finding the first
+    one's counters and done flags in the scratch."""
     for shape, iters in (((20, 22, 24), 7), ((10, 12, 14), 5)):
         m = random_mask(shape, 0.25, 44)
         a = poredvm.Solver(m, [4, 4, 4], 0.7, precision="fp32", schedule=schedule)
         b = poredvm.Solver(m, [4, 4, 4], 0.7, precision="fp32", schedule=schedule)
-        assert b.schedule == "queue"
+        assert b.schedule == ("columns" if schedule == "columns" else "queue")
         a.iterate(iters)
         b.iterate_noalloc(iters)
         _same(a, b)
