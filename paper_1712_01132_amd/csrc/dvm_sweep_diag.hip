@@ -28,16 +28,21 @@ namespace {
 // nothing waits for the load early) and with no branch: the buffer, the node
 // and the velocity slot are selected (uniform values), so the load is issued
 // whatever the case and many can be in flight before the first wait.
+// The node's offset is formed in 32 bits (a problem has under 2^31 / 6
+// voxels) and scaled by the voxel's bytes colb in one 32 x 32 -> 64 bit
+// product: these are scalar instructions, a dozen per halo value fewer than
+// with 64-bit index arithmetic.
 template <typename T>
 __device__ __forceinline__ T upstream_sel(const Dom<T> &g, gptr<const T> hc, gptr<const T> hp, int j, int x, int y,
-                                          int z, int kofs, int kmir) {
+                                          int z, int kofs, int kmir, uint32_t colb) {
   int c[3] = {x, y, z};
   const bool in = c[j] >= 0 && c[j] < g.n[j];
   const Img im = image_of(j, c[j], g.n[j], g.latp);
   c[j] = in ? c[j] : im.r;
   const int k = (!in && im.mir) ? kmir : kofs;
-  const gptr<const T> b = in ? hc : hp;
-  return b[cell_of(g, c[0], c[1], c[2]) * g.Kpad + k];
+  const uint32_t cell = (uint32_t)(c[0] + g.n[0] * (c[1] + g.n[1] * c[2]));
+  const gptr<const char> b = (gptr<const char>)(in ? hc : hp) + (uint64_t)cell * colb;
+  return ((gptr<const T>)b)[k];
 }
 // The jump that upstream_sel leaves out at x1 = x (images across the wrap).
 template <typename T>
@@ -168,10 +173,10 @@ __device__ __forceinline__ void sweep_tile(const Geo<T> &G_, int o, int grp, con
 #pragma unroll
     for (int k = 0; k < TT; ++k) {
       const int y = ys + min(k, cnt[1] - 1) * s[1], x = xs + min(k, cnt[0] - 1) * s[0];
-      L1[k] = upstream_sel(dv, hcc, hp, 0, xs - s[0], y, z, kofs, kmir[0]);
-      L2[k] = upstream_sel(dv, hcc, hp, 0, xs - 2 * s[0], y, z, kofs, kmir[0]);
-      B1[k] = upstream_sel(dv, hcc, hp, 1, x, ys - s[1], z, kofs, kmir[1]);
-      B2[k] = upstream_sel(dv, hcc, hp, 1, x, ys - 2 * s[1], z, kofs, kmir[1]);
+      L1[k] = upstream_sel(dv, hcc, hp, 0, xs - s[0], y, z, kofs, kmir[0], colb);
+      L2[k] = upstream_sel(dv, hcc, hp, 0, xs - 2 * s[0], y, z, kofs, kmir[0], colb);
+      B1[k] = upstream_sel(dv, hcc, hp, 1, x, ys - s[1], z, kofs, kmir[1], colb);
+      B2[k] = upstream_sel(dv, hcc, hp, 1, x, ys - 2 * s[1], z, kofs, kmir[1], colb);
     }
   };
   // records of the voxels of planes c0 .. c0 + np - 1 (lane l takes voxels
@@ -257,8 +262,8 @@ __device__ __forceinline__ void sweep_tile(const Geo<T> &G_, int o, int grp, con
 #pragma unroll
     for (int v = 0; v < (ZREG ? NC : 0); ++v) {
       const int x = xs + min(v % TT, cnt[0] - 1) * s[0], y = ys + min(v / TT, cnt[1] - 1) * s[1];
-      ZA[v] = upstream_sel(dv, hcc, hp, 2, x, y, z - s[2], kofs, kmir[2]);
-      ZB[v] = upstream_sel(dv, hcc, hp, 2, x, y, z - 2 * s[2], kofs, kmir[2]);
+      ZA[v] = upstream_sel(dv, hcc, hp, 2, x, y, z - s[2], kofs, kmir[2], colb);
+      ZB[v] = upstream_sel(dv, hcc, hp, 2, x, y, z - 2 * s[2], kofs, kmir[2], colb);
     }
   }
   __syncthreads();
@@ -289,8 +294,8 @@ __device__ __forceinline__ void sweep_tile(const Geo<T> &G_, int o, int grp, con
 #pragma unroll
     for (int k = 0; k < TT; ++k)
       rowrs[k] = __builtin_amdgcn_make_buffer_rsrc(
-          (void *)(T *)(hc + (int64_t)(n1 * z + ys + min(k, cnt[1] - 1) * s[1]) * n0 * Kp), (short)0,
-          (int)(colb * (uint32_t)n0), kBufferFlags);
+          (void *)((gptr<char>)hc + (uint64_t)(uint32_t)((n1 * z + ys + min(k, cnt[1] - 1) * s[1]) * n0) * colb),
+          (short)0, (int)(colb * (uint32_t)n0), kBufferFlags);
     // --- the plane's anti-diagonals ---------------------------------------
     T D1[TT], D2[TT];
 #pragma unroll
@@ -308,8 +313,8 @@ __device__ __forceinline__ void sweep_tile(const Geo<T> &G_, int o, int grp, con
         const int i = d - r;
         if (DIM == 3 && !ZREG && i >= 0 && i < TT) {
           const int x = xs + min(i, cnt[0] - 1) * s[0], y = ys + min(r, cnt[1] - 1) * s[1];
-          Z1[r] = upstream_sel(dv, hcc, hp, 2, x, y, z - s[2], kofs, kmir[2]);
-          Z2[r] = upstream_sel(dv, hcc, hp, 2, x, y, z - 2 * s[2], kofs, kmir[2]);
+          Z1[r] = upstream_sel(dv, hcc, hp, 2, x, y, z - s[2], kofs, kmir[2], colb);
+          Z2[r] = upstream_sel(dv, hcc, hp, 2, x, y, z - 2 * s[2], kofs, kmir[2], colb);
         }
       }
 #pragma unroll
