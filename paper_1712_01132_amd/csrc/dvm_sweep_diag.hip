@@ -55,14 +55,17 @@ __device__ __forceinline__ T wrap_jump(const Dom<T> &g, int x) {
 template <typename T, int DIM, int TT, int EXT>
 struct TileLds {
   static constexpr int NC = TT * TT;
-  static constexpr int RW = 5 + 3 * DIM + ((EXT & 2) ? DIM : 0);  // src (4), nu tau, per axis (c1, c2, w), [q]
+  // a record: src (4), nu tau, per axis (c1, c2, w), [q]; its stride RW is
+  // padded to 16 bytes, so that a voxel's record is read with 16-byte loads
+  static constexpr int RW0 = 5 + 3 * DIM + ((EXT & 2) ? DIM : 0);
+  static constexpr int RW = (RW0 * (int)sizeof(T) + 15) / 16 * 16 / (int)sizeof(T);
   static constexpr int PZ = DIM == 3 ? 128 / NC : 1;
   // 3D with 4 x 4 tiles: the two x3-upstream planes of the tile's voxels are
   // carried in registers, ZN values each (one unused value otherwise)
   static constexpr bool ZREG = DIM == 3 && TT == 4;
   static constexpr int ZN = ZREG ? NC : 1;
   T rd[8 * kWave];
-  T rec[PZ * NC * RW];
+  alignas(16) T rec[PZ * NC * RW];
   uint32_t rcode[PZ * NC];
 };
 
