@@ -272,8 +272,10 @@ __device__ __forceinline__ void sweep_tile(const Geo<T> &G_, int o, int grp, con
   __syncthreads();
   // one plane; the first is peeled off the loop, so that the loop is entered,
   // as it is re-entered, right after a plane's stores: its waits for the
-  // halos loaded ahead then never cover those stores
-  auto plane = [&](int c3) __attribute__((always_inline)) {
+  // halos loaded ahead then never cover those stores. The last is peeled too:
+  // it loads no halos ahead (one-plane tiles, rare, reload their own)
+  auto plane = [&](int c3, auto next) __attribute__((always_inline)) {
+    constexpr bool NEXT = decltype(next)::value;  // a plane follows in this tile
     const int z = zof(c3);
     const int pz = c3 % PZ;
     if (c3 > 0 && pz == 0) {  // the next chunk of records (only LDS is written here)
@@ -281,10 +283,10 @@ __device__ __forceinline__ void sweep_tile(const Geo<T> &G_, int o, int grp, con
       stage(c3, min(PZ, cnt[2] - c3), [] {});
       __syncthreads();
     }
-    // the next plane's halos (the last plane re-reads its own), issued before
-    // this plane's stores: waiting for them then does not wait for the stores
+    // the next plane's halos, issued before this plane's stores: waiting for
+    // them then does not wait for the stores
     T L1n[TT], L2n[TT], B1n[TT], B2n[TT];
-    if (DIM == 3) load_halo(zof(min(c3 + 1, cnt[2] - 1)), L1n, L2n, B1n, B2n);
+    if (DIM == 3 && NEXT) load_halo(zof(min(c3 + 1, cnt[2] - 1)), L1n, L2n, B1n, B2n);
     const T *recp = rec + pz * NC * RW;
     const uint32_t *rcodep = rcode + pz * NC;
     // stores: one buffer resource per row of the tile (a row of h spans below
@@ -376,7 +378,7 @@ __device__ __forceinline__ void sweep_tile(const Geo<T> &G_, int o, int grp, con
         D1[r] = Nw[r];
       }
     }
-    if (DIM == 3) {
+    if (DIM == 3 && NEXT) {
 #pragma unroll
       for (int k = 0; k < TT; ++k) {
         L1[k] = L1n[k];
@@ -386,8 +388,9 @@ __device__ __forceinline__ void sweep_tile(const Geo<T> &G_, int o, int grp, con
       }
     }
   };
-  plane(0);
-  for (int c3 = 1; c3 < cnt[2]; ++c3) plane(c3);
+  plane(0, std::true_type{});
+  for (int c3 = 1; c3 < cnt[2] - 1; ++c3) plane(c3, std::true_type{});
+  if (cnt[2] > 1) plane(cnt[2] - 1, std::false_type{});
 }
 
 // Step (i) for one diagonal of tiles: block = (octant, group, tile of the
