@@ -1034,24 +1034,41 @@ int build_queue(pdvm_solver *s) {
     chain_base[p + 1] = chain_base[p] + chains;
     maxd = std::max(maxd, P.ndiag);
   }
-  // deal the chains: largest work first, each to the least loaded queue
-  std::vector<int64_t> order(chain_base[n]);
-  std::vector<int> owner(chain_base[n]), pof(chain_base[n]);
+  // deal the chains: an octant of a problem (all its velocity groups, or a
+  // share of them when there are fewer octants than XCDs) to one XCD, largest
+  // work first to the least loaded, and its groups to that XCD's least loaded
+  // sub-queues. The groups of an octant sweep the same tiles in the same
+  // order, so the XCD's L2 serves each tile's records (flags, sources, wall
+  // values) to all of them from one fetch.
+  std::vector<int> owner(chain_base[n]);
+  struct Unit {
+    int p, o, g0, g1;
+  };
+  std::vector<Unit> units;
+  int octants = 0;
+  for (int p = 0; p < n; ++p) octants += 1 << s->P[p].dim;
+  const int split = (8 + octants - 1) / octants;
   for (int p = 0; p < n; ++p)
-    for (int64_t c = chain_base[p]; c < chain_base[p + 1]; ++c) pof[c] = p;
-  for (size_t c = 0; c < order.size(); ++c) order[c] = (int64_t)c;
-  std::stable_sort(order.begin(), order.end(), [&](int64_t a, int64_t b) { return work[pof[a]] > work[pof[b]]; });
+    for (int o = 0; o < (1 << s->P[p].dim); ++o) {
+      const int ng = s->P[p].ngroups, parts = std::min(split, ng);
+      for (int k = 0; k < parts; ++k) units.push_back({p, o, ng * k / parts, ng * (k + 1) / parts});
+    }
+  std::stable_sort(units.begin(), units.end(), [&](const Unit &a, const Unit &b) {
+    return work[a.p] * (a.g1 - a.g0) > work[b.p] * (b.g1 - b.g0);
+  });
   // queue index x * kQueueSub + i: the XCD, then its sub-queue, both least
   // loaded (ties to the lowest index, so an XCD's used sub-queues come first)
   int64_t load[8] = {0, 0, 0, 0, 0, 0, 0, 0};
   std::vector<int64_t> subload(8 * kQueueSub, 0);
-  for (int64_t c : order) {
+  for (const Unit &u : units) {
     const int x = (int)(std::min_element(load, load + 8) - load);
-    const auto b = subload.begin() + x * kQueueSub;
-    const int i = (int)(std::min_element(b, b + kQueueSub) - b);
-    owner[c] = x * kQueueSub + i;
-    load[x] += work[pof[c]];
-    subload[x * kQueueSub + i] += work[pof[c]];
+    load[x] += work[u.p] * (u.g1 - u.g0);
+    for (int g = u.g0; g < u.g1; ++g) {
+      const auto b = subload.begin() + x * kQueueSub;
+      const int i = (int)(std::min_element(b, b + kQueueSub) - b);
+      owner[chain_base[u.p] + u.o * s->P[u.p].ngroups + g] = x * kQueueSub + i;
+      subload[x * kQueueSub + i] += work[u.p];
+    }
   }
   // per problem and diagonal: (octant, tile, waits) of the tiles holding
   // fluid, or (octant, column) of the columns holding fluid; tinfo: per
