@@ -378,12 +378,14 @@ __global__ void __launch_bounds__(kWave * NW)
     // fetches itself again, which keeps the code free of branches)
     fetch(min(a + 1, ntile0 - 1), nxt);
 #pragma unroll
-    for (int k = 0; k < TT; ++k) hrow[k] = (gptr<char>)(hz + (int64_t)((ys + k * s[1]) * n0 + xs) * Kp);
+    for (int k = 0; k < TT; ++k)
+      hrow[k] = (gptr<char>)(hz + (int64_t)((uint64_t)(uint32_t)((ys + k * s[1]) * n0 + xs) * (uint32_t)Kp));
     const int64_t colb = (int64_t)s[0] * Kp * (int64_t)sizeof(T);  // bytes from one column to the next
     // a whole tile is stored through one buffer resource based at its
     // lowest-addressed voxel, with wavefront-constant row and column offsets
     const __amdgpu_buffer_rsrc_t tile_rsrc = __builtin_amdgcn_make_buffer_rsrc(
-        (void *)(T *)(hz + (int64_t)(ylo * n0 + (s[0] > 0 ? xs : xs - (TT - 1))) * Kp), (short)0, -1, kBufferFlags);
+        (void *)(T *)(hz + (int64_t)((uint64_t)(uint32_t)(ylo * n0 + (s[0] > 0 ? xs : xs - (TT - 1))) * (uint32_t)Kp)),
+        (short)0, -1, kBufferFlags);
 
     // --- the tile's anti-diagonals (as in sweep_kernel) ---------------------
     // FULL: a whole TT x TT tile, so the columns and rows handed on are
