@@ -35,6 +35,22 @@ __device__ __forceinline__ double wave_sum8(const double (&v)[8], int lane) {
   return c;
 }
 
+// wave_sum8 within each half of the wavefront (lanes 0-31 and 32-63 sum
+// separately): lane l holds the total of its half's value
+// ((l >> 4) & 1) * 4 + ((l >> 3) & 1) * 2 + ((l >> 2) & 1).
+__device__ __forceinline__ double half_sum8(const double (&v)[8], int lane) {
+  double a[4], b[2];
+  const bool u16 = lane & 16, u8 = lane & 8, u4 = lane & 4;
+#pragma unroll
+  for (int k = 0; k < 4; ++k) a[k] = (u16 ? v[4 + k] : v[k]) + __shfl_xor(u16 ? v[k] : v[4 + k], 16, kWave);
+#pragma unroll
+  for (int k = 0; k < 2; ++k) b[k] = (u8 ? a[2 + k] : a[k]) + __shfl_xor(u8 ? a[k] : a[2 + k], 8, kWave);
+  double c = (u4 ? b[1] : b[0]) + __shfl_xor(u4 ? b[0] : b[1], 4, kWave);
+  c += __shfl_xor(c, 2, kWave);
+  c += __shfl_xor(c, 1, kWave);
+  return c;
+}
+
 __device__ __forceinline__ double readlane_d(double v, int l) {
   const uint64_t b = __builtin_bit_cast(uint64_t, v);
   const uint32_t lo = __builtin_amdgcn_readlane((uint32_t)b, l), hi = __builtin_amdgcn_readlane((uint32_t)(b >> 32), l);
@@ -59,9 +75,15 @@ using vec2_t = T __attribute__((ext_vector_type(2)));
 // and the pair start are even) reads the last valid pair and weighs 0.
 // SH: also the heat flux q_j (signed per octant from the weights
 // W |v_j| (|v|^2 - 5/2)), stored as the Shakhov source nu (4/5)(1 - Pr) q_j.
-template <typename T, int DIM, int NS, bool PAIR, bool SH>
+// HALF: two voxels at a time, one per half of the wavefront (lane l owns
+// the slots q = (l & 31) + 32 m of its half's voxel), for octant sizes just
+// above a multiple of 64 (144 velocities per octant: 160 slots per voxel
+// instead of 192, and half the reductions and result stores per voxel).
+template <typename T, int DIM, int NS, bool PAIR, bool SH, bool HALF = false>
 __global__ void __launch_bounds__(kMomBlock)
     moments_kernel(const Geo<T> *__restrict__ G, const int *__restrict__ blk_off, int nprob, double *part_scr) {
+  static_assert(!(HALF && PAIR), "one slot layout at a time");
+  constexpr int LW = HALF ? kWave / 2 : kWave;  // lanes per voxel
   const int pb = nprob > 1 ? owner_of(blk_off, nprob, blockIdx.x) : 0;
   const Geo<T> &g = G[pb];
   const int blk = nprob > 1 ? blockIdx.x - blk_off[pb] : blockIdx.x;
@@ -90,7 +112,7 @@ __global__ void __launch_bounds__(kMomBlock)
   int qc[NS];
 #pragma unroll
   for (int m = 0; m < NS; ++m) {
-    const int q = PAIR ? 2 * kWave * (m / 2) + 2 * lane + (m & 1) : lane + m * kWave;
+    const int q = PAIR ? 2 * kWave * (m / 2) + 2 * lane + (m & 1) : (lane & (LW - 1)) + m * LW;
     const bool ok = q < Ko;
     qc[m] = ok ? q : (PAIR ? Ko - 2 + (m & 1) : Ko - 1);
 #pragma unroll
@@ -127,11 +149,20 @@ __global__ void __launch_bounds__(kMomBlock)
     const int64_t il = base + (int64_t)lane * nw;
     const int32_t cl = fidx[il < nf ? il : base];
     const int cnt = (int)min<int64_t>(kWave, (nf - base + nw - 1) / nw);
+    // HALF: step t takes voxels 2 t (lanes 0-31) and 2 t + 1 (lanes 32-63;
+    // none past an odd count: that half re-reads the last one and stores nothing)
+    const int hsel = HALF ? lane >> 5 : 0;
+    auto voxel = [&](int t) __attribute__((always_inline)) {
+      if (!HALF) return (int64_t)__builtin_amdgcn_readlane(cl, t);
+      const int32_t a = __builtin_amdgcn_readlane(cl, 2 * t), b = __builtin_amdgcn_readlane(cl, min(2 * t + 1, cnt - 1));
+      return (int64_t)(hsel ? b : a);
+    };
+    const int steps = HALF ? (cnt + 1) / 2 : cnt;
     T hv[1 << DIM][NS];
-    int64_t c = __builtin_amdgcn_readlane(cl, 0);
+    int64_t c = voxel(0);
     load(c, hv);
-    for (int t = 0; t < cnt; ++t) {
-      const int64_t cn = __builtin_amdgcn_readlane(cl, min(t + 1, cnt - 1));
+    for (int t = 0; t < steps; ++t) {
+      const int64_t cn = voxel(min(t + 1, steps - 1));
       T hn[1 << DIM][NS];
       if (kAhead) load(cn, hn);  // in flight while this voxel is reduced
       double v[8] = {0, 0, 0, 0, 0, 0, 0, 0};  // rho, half-fluxes (j, +/-), energy
@@ -156,25 +187,34 @@ __global__ void __launch_bounds__(kMomBlock)
         v[5] = qa[0];
         v[6] = qa[1];
       }
-      const double tot = wave_sum8(v, lane);
+      const double tot = HALF ? half_sum8(v, lane) : wave_sum8(v, lane);
       double qt = 0;
       if (SH && DIM == 3) {
         const double w2[8] = {qa[0], qa[1], qa[2], 0, 0, 0, 0, 0};
-        qt = wave_sum8(w2, lane);
+        qt = HALF ? half_sum8(w2, lane) : wave_sum8(w2, lane);
       }
-      const double r = readlane_d(tot, 0);
+      // the lane of the total of value k: 8 k (wave_sum8), or in each half
+      // 16 ((k >> 2) & 1) + 8 ((k >> 1) & 1) + 4 (k & 1) (half_sum8); with
+      // HALF each lane selects its own half's totals
+      auto total = [&](double x, int k) __attribute__((always_inline)) {
+        if (!HALF) return readlane_d(x, 8 * k);
+        const int l = 16 * ((k >> 2) & 1) + 8 * ((k >> 1) & 1) + 4 * (k & 1);
+        const double a = readlane_d(x, l), b = readlane_d(x, 32 + l);
+        return hsel ? b : a;
+      };
+      const double r = total(tot, 0);
       // every lane reads the totals here, outside the lane-0 branch below: a
       // read of another lane inside it could see a value whose last step the
       // compiler moved into the branch, where only lane 0 computes it
       double ph[3][2], qf[3] = {0, 0, 0};
 #pragma unroll
       for (int j = 0; j < DIM; ++j) {
-        ph[j][0] = readlane_d(tot, 8 * (1 + 2 * j));
-        ph[j][1] = readlane_d(tot, 8 * (2 + 2 * j));
-        if (SH) qf[j] = DIM == 2 ? readlane_d(tot, 8 * (5 + j)) : readlane_d(qt, 8 * j);
+        ph[j][0] = total(tot, 1 + 2 * j);
+        ph[j][1] = total(tot, 2 + 2 * j);
+        if (SH) qf[j] = DIM == 2 ? total(tot, 5 + j) : total(qt, j);
       }
-      const double en = readlane_d(tot, 56);
-      if (lane == 0) {
+      const double en = total(tot, 7);
+      if ((lane & (LW - 1)) == 0 && (!HALF || 2 * t + hsel < cnt)) {
         // Offset form: the sums above are moments of h - rho_r. rho_r adds
         // rho_r w0 to rho, rho_r D_j to each half-flux (so nothing to u) and
         // rho_r we to the energy. The records then describe the sweep of
@@ -214,6 +254,11 @@ __global__ void __launch_bounds__(kMomBlock)
       }
       c = cn;
     }
+  }
+  if (HALF) {  // lane 32's voxels into lane 0's accumulators
+    mdu = fmax(mdu, __shfl_xor(mdu, 32, kWave));
+    mu = fmax(mu, __shfl_xor(mu, 32, kWave));
+    su += __shfl_xor(su, 32, kWave);
   }
   __shared__ double sh[WPB][3];
   if (lane == 0) {
@@ -496,14 +541,14 @@ int grid_for(int64_t work, int block) {
 
 }  // namespace
 
-template <typename T, int D, int S, bool P>
+template <typename T, int D, int S, bool P, bool H = false>
 void launch_moments_as(const Batch<T> &B, int blocks, hipStream_t st, double *part) {
   if (B.shakhov)
-    hipLaunchKernelGGL((moments_kernel<T, D, S, P, true>), dim3(blocks), dim3(kMomBlock), 0, st, B.d_geo, B.d_blk_off,
-                       B.nprob, part);
+    hipLaunchKernelGGL((moments_kernel<T, D, S, P, true, H>), dim3(blocks), dim3(kMomBlock), 0, st, B.d_geo,
+                       B.d_blk_off, B.nprob, part);
   else
-    hipLaunchKernelGGL((moments_kernel<T, D, S, P, false>), dim3(blocks), dim3(kMomBlock), 0, st, B.d_geo, B.d_blk_off,
-                       B.nprob, part);
+    hipLaunchKernelGGL((moments_kernel<T, D, S, P, false, H>), dim3(blocks), dim3(kMomBlock), 0, st, B.d_geo,
+                       B.d_blk_off, B.nprob, part);
 }
 
 template <typename T>
@@ -521,6 +566,26 @@ hipError_t launch_moments(const Batch<T> &B, hipStream_t st, const Scratch &scr)
     else if (ns <= 4) PDVM_MOM(2, 4, true);
     else if (ns <= 8) PDVM_MOM(2, 8, true);
     else PDVM_MOM(2, 16, true);
+    return hipGetLastError();
+  }
+  // two voxels per wavefront where an octant fills a half-wavefront's slots
+  // better (the octant size is 1 to 32 past a multiple of 64: 144 velocities
+  // take 160 slots instead of 192)
+  const int nh = (B.Ko + kWave / 2 - 1) / (kWave / 2);
+  if ((B.Ko - 1) % kWave < kWave / 2 && nh <= 9) {
+#define PDVM_MOMH(D, S) launch_moments_as<T, D, S, false, true>(B, blocks, st, scr.part)
+    if (B.dim == 2) {
+      if (nh <= 1) PDVM_MOMH(2, 1);
+      else if (nh <= 3) PDVM_MOMH(2, 3);
+      else if (nh <= 5) PDVM_MOMH(2, 5);
+      else PDVM_MOMH(2, 9);
+    } else {
+      if (nh <= 1) PDVM_MOMH(3, 1);
+      else if (nh <= 3) PDVM_MOMH(3, 3);
+      else if (nh <= 5) PDVM_MOMH(3, 5);
+      else PDVM_MOMH(3, 9);
+    }
+#undef PDVM_MOMH
     return hipGetLastError();
   }
   const int ns = (B.Ko + kWave - 1) / kWave;
