@@ -70,21 +70,21 @@ def timed_updates(solver, fluid, K, steps, warmup):
 # HBM bytes per sweep launch from the rocprofv3 FETCH_SIZE / WRITE_SIZE passes
 # (scaled by a 1 GiB copy; summaries in profiles/), valid only for the kernel
 # source they were taken on. Key: (source hash, schedule, tile, bytes per value).
-_H = "a2b8a8c579eb6111"
+_H = "3e9c9fb2dde38e62"
 TRAFFIC = {
-    (_H, "rows-xcd", (4, 4), 8): 523.6e6 + 841.9e6,            # rock2d FP64
-    (_H, "rows-xcd", (4, 4), 4): 264.4e6 + 421.4e6,            # rock2d FP32
-    (_H, "queue", (4, 4, 4), 4): 15830.8e6 + 5105.9e6,         # pack3d FP32, 1 launch
-    (_H, "diagonals", (4, 4, 4), 4): (16742.0e6 + 5066.1e6) / 70,  # pack3d FP32, mean of 70 launches
-    (_H, "queue", (8, 8), 4): 6383.1e6 + 4601.8e6,             # batch64 FP32, 1 launch
+    (_H, "rows-xcd", (4, 4), 8): 523.4e6 + 841.9e6,            # rock2d FP64
+    (_H, "rows-xcd", (4, 4), 4): 264.1e6 + 421.4e6,            # rock2d FP32
+    (_H, "queue", (4, 4, 4), 4): 12069.6e6 + 5104.0e6,         # pack3d FP32, 1 launch
+    (_H, "columns", (4, 4, 4), 4): 13454.6e6 + 5096.5e6,       # pack3d FP32, 1 launch
+    (_H, "queue", (8, 8), 4): 5960.5e6 + 4601.8e6,             # batch64 FP32, 1 launch
 }
 # the same for the moment kernel of that iteration (h read once, moments written)
 MOM_TRAFFIC = {
-    (_H, "rows-xcd", (4, 4), 8): 880.1e6 + 12.8e6,
-    (_H, "rows-xcd", (4, 4), 4): 445.2e6 + 9.5e6,
-    (_H, "queue", (4, 4, 4), 4): 5236.3e6 + 35.7e6,
-    (_H, "diagonals", (4, 4, 4), 4): 5236.3e6 + 35.7e6,
-    (_H, "queue", (8, 8), 4): 5538.8e6 + 184.3e6,
+    (_H, "rows-xcd", (4, 4), 8): 880.2e6 + 12.8e6,
+    (_H, "rows-xcd", (4, 4), 4): 445.3e6 + 9.5e6,
+    (_H, "queue", (4, 4, 4), 4): 5236.9e6 + 35.7e6,
+    (_H, "columns", (4, 4, 4), 4): 5236.9e6 + 35.7e6,
+    (_H, "queue", (8, 8), 4): 5821.9e6 + 184.4e6,
 }
 
 
@@ -101,7 +101,8 @@ def kernel_source_hash():
     return h.hexdigest()[:16]
 
 
-SWEEP_KERNEL = {"diagonals": "sweep_kernel", "queue": "sweep_queue_kernel", "strips": "sweep_strips_kernel",
+SWEEP_KERNEL = {"diagonals": "sweep_kernel", "queue": "sweep_queue_kernel", "columns": "sweep_queue_kernel",
+                "strips": "sweep_strips_kernel",
                 "rows": "sweep_rows_kernel", "rows-xcd": "sweep_rows_kernel"}
 
 
