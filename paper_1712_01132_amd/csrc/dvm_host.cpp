@@ -77,81 +77,95 @@ void set_thread_error(const char *fmt, ...) {
 // ---------------------------------------------------------------------------
 // Half-range Gauss-Hermite rule in extended precision: the recurrence of the
 // orthogonal polynomials for exp(-x^2) on [0, inf) by the discretised
-// Stieltjes procedure (composite Gauss-Legendre on [0, 14]), then nodes and
-// weights from the Jacobi matrix by implicit QL iterations.
+// Stieltjes procedure (composite Gauss-Legendre on [0, 14]); the nodes are
+// the eigenvalues of the recurrence's Jacobi matrix (Golub-Welsch), the
+// weights the Christoffel numbers 1 / sum_j p_j(x)^2 of the orthonormal
+// polynomials at each node (a sum of positive terms: full relative accuracy
+// also for the smallest weights).
 
-void gauss_legendre(int m, std::vector<long double> &x, std::vector<long double> &w) {
-  x.assign(m, 0);
-  w.assign(m, 0);
-  const long double pi = 3.141592653589793238462643383279502884L;
-  for (int i = 0; i < m; ++i) {
-    long double z = cosl(pi * (i + 0.75L) / (m + 0.5L));
-    long double dp = 0;
-    for (int it = 0; it < 100; ++it) {
-      long double p0 = 1, p1 = z;
-      for (int k = 2; k <= m; ++k) {
-        const long double p2 = ((2 * k - 1) * z * p1 - (k - 1) * p0) / k;
-        p0 = p1;
-        p1 = p2;
+// Eigenvalues of the symmetric tridiagonal matrix with diagonal `diag` and
+// off-diagonal `off` (off[i] couples i and i + 1), by cyclic Jacobi
+// rotations on the dense matrix: each rotation in the (p, q) plane makes the
+// (p, q) entry zero, with the tangent of the smaller rotation angle taken
+// from tau = (a_qq - a_pp) / (2 a_pq), t = sign(tau) / (|tau| + sqrt(1 +
+// tau^2)). Sweeps over all pairs repeat until the off-diagonal mass is at
+// rounding level (quadratic convergence; the matrices here have at most 32
+// rows).
+bool symtri_eigen(const std::vector<long double> &diag, const std::vector<long double> &off,
+                  std::vector<long double> &val) {
+  const int n = (int)diag.size();
+  std::vector<long double> A((size_t)n * n, 0);
+  auto at = [&A, n](int r, int c) -> long double & { return A[(size_t)r * n + c]; };
+  for (int i = 0; i < n; ++i) at(i, i) = diag[i];
+  for (int i = 0; i + 1 < n; ++i) at(i, i + 1) = at(i + 1, i) = off[i];
+  bool done = false;
+  for (int sweep = 0; sweep < 60 && !done; ++sweep) {
+    long double offd = 0, all = 0;
+    for (int r = 0; r < n; ++r)
+      for (int c = 0; c < n; ++c) {
+        const long double a2 = at(r, c) * at(r, c);
+        all += a2;
+        if (r != c) offd += a2;
       }
-      dp = m * (z * p1 - p0) / (z * z - 1);
-      const long double dz = p1 / dp;
-      z -= dz;
-      if (fabsl(dz) < 1e-19L) break;
+    if (offd <= 1e-36L * all) {
+      done = true;
+      break;
     }
-    x[i] = z;
-    w[i] = 2 / ((1 - z * z) * dp * dp);
+    for (int p = 0; p + 1 < n; ++p)
+      for (int q = p + 1; q < n; ++q) {
+        const long double apq = at(p, q);
+        if (fabsl(apq) <= 1e-24L * (fabsl(at(p, p)) + fabsl(at(q, q)))) {
+          at(p, q) = at(q, p) = 0;
+          continue;
+        }
+        const long double tau = (at(q, q) - at(p, p)) / (2 * apq);
+        const long double t = (tau >= 0 ? 1.0L : -1.0L) / (fabsl(tau) + sqrtl(1 + tau * tau));
+        const long double c = 1 / sqrtl(1 + t * t), s = t * c;
+        for (int k = 0; k < n; ++k) {  // A <- A J
+          const long double akp = at(k, p), akq = at(k, q);
+          at(k, p) = c * akp - s * akq;
+          at(k, q) = s * akp + c * akq;
+        }
+        for (int k = 0; k < n; ++k) {  // A <- J^T A
+          const long double apk = at(p, k), aqk = at(q, k);
+          at(p, k) = c * apk - s * aqk;
+          at(q, k) = s * apk + c * aqk;
+        }
+        at(p, q) = at(q, p) = 0;  // zero by construction; drop the rounding
+      }
   }
+  if (!done) return false;
+  val.assign(n, 0);
+  for (int k = 0; k < n; ++k) val[k] = at(k, k);
+  return true;
 }
 
-bool jacobi_eigen(std::vector<long double> &d, std::vector<long double> &e, std::vector<long double> &z) {
-  const int n = (int)d.size();
-  for (int l = 0; l < n; ++l) {
-    int iter = 0;
-    int m;
-    do {
-      for (m = l; m < n - 1; ++m) {
-        const long double dd = fabsl(d[m]) + fabsl(d[m + 1]);
-        if (fabsl(e[m]) <= 1e-21L * dd) break;
-      }
-      if (m != l) {
-        if (++iter > 200) return false;
-        long double g = (d[l + 1] - d[l]) / (2 * e[l]);
-        long double r = hypotl(g, 1.0L);
-        g = d[m] - d[l] + e[l] / (g + (g >= 0 ? r : -r));
-        long double s = 1, c = 1, p = 0;
-        int i;
-        bool early = false;
-        for (i = m - 1; i >= l; --i) {
-          long double f = s * e[i];
-          const long double b = c * e[i];
-          r = hypotl(f, g);
-          e[i + 1] = r;
-          if (r == 0) {
-            d[i + 1] -= p;
-            e[m] = 0;
-            early = true;
-            break;
-          }
-          s = f / r;
-          c = g / r;
-          g = d[i + 1] - p;
-          r = (d[i] - g) * s + 2 * c * b;
-          p = s * r;
-          d[i + 1] = g + p;
-          g = c * r - b;
-          f = z[i + 1];
-          z[i + 1] = s * z[i] + c * f;
-          z[i] = c * z[i] - s * f;
-        }
-        if (early) continue;
-        d[l] -= p;
-        e[l] = g;
-        e[m] = 0;
-      }
-    } while (m != l);
+// Gauss rule of the three-term recurrence with diagonal `diag`, off-diagonal
+// `off` (the square roots of beta_1 ..) and weight-function mass `mass`.
+bool gauss_rule(const std::vector<long double> &diag, const std::vector<long double> &off, long double mass,
+                std::vector<long double> &x, std::vector<long double> &w) {
+  const int n = (int)diag.size();
+  if (!symtri_eigen(diag, off, x)) return false;
+  w.assign(n, 0);
+  for (int i = 0; i < n; ++i) {
+    long double pm = 0, pc = 1 / sqrtl(mass), sum = pc * pc;  // p_{j-1}, p_j at x_i
+    for (int j = 0; j + 1 < n; ++j) {
+      const long double pn = ((x[i] - diag[j]) * pc - (j > 0 ? off[j - 1] * pm : 0)) / off[j];
+      pm = pc;
+      pc = pn;
+      sum += pc * pc;
+    }
+    w[i] = 1 / sum;
   }
   return true;
+}
+
+// m-point Gauss-Legendre rule on [-1, 1]: zero diagonal, off-diagonal
+// k / sqrt(4 k^2 - 1), mass 2.
+bool gauss_legendre(int m, std::vector<long double> &x, std::vector<long double> &w) {
+  std::vector<long double> diag(m, 0), off(m > 1 ? m - 1 : 0);
+  for (int k = 1; k < m; ++k) off[k - 1] = k / sqrtl(4.0L * k * k - 1);
+  return gauss_rule(diag, off, 2.0L, x, w);
 }
 
 // ---------------------------------------------------------------------------
@@ -565,7 +579,10 @@ int halfrange_gh(int32_t n_total, double *nodes, double *weights) {
   const int n = n_total / 2;
   // discretise int_0^14 f(x) exp(-x^2) dx by composite Gauss-Legendre
   std::vector<long double> gx, gw;
-  gauss_legendre(24, gx, gw);
+  if (!gauss_legendre(24, gx, gw)) {
+    set_thread_error("eigenvalue iteration did not converge");
+    return PDVM_E_INVAL;
+  }
   const int panels = 96;
   const long double X = 14.0L, hp = X / panels;
   std::vector<long double> x, w;
@@ -593,17 +610,16 @@ int halfrange_gh(int32_t n_total, double *nodes, double *weights) {
       p1[i] = p2[i];
     }
   }
-  std::vector<long double> d(alpha), e(n, 0), z(n, 0);
-  for (int i = 0; i + 1 < n; ++i) e[i] = sqrtl(beta[i + 1]);
-  z[0] = 1;
-  if (!jacobi_eigen(d, e, z)) {
+  std::vector<long double> off(n > 1 ? n - 1 : 0), d, z;
+  for (int i = 0; i + 1 < n; ++i) off[i] = sqrtl(beta[i + 1]);
+  if (!gauss_rule(alpha, off, beta[0], d, z)) {
     set_thread_error("eigenvalue iteration did not converge");
     return PDVM_E_INVAL;
   }
   std::vector<std::pair<long double, long double>> nw(n);
   long double tot = 0;
   for (int i = 0; i < n; ++i) {
-    nw[i] = {d[i], beta[0] * z[i] * z[i]};
+    nw[i] = {d[i], z[i]};
     tot += nw[i].second;
   }
   std::sort(nw.begin(), nw.end());
