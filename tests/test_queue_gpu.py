@@ -157,3 +157,17 @@ def test_queue_abandoned_sweep_keeps_state_and_poisons_the_solver():
     ref.iterate(5)
     for x, y in zip(ref.moments(diagnostics=False), s.moments(diagnostics=False)):
         assert np.array_equal(x, y)
+
+
+def test_autotuner_compares_the_3d_schedules(tmp_path, monkeypatch):
+    """In 3D the tuner times tile queues, column queues and per-diagonal
+    launches for every tile; its choice runs the same iterates as any other."""
+    from paper_1712_01132_amd import autotune
+    monkeypatch.setenv("PDVM_AUTOTUNE_CACHE", str(tmp_path / "tune.json"))
+    m = random_mask((14, 12, 16), 0.3, 91)
+    (sched, tile), ms = autotune.best_config(m, [4, 4, 4], "fp32", iters=2)
+    assert sched in autotune.SCHEDULES_3D and tile in autotune.CANDIDATES_3D
+    assert len(ms) == len(autotune.SCHEDULES_3D) * len(autotune.CANDIDATES_3D)
+    assert all(v > 0 for v in ms.values())
+    same(run(m, [4, 4, 4], 0.9, sched, 6, precision="fp32", tile=tile),
+         run(m, [4, 4, 4], 0.9, "diagonals", 6, precision="fp32", tile=(4, 4, 4)))
